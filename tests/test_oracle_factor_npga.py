@@ -1,0 +1,106 @@
+"""Pins for oracle.factor (Sec. 2.1), oracle.npga (Alg. 1, power-method
+remark) and the seeded generator."""
+import numpy as np
+import pytest
+
+import gen
+from oracle import factor, npga, qp
+from oracle.projection import proj_F
+from oracle.reference import exact_mv, exact_mv_factor, factor_objective
+
+
+def _small_panel(n=30, T=200, seed=0):
+    spec = gen.SPECS["c1"].scaled(n, T)
+    spec = spec.__class__(**{**spec.__dict__, "seed": seed})
+    return spec, gen.returns_TxN(spec)
+
+
+def test_factor_matches_numpy_cov():
+    spec, Rt = _small_panel()
+    mu, L = factor.build_factor(Rt.T)
+    np.testing.assert_allclose(L @ L.T, np.cov(Rt.T.astype(np.float64), ddof=1), rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(mu, Rt.astype(np.float64).mean(axis=0), rtol=1e-13)
+    # centering: every row of L sums to zero
+    assert np.abs(L.sum(axis=1)).max() <= 1e-15 * np.abs(L).sum(axis=1).max()
+
+
+def test_generator_deterministic_and_chunk_invariant():
+    spec = gen.SPECS["c1"]
+    a = gen.returns_TxN(spec)
+    b = gen.returns_TxN(spec, chunk=17)
+    assert a.dtype == np.float32 and a.shape == (spec.T, spec.n)
+    assert np.array_equal(a, b)
+    c = gen.returns_TxN(spec.__class__(**{**spec.__dict__, "seed": 99}))
+    assert not np.array_equal(a, c)
+
+
+def test_generator_moments_c1():
+    spec = gen.SPECS["c1"]
+    Rt = gen.returns_TxN(spec).astype(np.float64)
+    # idiosyncratic sd of 0.02 * t_4 is 0.02 * sqrt(2); factors add ~0.01 * |B_i|
+    sd = Rt.std(axis=0)
+    assert 0.02 < np.median(sd) < 0.045
+    assert abs(np.mean(Rt) - spec.drift_mean) < 5e-3
+
+
+def test_power_method_monotone_and_bounded():
+    rng = np.random.default_rng(1)
+    L = rng.standard_normal((40, 300))
+    ray, _ = npga.power_method(L, 30, rng.standard_normal(40))
+    s = np.linalg.norm(L, 2)
+    assert np.all(np.diff(ray) >= -1e-12 * s)   # rises monotonically (Remark)
+    assert ray[-1] <= s * (1 + 1e-12)
+    assert ray[-1] >= 0.999 * s
+
+
+def test_lipschitz_matches_eigs():
+    rng = np.random.default_rng(2)
+    L = rng.standard_normal((20, 50))
+    m = npga.FactorModel(L, gamma=0.3)
+    ev = np.linalg.eigvalsh(L @ L.T)
+    assert m.lipschitz_exact() == pytest.approx(2 * ev[-1] + 0.6, rel=1e-12)
+
+
+def test_npga_converges_to_exact_minimiser():
+    spec, Rt = _small_panel(40, 400, seed=3)
+    mu, L = factor.build_factor(Rt.T)
+    r = float(np.percentile(mu, 60))
+    model = npga.FactorModel(L)
+    alpha = 1.0 / model.lipschitz_exact()
+    out = npga.npga(model, mu, r, alpha, np.full(40, 1 / 40), tol=1e-10, max_iter=100000)
+    assert out["converged"]
+    ref = exact_mv_factor(L, 0.0, mu, r)
+    assert np.abs(out["x"] - ref["x"]).max() <= 1e-6
+    assert abs(model.value(out["x"]) - ref["f"]) <= 1e-9 * ref["f"]
+    # the stopping residual vanishes at the certified minimiser (G_alpha(x*) = 0)
+    p, _, _ = proj_F(ref["x"] - alpha * model.grad(ref["x"]), mu, r)
+    assert np.linalg.norm(p - ref["x"]) <= 1e-12
+
+
+def test_npga_residual_envelope_convex_and_ridge():
+    """Qualitative regimes of Thm. npga-convergence / Sec. 5.3: the residual
+    falls far faster with a ridge (strongly convex) than without."""
+    spec, Rt = _small_panel(60, 50, seed=4)   # T < n: singular Sigma
+    mu, L = factor.build_factor(Rt.T)
+    r = float(np.median(mu))
+    res = {}
+    for g in (0.0, 5e-2 * np.trace(L @ L.T) / 60):
+        model = npga.FactorModel(L, g)
+        alpha = 1.0 / model.lipschitz_exact()
+        out = npga.npga(model, mu, r, alpha, np.full(60, 1 / 60), tol=1e-8,
+                        check_every=1, max_iter=20000, record=True)
+        res[g > 0] = out
+    assert res[True]["converged"]
+    assert res[True]["iters"] < res[False]["iters"]
+
+
+def test_exact_mv_certificate_c1():
+    spec = gen.SPECS["c1"]
+    Rt = gen.returns_TxN(spec)
+    mu, L = factor.build_factor(Rt.T)
+    r = gen.target_return(spec, Rt)
+    out = exact_mv_factor(L, 0.0, mu, r)
+    H = 2 * (L @ L.T)
+    rep = qp.kkt_report(H, np.zeros(spec.n), mu, r, out["x"], out["lam"], out["nu"])
+    assert qp.certificate_ok(rep, tol_stat=1e-10, tol_feas=1e-13, r_scale=abs(mu).max())
+    assert out["f"] == pytest.approx(factor_objective(L, 0.0, out["x"]))
