@@ -1,0 +1,252 @@
+/*
+ * npga.h - C ABI of libnpga, a gfx950 (MI355X) implementation of the NPGA
+ * mean-variance solver and the Sketch-Truncate-Ridge (STR) factor builder of
+ * Niu and Wang, "Scalable Mean-Variance Portfolio Optimization via Subspace
+ * Embeddings and GPU-Friendly Nesterov-Accelerated Projected Gradient"
+ * (arXiv 2604.02917).
+ *
+ * Problem (eq. mv, Sec. 1; unified model eq. npga-unified-grad, Sec. 3.1):
+ *     minimise   f(x) = ||L_eff^T x||_2^2 + gamma ||x||_2^2
+ *     over       F = { x in R^n : 1^T x = 1, mu^T x >= r, x >= 0 }.
+ * The feasible set has no other bounds (Sec. 1 and Sec. 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the argument is marked (host).
+ *   - Matrices are column-major: element (i, j) of an m x c matrix with
+ *     leading dimension ld is at p[i + j * ld].  For the factor L (n x T)
+ *     period t's n-vector is contiguous.
+ *   - Float32 matrices must be 16-byte aligned and ld must be a multiple of
+ *     4 (the kernels load float4).  The caller's buffer must hold ld * cols
+ *     elements; rows n..ld-1 are never read as data.
+ *   - All work is enqueued on `stream`.  Entry points that fill a host
+ *     result struct synchronise `stream` before returning.
+ *   - The library never allocates device memory.  Scratch space is the
+ *     caller's workspace `ws` (256-byte aligned) of at least the size the
+ *     matching *_workspace_size function returns.  The library keeps no
+ *     state between calls except a small pinned host status buffer per
+ *     call in flight.  Calls on different streams with distinct
+ *     workspaces may run concurrently; calls sharing a workspace must not.
+ *   - Return value: an npga_status code.  No C++ exception crosses the ABI.
+ *     Arguments are validated before anything is enqueued; on
+ *     NPGA_ERR_INVALID nothing has been launched.
+ */
+#ifndef NPGA_H
+#define NPGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest n supported by the register-resident projection and the fused
+ * gradient sweep: one 256-thread workgroup holds 32 entries per thread. */
+#define NPGA_MAX_N 8192
+
+typedef enum npga_status {
+  NPGA_OK = 0,
+  NPGA_ERR_INVALID = 1,       /* bad argument; nothing was launched          */
+  NPGA_ERR_INFEASIBLE = 2,    /* r > max_i mu_i, so F is empty (Sec. 3.1)    */
+  NPGA_ERR_NOT_CONVERGED = 3, /* max_iter reached; x is the last iterate (in F) */
+  NPGA_ERR_BRACKET = 4,       /* the dual search of Pi_F failed to bracket   */
+  NPGA_ERR_NUMERIC = 5,       /* NaN or Inf met in the data or the iteration */
+  NPGA_ERR_WORKSPACE = 6,     /* workspace missing, misaligned or too small  */
+  NPGA_ERR_HIP = 7,           /* a HIP runtime call failed                   */
+  NPGA_ERR_UNSUPPORTED = 8    /* valid request this build does not implement */
+} npga_status;
+
+typedef enum npga_path {
+  NPGA_PATH_AUTO = 0, /* choose GEMV or SYRK from the shape                   */
+  NPGA_PATH_GEMV = 1, /* grad = 2 L (L^T x): one fused sweep over L per step */
+  NPGA_PATH_SYRK = 2  /* Sigma = L L^T once (MFMA), then grad = 2 Sigma x     */
+} npga_path;
+
+/* Effective factor L_eff and ridge gamma of the unified model
+ * (Sec. 3.1, Tab. model-mapping): L (full), L Phi (sketch) or U_ell S_ell (STR). */
+typedef struct npga_factor {
+  int64_t n;         /* assets: 1 <= n <= NPGA_MAX_N                              */
+  int64_t cols;      /* columns of L_eff (T, s or ell), >= 1                      */
+  int64_t ld;        /* leading dimension in elements, >= n, multiple of 4       */
+  const float *L;    /* device, column-major n x cols, float32                    */
+  const double *mu;  /* device, n expected returns (float64)                      */
+  double gamma;      /* ridge >= 0                                                */
+} npga_factor;
+
+/* Solver options (host).  npga_default_options fills the defaults shown. */
+typedef struct npga_options {
+  double tol;            /* eps of the stopping rule ||Pi_F(x - a grad f(x)) - x||_2 <= eps
+                            (Sec. 3.1 "Stopping condition"); default 1e-6           */
+  int32_t check_every;   /* residual cadence in iterations (Sec. 5.1); default 5     */
+  int32_t max_iter;      /* default 200000                                            */
+  double proj_tol;       /* dual search stops at |mu^T x - r| <= proj_tol * max(|r|, max|mu|);
+                            default 1e-12 (the search normally finishes exactly)      */
+  int32_t power_iters;   /* power-method iterations for ||L_eff||_2 (Sec. 3.1 Remark);
+                            default 30                                                 */
+  double step_safety;    /* alpha = 1 / (step_safety * L_f_estimate), >= 1; default 1.05 */
+  int32_t refine;        /* 1 = FP64 KKT refinement after the stop; default 1         */
+  int32_t path;          /* npga_path; default NPGA_PATH_AUTO                          */
+  uint64_t seed;         /* seed of the power-method start vector; default 1          */
+  int32_t warm_start;    /* 1 = x holds x^0 on entry (projected onto F first)          */
+  int32_t restart;       /* 1 = adaptive gradient restart of the momentum; default 0  */
+  double refine_tol;     /* residual target of the refinement phase; default 1e-9     */
+  int32_t refine_max_iter; /* iteration cap of the refinement phase; default 20000    */
+} npga_options;
+
+/* Result of a solve (host). */
+typedef struct npga_result {
+  int32_t status;         /* npga_status of the solve                                */
+  int32_t iters;          /* NPGA iterations until the stopping test first passed   */
+  int32_t refine_iters;   /* iterations spent in the refinement phase               */
+  int32_t support;        /* number of x_i > 0                                       */
+  int32_t return_active;  /* 1 if the return constraint binds (nu > 0)              */
+  int32_t refined;        /* 1 if the refinement reached refine_tol                  */
+  int32_t path_used;      /* npga_path actually run                                  */
+  int32_t reserved;
+  double residual;        /* stopping residual when the test first passed           */
+  double final_residual;  /* residual of the returned x                             */
+  double objective;       /* f(x) of the returned x, accumulated in float64         */
+  double nu;              /* multiplier of mu^T x >= r (from the projection)        */
+  double lambda;          /* multiplier of 1^T x = 1                                 */
+  double alpha;           /* step size used                                          */
+  double lipschitz;       /* estimated L_f = 2 ||L_eff||_2^2 + 2 gamma              */
+  double time_ms;         /* host wall time of the whole call                       */
+  double time_to_tol_ms;  /* GPU time from entry until the stopping test first passed */
+  double setup_ms;        /* GPU time of checks, SYRK and step-size estimate          */
+  double sweep_ms;        /* mean duration of the gradient launch (fused sweep, or the
+                             covariance-path SYMV+tail), timed with HIP events on
+                             `stream` around one launch per chunk of the main phase   */
+  int32_t sweep_samples;  /* number of launches averaged into sweep_ms               */
+  int32_t reserved2;
+} npga_result;
+
+/* Fill `opt` (host) with the defaults documented above. */
+void npga_default_options(npga_options *opt);
+
+/* Text for a status code (static storage). */
+const char *npga_status_string(int status);
+
+/* ---------------------------------------------------------------------------
+ * npga_build_factor - sample mean and centred covariance factor (Sec. 2.1):
+ *     mu = (1/T) R 1_T,     L = (R - mu 1_T^T) / sqrt(T - 1),
+ * so that Sigma = L L^T is the unbiased sample covariance.
+ *   R      device, n x T float32 returns, column-major, leading dim ldr
+ *   L      device, n x T float32 output, leading dim ldl; may equal R when
+ *          ldl == ldr (in place)
+ *   mu_out device, n float64 output (sums accumulated in float64)
+ *   ws     device workspace of npga_build_factor_workspace_size(n, T) bytes
+ *          (per-workgroup partial row sums)
+ * Requires 1 <= n <= NPGA_MAX_N, T >= 2, ldr, ldl >= n and multiples of 4.
+ * Returns NPGA_ERR_NUMERIC (after the kernels ran) if R holds NaN or Inf.
+ * Synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+size_t npga_build_factor_workspace_size(int64_t n, int64_t T);
+int npga_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr,
+                      float *L, int64_t ldl, double *mu_out, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * npga_solve - Algorithm 1 (NPGA, Sec. 3.1) with the fixed step
+ * alpha = 1 / (step_safety * L_f_hat), L_f_hat from the power method on
+ * L_eff (Sec. 3.1 Remark), FISTA momentum t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+ * beta_k = (t_k - 1)/t_{k+1}, and x^{k+1} = Pi_F(y^k - alpha grad f(y^k)).
+ * Pi_F is computed exactly by the scalar dual search of eq. projF-dualpath
+ * (Sec. 3.1).  The stopping rule is checked every check_every iterations.
+ * With refine = 1 the iteration then continues (momentum restarted,
+ * adaptive restart on) until the residual reaches refine_tol, using
+ * mixed-precision iterative refinement: the gradient at the stopping point
+ * x_a is recomputed with float64 products, and later gradients are
+ * g_a + 2 L L^T (x - x_a) + 2 gamma x with the float32 sweep applied to the
+ * small correction x - x_a.
+ *   f      (host) effective factor and ridge; n <= NPGA_MAX_N
+ *   r      target return R_target; r > max mu gives NPGA_ERR_INFEASIBLE
+ *   opt    (host) options, or NULL for the defaults
+ *   x      device, n float32: x^0 on entry if opt->warm_start, the solution
+ *          on exit.  On NOT_CONVERGED it holds the last iterate, which lies
+ *          in F.
+ *   res    (host) result, may be NULL
+ *   ws     device workspace of npga_solve_workspace_size(n, cols, opt) bytes
+ * Synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *opt);
+int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x,
+               npga_result *res, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Step-level entry points (each is one step of the solve, exposed so that
+ * it can be checked on its own).
+ *
+ * npga_project - x = Pi_F(v) for F above (Sec. 3.1: simplex threshold of
+ *   eq. simplex-tau / simplex-proj, return face by eq. projF-dualpath).
+ *   v, mu device float64 (n); x device float64 (n) output; nu_tau (host,
+ *   may be NULL) receives {nu, tau}.  Returns NPGA_ERR_INFEASIBLE if
+ *   r > max mu.  Uses ws of npga_solve_workspace_size(n, 1, NULL) bytes.
+ *
+ * npga_gradient - g = 2 L_eff (L_eff^T x) + 2 gamma x and
+ *   f = ||L_eff^T x||^2 + gamma ||x||^2 (eq. npga-unified-grad) by the
+ *   fused single-pass sweep.  x device float32 (n), g device float64 (n),
+ *   f_out (host, may be NULL).  ws as for npga_solve.
+ *
+ * npga_spectral_norm_sq - ||L_eff||_2^2 estimated by `iters` power-method
+ *   steps from a seeded Gaussian start (Sec. 3.1 Remark); the returned value
+ *   is the last Rayleigh value ||L_eff^T u||^2, a lower bound.
+ *
+ * npga_syrk - Sigma = L L^T (n x n float32, column-major, leading dim lds,
+ *   both triangles written) by float32 MFMA with float64 accumulation
+ *   across k-chunks.  The explicit-covariance form of Sec. 3.1 uses it.
+ * ------------------------------------------------------------------------- */
+int npga_project(const double *v, const double *mu, int64_t n, double r, double *x,
+                 double *nu_tau, void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out,
+                  void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed,
+                          double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
+              hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * npga_sketch_str - Sketch-Truncate-Ridge (Sec. 2.5; App. D):
+ *     Y = L S                       (sketch stage, S T x k, entries N(0, 1/k)),
+ *     Y = U Sig V^T, keep ell       (truncation stage),
+ *     L_eff = Y V_ell = U_ell Sig_ell  (n x ell; App. D "STR as one sketch"),
+ *     gamma = ridge_coef * trace(Y Y^T) / n   (ridge stage; untruncated Y).
+ *   L       device n x T float32 (ldl)
+ *   S_opt   device T x k float32 column-major (leading dim T), or NULL to draw
+ *           S on the device from Philox4x32-10 keyed by `seed`
+ *   Leff    device n x ell float32 output (ldle >= n, multiple of 4)
+ *   sigma   device ell float32 output: leading singular values of Y
+ *   gamma_out (host) receives gamma
+ *   ws      npga_sketch_workspace_size(n, T, k, ell) bytes
+ * Requires 1 <= ell <= k <= 8192 and ell < n.
+ * ------------------------------------------------------------------------- */
+size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell);
+int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k,
+                    int64_t ell, double ridge_coef, uint64_t seed, const float *S_opt,
+                    float *Leff, int64_t ldle, float *sigma, double *gamma_out, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * npga_solve_batched - m independent solves sharing L_eff (an efficient
+ * frontier: one target r_j per column of X).  r_targets (host, m values),
+ * X device n x m float32 (leading dim n), res (host, m results, may be NULL).
+ * Returns NPGA_ERR_UNSUPPORTED in builds without the batched path.
+ *
+ * npga_backward - gradients of a loss l(x*) through the solution map
+ * x*(mu, L) by implicit differentiation of the KKT system on the active set.
+ * Returns NPGA_ERR_UNSUPPORTED in builds without the adjoint.
+ * ------------------------------------------------------------------------- */
+size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt);
+int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
+                       const npga_options *opt, float *X, npga_result *res, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,
+                  double *dl_dmu, float *dl_dL, void *ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPGA_H */

@@ -92,11 +92,14 @@ def multipliers(H, c, mu, r, x, act_tol=None):
     return float(sol[0]), float(sol[1])
 
 
-def kkt_report(H, c, mu, r, x, lam=None, nu=None):
-    """Residuals of every KKT condition at x (all as plain floats)."""
+def kkt_report(H, c, mu, r, x, lam=None, nu=None, act_tol=None):
+    """Residuals of every KKT condition at x (all as plain floats).
+
+    ``act_tol`` is the slack below which the return constraint counts as
+    active when the multipliers are estimated (default: float64 rounding)."""
     x = np.asarray(x, dtype=np.float64)
     if lam is None:
-        lam, nu = multipliers(H, c, mu, r, x)
+        lam, nu = multipliers(H, c, mu, r, x, act_tol=act_tol)
     g = H @ x + c
     d = g - lam - nu * mu
     S = x > 0

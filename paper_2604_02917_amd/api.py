@@ -1,0 +1,250 @@
+"""ctypes binding of libnpga (see include/npga.h for the semantics).
+
+Every function takes CUDA/HIP torch tensors already resident on the device
+and enqueues on ``torch.cuda.current_stream()``.  Matrices are passed as
+C-contiguous (cols, n) float32 tensors: row t is column t of the n x cols
+matrix, i.e. the column-major layout with leading dimension n.  When n is
+not a multiple of 4 the binding copies into a padded buffer (ld = 4
+ceil(n/4)) because the kernels load float4.
+"""
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnpga.so")
+
+NPGA_OK = 0
+STATUS_NAMES = {
+    0: "OK", 1: "INVALID", 2: "INFEASIBLE", 3: "NOT_CONVERGED", 4: "BRACKET",
+    5: "NUMERIC", 6: "WORKSPACE", 7: "HIP", 8: "UNSUPPORTED",
+}
+PATHS = {"auto": 0, "gemv": 1, "syrk": 2}
+
+
+class NpgaError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)} ({status_string(code)})")
+
+
+class _Factor(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("L", ctypes.c_void_p), ("mu", ctypes.c_void_p), ("gamma", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("proj_tol", ctypes.c_double),
+                ("power_iters", ctypes.c_int32), ("step_safety", ctypes.c_double),
+                ("refine", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("return_active", ctypes.c_int32), ("refined", ctypes.c_int32),
+                ("path_used", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("final_residual", ctypes.c_double),
+                ("objective", ctypes.c_double), ("nu", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("lipschitz", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("time_to_tol_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("sweep_samples", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_2604_02917_amd.build` "
+            "(there is no non-HIP fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    u64 = ctypes.c_uint64
+    sig = {
+        "npga_default_options": (None, [ctypes.POINTER(_Options)]),
+        "npga_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "npga_solve_workspace_size": (sz, [i64, i64, ctypes.POINTER(_Options)]),
+        "npga_solve": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, ctypes.POINTER(_Options), vp,
+                                      ctypes.POINTER(_Result), vp, sz, vp]),
+        "npga_project": (ctypes.c_int, [vp, vp, i64, dbl, vp, vp, vp, sz, vp]),
+        "npga_gradient": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp, sz, vp]),
+        "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, vp, vp, sz, vp]),
+        "npga_syrk": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
+        "npga_build_factor_workspace_size": (sz, [i64, i64]),
+        "npga_build_factor": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]),
+        "npga_sketch_workspace_size": (sz, [i64, i64, i64, i64]),
+        "npga_sketch_str": (ctypes.c_int, [vp, i64, i64, i64, i64, i64, dbl, u64, vp, vp, i64, vp,
+                                           vp, vp, sz, vp]),
+        "npga_batched_workspace_size": (sz, [i64, i64, i32, ctypes.POINTER(_Options)]),
+        "npga_solve_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i32, ctypes.POINTER(_Options),
+                                              vp, ctypes.POINTER(_Result), vp, sz, vp]),
+        "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def status_string(code):
+    return _lib.npga_status_string(int(code)).decode()
+
+
+@dataclasses.dataclass
+class Options:
+    tol: float = 1e-6
+    check_every: int = 5
+    max_iter: int = 200000
+    proj_tol: float = 1e-12
+    power_iters: int = 30
+    step_safety: float = 1.05
+    refine: bool = True
+    path: str = "auto"
+    seed: int = 1
+    warm_start: bool = False
+    restart: bool = False
+    refine_tol: float = 1e-9
+    refine_max_iter: int = 20000
+
+    def _c(self):
+        o = _Options()
+        _lib.npga_default_options(ctypes.byref(o))
+        o.tol, o.check_every, o.max_iter = self.tol, self.check_every, self.max_iter
+        o.proj_tol, o.power_iters, o.step_safety = self.proj_tol, self.power_iters, self.step_safety
+        o.refine, o.path, o.seed = int(self.refine), PATHS[self.path], self.seed
+        o.warm_start, o.restart = int(self.warm_start), int(self.restart)
+        o.refine_tol, o.refine_max_iter = self.refine_tol, self.refine_max_iter
+        return o
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(code, where):
+    if code != NPGA_OK:
+        raise NpgaError(code, where)
+
+
+def _as_colmajor(M):
+    """(cols, n) float32 CUDA tensor -> (tensor with row stride ld, n, cols, ld)."""
+    if M.dim() != 2 or M.dtype != torch.float32 or not M.is_cuda:
+        raise ValueError("expected a 2-D float32 CUDA tensor of shape (cols, n)")
+    cols, n = M.shape
+    ld = (n + 3) // 4 * 4
+    if M.is_contiguous() and ld == n and M.data_ptr() % 16 == 0:
+        return M, n, cols, ld
+    buf = torch.zeros((cols, ld), dtype=torch.float32, device=M.device)
+    buf[:, :n].copy_(M)
+    return buf, n, cols, ld
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _factor(Lb, n, cols, ld, mu, gamma):
+    return _Factor(n, cols, ld, Lb.data_ptr(), mu.data_ptr(), float(gamma))
+
+
+def build_factor(R_TxN):
+    """mu = R 1/T, L = (R - mu 1^T)/sqrt(T-1) on the GPU (Sec. 2.1).
+
+    R_TxN: (T, n) float32 CUDA tensor.  Returns (L (T, n) float32, mu (n,) float64).
+    """
+    Rb, n, T, ld = _as_colmajor(R_TxN)
+    L = torch.empty((T, ld), dtype=torch.float32, device=Rb.device)
+    mu = torch.empty(n, dtype=torch.float64, device=Rb.device)
+    ws = _workspace(_lib.npga_build_factor_workspace_size(n, T), Rb.device)
+    _check(_lib.npga_build_factor(_ptr(Rb), n, T, ld, _ptr(L), ld, _ptr(mu), _ptr(ws), ws.numel(),
+                                  _stream()), "npga_build_factor")
+    return (L if ld == n else L[:, :n]), mu
+
+
+def solve(L_TxN, mu, r, gamma=0.0, x0=None, options=None, **kw):
+    """NPGA solve (Algorithm 1).  Returns (x (n,) float32 tensor, info dict)."""
+    opts = options or Options(**kw)
+    if x0 is not None:
+        opts = dataclasses.replace(opts, warm_start=True)
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    mu = mu.to(dtype=torch.float64).contiguous()
+    co = opts._c()
+    ws = _workspace(_lib.npga_solve_workspace_size(n, cols, ctypes.byref(co)), Lb.device)
+    x = torch.empty(n, dtype=torch.float32, device=Lb.device)
+    if x0 is not None:
+        x.copy_(x0.to(torch.float32))
+    res = _Result()
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    code = _lib.npga_solve(ctypes.byref(f), float(r), ctypes.byref(co), _ptr(x), ctypes.byref(res),
+                           _ptr(ws), ws.numel(), _stream())
+    info = {k: getattr(res, k) for k, _ in _Result._fields_}
+    info["lambda"] = info.pop("lambda_")
+    info["status_name"] = STATUS_NAMES.get(code, str(code))
+    if code not in (NPGA_OK, 3):
+        raise NpgaError(code, "npga_solve")
+    return x, info
+
+
+def project(v, mu, r):
+    """Pi_F(v) (Sec. 3.1).  v, mu: (n,) float64 CUDA.  Returns (x, nu, tau)."""
+    v = v.to(torch.float64).contiguous()
+    mu = mu.to(torch.float64).contiguous()
+    n = v.numel()
+    x = torch.empty_like(v)
+    ws = _workspace(_lib.npga_solve_workspace_size(n, 1, None), v.device)
+    nt = (ctypes.c_double * 2)()
+    _check(_lib.npga_project(_ptr(v), _ptr(mu), n, float(r), _ptr(x), nt, _ptr(ws), ws.numel(),
+                             _stream()), "npga_project")
+    return x, nt[0], nt[1]
+
+
+def gradient(L_TxN, x, gamma=0.0):
+    """g = 2 L(L^T x) + 2 gamma x and f(x) (eq. npga-unified-grad) by the fused sweep."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    x = x.to(torch.float32).contiguous()
+    mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
+    g = torch.empty(n, dtype=torch.float64, device=Lb.device)
+    ws = _workspace(_lib.npga_solve_workspace_size(n, cols, None), Lb.device)
+    fv = ctypes.c_double(0.0)
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    _check(_lib.npga_gradient(ctypes.byref(f), _ptr(x), _ptr(g), ctypes.byref(fv), _ptr(ws),
+                              ws.numel(), _stream()), "npga_gradient")
+    return g, fv.value
+
+
+def spectral_norm_sq(L_TxN, iters=30, seed=1):
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
+    ws = _workspace(_lib.npga_solve_workspace_size(n, cols, None), Lb.device)
+    out = ctypes.c_double(0.0)
+    f = _factor(Lb, n, cols, ld, mu, 0.0)
+    _check(_lib.npga_spectral_norm_sq(ctypes.byref(f), int(iters), int(seed), ctypes.byref(out),
+                                      _ptr(ws), ws.numel(), _stream()), "npga_spectral_norm_sq")
+    return out.value
+
+
+def syrk(L_TxN):
+    """Sigma = L L^T (n x n float32, symmetric, both triangles)."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    lds = ld
+    S = torch.empty((n, lds), dtype=torch.float32, device=Lb.device)
+    _check(_lib.npga_syrk(_ptr(Lb), n, cols, ld, _ptr(S), lds, _stream()), "npga_syrk")
+    return S[:, :n]

@@ -1,0 +1,619 @@
+// Host orchestration and the C ABI of libnpga (declared in include/npga.h).
+//
+// Every entry point validates its arguments before enqueuing anything,
+// carves the caller's workspace, and enqueues HIP kernels on the caller's
+// stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "npga.h"
+#include "npga_internal.h"
+
+using npga::DevState;
+using npga::SolveArgs;
+using npga::SolveLayout;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Pinned host mirrors of the device state, one set per host thread.  They
+// are allocated on first use and kept for the life of the process.
+constexpr int kStatusSlots = 4;
+DevState *pinned_status() {
+  thread_local DevState *buf = nullptr;
+  if (!buf) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sizeof(DevState) * kStatusSlots, hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    buf = static_cast<DevState *>(p);
+  }
+  return buf;
+}
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    if ((expr) != hipSuccess) return NPGA_ERR_HIP;     \
+  } while (0)
+#define LAUNCHCHK(expr)                                \
+  do {                                                 \
+    if ((expr) != 0) return NPGA_ERR_HIP;              \
+  } while (0)
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+namespace npga {
+
+int sweep_grid_for(int64_t cols) {
+  const int64_t waves_needed = cols;  // one wavefront per column at most
+  const int64_t g = (waves_needed + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
+}
+
+SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
+  SolveLayout l{};
+  l.slots = slots_for(n);
+  const int64_t npad = (int64_t)256 * std::max(l.slots, 1);
+  l.ldp = npad;
+  l.sweep_grid = sweep_grid_for(path == NPGA_PATH_SYRK ? n : cols);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  l.off_state = take(sizeof(DevState));
+  l.off_status_dev = take(sizeof(DevState));
+  l.off_xs = take(sizeof(float) * npad);
+  l.off_x0 = take(sizeof(double) * npad);
+  l.off_x1 = take(sizeof(double) * npad);
+  l.off_g0 = take(sizeof(double) * npad);
+  l.off_g1 = take(sizeof(double) * npad);
+  // partial vectors: float32 for the sweep, float64 for the anchor gradient
+  const int gmax = sweep_grid_for(std::max(cols, n));
+  l.off_part = take(sizeof(double) * (size_t)std::max(gmax, l.sweep_grid) * (size_t)l.ldp);
+  l.off_usq = take(sizeof(double) * (size_t)l.sweep_grid);
+  if (path == NPGA_PATH_SYRK) {
+    const int64_t lds = (n + 3) / 4 * 4;
+    l.off_sigma = take(sizeof(float) * (size_t)lds * (size_t)n);
+  } else {
+    l.off_sigma = 0;
+  }
+  l.off_vecs = take(sizeof(double) * npad * 4);
+  l.off_xa = take(sizeof(double) * npad);
+  l.off_ga = take(sizeof(double) * npad);
+  l.off_ua = take(sizeof(double) * (size_t)cols);
+  l.total = off;
+  return l;
+}
+
+}  // namespace npga
+
+namespace {
+
+int resolve_path(int requested, int64_t n, int64_t cols) {
+  if (requested == NPGA_PATH_GEMV || requested == NPGA_PATH_SYRK) return requested;
+  (void)n;
+  (void)cols;
+  return NPGA_PATH_GEMV;
+}
+
+bool options_valid(const npga_options &o) {
+  return is_fin(o.tol) && o.tol > 0 && o.check_every >= 1 && o.max_iter >= 1 && is_fin(o.proj_tol) &&
+         o.proj_tol > 0 && o.power_iters >= 1 && is_fin(o.step_safety) && o.step_safety >= 1.0 &&
+         (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
+         is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0;
+}
+
+bool factor_valid(const npga_factor *f) {
+  if (!f || !f->L || !f->mu) return false;
+  if (f->n < 1 || f->n > NPGA_MAX_N || f->cols < 1) return false;
+  if (f->ld < f->n || (f->ld % 4) != 0) return false;
+  if (!aligned(f->L, 16) || !aligned(f->mu, 8)) return false;
+  if (!is_fin(f->gamma) || f->gamma < 0) return false;
+  return true;
+}
+
+struct Carved {
+  SolveArgs a;
+  DevState *st;
+  float *sigma;
+  int64_t lds;
+};
+
+Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
+  char *base = static_cast<char *>(ws);
+  Carved c{};
+  SolveArgs &a = c.a;
+  a.L = f->L;
+  a.ld = f->ld;
+  a.n = f->n;
+  a.cols = f->cols;
+  a.mu = f->mu;
+  a.xs = reinterpret_cast<float *>(base + l.off_xs);
+  a.xbuf0 = reinterpret_cast<double *>(base + l.off_x0);
+  a.xbuf1 = reinterpret_cast<double *>(base + l.off_x1);
+  a.gbuf0 = reinterpret_cast<double *>(base + l.off_g0);
+  a.gbuf1 = reinterpret_cast<double *>(base + l.off_g1);
+  a.partials = reinterpret_cast<float *>(base + l.off_part);
+  a.usq_part = reinterpret_cast<double *>(base + l.off_usq);
+  a.ldp = l.ldp;
+  a.sweep_grid = l.sweep_grid;
+  a.mode = npga::kTailNpga;
+  a.st = reinterpret_cast<DevState *>(base + l.off_state);
+  c.st = a.st;
+  c.lds = (f->n + 3) / 4 * 4;
+  c.sigma = (path == NPGA_PATH_SYRK) ? reinterpret_cast<float *>(base + l.off_sigma) : nullptr;
+  return c;
+}
+
+DevState initial_state(const npga_factor *f, double r, const npga_options &o) {
+  DevState s;
+  std::memset(&s, 0, sizeof(s));
+  s.done = npga::kRunning;
+  s.iter = 0;
+  s.stop_iter = -1;
+  s.max_iter = o.max_iter;
+  s.check_every = o.check_every;
+  s.restart = o.restart;
+  s.t = 1.0;
+  s.gamma = f->gamma;
+  s.r = r;
+  s.tol = o.tol;
+  s.residual = INFINITY;
+  s.stop_residual = INFINITY;
+  return s;
+}
+
+// One gradient evaluation + tail, on either path.
+int step(const Carved &c, int path, int slots, hipStream_t s) {
+  if (path == NPGA_PATH_SYRK) return npga::launch_symv_tail(c.a, c.sigma, c.lds, slots, s);
+  int e = npga::launch_sweep(c.a, slots, s);
+  if (e) return e;
+  return npga::launch_reduce_tail(c.a, slots, s);
+}
+
+int map_done(int done) {
+  switch (done) {
+    case npga::kConverged: return NPGA_OK;
+    case npga::kMaxIter: return NPGA_ERR_NOT_CONVERGED;
+    case npga::kNumeric: return NPGA_ERR_NUMERIC;
+    case npga::kBracket: return NPGA_ERR_BRACKET;
+    default: return NPGA_ERR_NOT_CONVERGED;
+  }
+}
+
+// Runs chunks of `check_every` iterations until the device reports done.
+// Two chunks are kept in flight; the status of chunk j is read while chunk
+// j+1 runs.  Returns the final done code via *done_out and the GPU time
+// from `ev0` to the end of the chunk in which the phase finished.
+struct SweepTimer {
+  hipEvent_t a[2], b[2];
+  double total_ms = 0.0;
+  int samples = 0;
+};
+
+int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max_chunks, hipStream_t s,
+              DevState *pin, hipEvent_t *evs, hipEvent_t ev0, int *done_out, double *phase_ms,
+              SweepTimer *tm) {
+  int64_t issued = 0, consumed = 0;
+  auto issue = [&](int slot) -> int {
+    for (int i = 0; i < check_every; ++i) {
+      if (i == 0 && tm) {
+        // time the first gradient launch of every chunk on this stream
+        if (hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+        const int e = (path == NPGA_PATH_SYRK) ? npga::launch_symv_tail(c.a, c.sigma, c.lds, slots, s)
+                                               : npga::launch_sweep(c.a, slots, s);
+        if (e) return NPGA_ERR_HIP;
+        if (hipEventRecord(tm->b[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+        if (path != NPGA_PATH_SYRK && npga::launch_reduce_tail(c.a, slots, s)) return NPGA_ERR_HIP;
+        continue;
+      }
+      if (step(c, path, slots, s)) return NPGA_ERR_HIP;
+    }
+    if (hipMemcpyAsync(&pin[slot], c.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return NPGA_ERR_HIP;
+    if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+    return NPGA_OK;
+  };
+  int e = issue(0);
+  if (e) return e;
+  ++issued;
+  e = issue(1);
+  if (e) return e;
+  ++issued;
+  for (;;) {
+    const int slot = consumed & 1;
+    if (hipEventSynchronize(evs[slot]) != hipSuccess) return NPGA_ERR_HIP;
+    ++consumed;
+    const int done = pin[slot].done;
+    if (tm && done == npga::kRunning) {  // only chunks that ran every launch in full
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, tm->a[slot], tm->b[slot]) == hipSuccess) {
+        tm->total_ms += ms;
+        tm->samples += 1;
+      }
+    }
+    if (done != npga::kRunning) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev0, evs[slot]);
+      *phase_ms = ms;
+      *done_out = done;
+      // drain the chunk still in flight (its kernels exit at once)
+      if (hipStreamSynchronize(s) != hipSuccess) return NPGA_ERR_HIP;
+      return NPGA_OK;
+    }
+    if (issued >= max_chunks) {
+      // the device must have reported max_iter long before this; stop
+      // rather than loop if it did not
+      if (hipStreamSynchronize(s) != hipSuccess) return NPGA_ERR_HIP;
+      *done_out = npga::kMaxIter;
+      *phase_ms = 0.0;
+      return NPGA_OK;
+    }
+    e = issue(slot);
+    if (e) return e;
+    ++issued;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void npga_default_options(npga_options *o) {
+  if (!o) return;
+  o->tol = 1e-6;
+  o->check_every = 5;
+  o->max_iter = 200000;
+  o->proj_tol = 1e-12;
+  o->power_iters = 30;
+  o->step_safety = 1.05;
+  o->refine = 1;
+  o->path = NPGA_PATH_AUTO;
+  o->seed = 1;
+  o->warm_start = 0;
+  o->restart = 0;
+  o->refine_tol = 1e-9;
+  o->refine_max_iter = 20000;
+}
+
+const char *npga_status_string(int status) {
+  switch (status) {
+    case NPGA_OK: return "ok";
+    case NPGA_ERR_INVALID: return "invalid argument";
+    case NPGA_ERR_INFEASIBLE: return "infeasible: target return exceeds max(mu)";
+    case NPGA_ERR_NOT_CONVERGED: return "not converged within max_iter";
+    case NPGA_ERR_BRACKET: return "dual search failed to bracket the return multiplier";
+    case NPGA_ERR_NUMERIC: return "non-finite value in the data or the iteration";
+    case NPGA_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case NPGA_ERR_HIP: return "HIP runtime error";
+    case NPGA_ERR_UNSUPPORTED: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *opt) {
+  if (n < 1 || n > NPGA_MAX_N || cols < 1) return 0;
+  npga_options o;
+  npga_default_options(&o);
+  if (opt) o = *opt;
+  const int path = resolve_path(o.path, n, cols);
+  return npga::solve_layout(n, cols, path).total;
+}
+
+int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x, npga_result *res,
+               void *ws, size_t ws_bytes, hipStream_t stream) {
+  const auto t0 = Clock::now();
+  npga_options o;
+  npga_default_options(&o);
+  if (opt) o = *opt;
+  if (!factor_valid(f) || !x || !is_fin(r) || !options_valid(o)) return NPGA_ERR_INVALID;
+  const int path = resolve_path(o.path, f->n, f->cols);
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, path);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  Carved c = carve(f, lay, ws, path);
+  const int slots = lay.slots;
+
+  hipEvent_t ev0, evs[2], ev_setup;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&evs[0]));
+  HIPCHK(hipEventCreate(&evs[1]));
+  HIPCHK(hipEventCreate(&ev_setup));
+  struct EvGuard {
+    hipEvent_t *e;
+    int k;
+    ~EvGuard() {
+      for (int i = 0; i < k; ++i) (void)hipEventDestroy(e[i]);
+    }
+  };
+  SweepTimer tm;
+  HIPCHK(hipEventCreate(&tm.a[0]));
+  HIPCHK(hipEventCreate(&tm.a[1]));
+  HIPCHK(hipEventCreate(&tm.b[0]));
+  HIPCHK(hipEventCreate(&tm.b[1]));
+  hipEvent_t all[8] = {ev0, evs[0], evs[1], ev_setup, tm.a[0], tm.a[1], tm.b[0], tm.b[1]};
+  EvGuard guard{all, 8};
+
+  HIPCHK(hipEventRecord(ev0, stream));
+  // state, mu statistics and the feasibility check (the only sync before the loop)
+  DevState init = initial_state(f, r, o);
+  pin[2] = init;
+  HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_prepare(c.a, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pin[3].n_nonfinite > 0) return NPGA_ERR_NUMERIC;
+  if (r > pin[3].mu_max) return NPGA_ERR_INFEASIBLE;
+  LAUNCHCHK(npga::launch_set_tolphi(c.st, o.proj_tol, stream));
+
+  // explicit covariance (SYRK path): Sigma = L L^T once
+  if (path == NPGA_PATH_SYRK)
+    LAUNCHCHK(npga::launch_syrk(f->L, f->n, f->cols, f->ld, c.sigma, c.lds, stream));
+
+  // step size: power method on L_eff (Sec. 3.1 Remark), alpha = 1/(safety L_f_hat)
+  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, o.seed, stream));
+  {
+    Carved cp = c;
+    cp.a.mode = npga::kTailPower;
+    for (int i = 0; i < o.power_iters; ++i) LAUNCHCHK(step(cp, path, slots, stream));
+  }
+  LAUNCHCHK(npga::launch_set_alpha(c.st, o.step_safety, stream));
+
+  // x^0 = Pi_F(x_in or 1/n)
+  LAUNCHCHK(npga::launch_set_vector(c.a.xbuf0, o.warm_start ? x : nullptr, nullptr, f->n,
+                                    1.0 / (double)f->n, c.a.xs, stream));
+  LAUNCHCHK(npga::launch_project_init(c.a, slots, o.warm_start, stream));
+  HIPCHK(hipEventRecord(ev_setup, stream));
+
+  int done = 0;
+  double tol_ms = 0.0;
+  const int64_t main_chunks = (int64_t)o.max_iter / o.check_every + 4;
+  int e = run_phase(c, path, slots, o.check_every, main_chunks, stream, pin, evs, ev0, &done, &tol_ms, &tm);
+  if (e) return e;
+  const int main_done = done;
+  DevState after_main = pin[0].done != npga::kRunning ? pin[0] : pin[1];
+  HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  after_main = pin[2];
+  const double host_tol_ms = ms_since(t0);
+  (void)host_tol_ms;
+
+  int refined = 0;
+  int refine_iters = 0;
+  if (main_done == npga::kConverged && o.refine && o.refine_max_iter > 0) {
+    // anchor x_a = x_k; float64 gradient there; iterate on d = x - x_a
+    char *base = static_cast<char *>(ws);
+    double *xa = reinterpret_cast<double *>(base + lay.off_xa);
+    double *ga = reinterpret_cast<double *>(base + lay.off_ga);
+    double *ua = reinterpret_cast<double *>(base + lay.off_ua);
+    double *scratch = reinterpret_cast<double *>(base + lay.off_vecs);
+    const double *xk = (after_main.iter & 1) ? c.a.xbuf1 : c.a.xbuf0;
+    HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
+    LAUNCHCHK(npga::launch_precise_gradient(c.a, xa, ua, ga, reinterpret_cast<double *>(c.a.partials),
+                                            slots, stream));
+    LAUNCHCHK(npga::launch_set_vector(scratch, nullptr, nullptr, f->n, 0.0, c.a.xs, stream));
+    c.a.xa = xa;
+    c.a.ga = ga;
+    c.a.ua = (path == NPGA_PATH_GEMV) ? ua : nullptr;
+    const int32_t cap = after_main.iter + o.refine_max_iter;
+    LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, cap, stream));
+    double rms = 0.0;
+    const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
+    e = run_phase(c, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
+    if (e) return e;
+    refined = (done == npga::kConverged) ? 1 : 0;
+  }
+  LAUNCHCHK(npga::launch_finalize(c.a, x, slots, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const DevState &fin = pin[3];
+  refine_iters = (main_done == npga::kConverged) ? fin.iter - after_main.iter : 0;
+
+  int status = map_done(main_done);
+  if (main_done == npga::kConverged && done != npga::kConverged && done != npga::kMaxIter)
+    status = map_done(done);  // numeric or bracket failure during refinement
+  if (res) {
+    float setup_ms = 0.f;
+    (void)hipEventElapsedTime(&setup_ms, ev0, ev_setup);
+    std::memset(res, 0, sizeof(*res));
+    res->status = status;
+    res->iters = (main_done == npga::kConverged) ? after_main.stop_iter : after_main.iter;
+    res->refine_iters = refine_iters;
+    res->support = fin.support;
+    res->return_active = fin.nu_c > 0.0 ? 1 : 0;
+    res->refined = refined;
+    res->path_used = path;
+    res->residual = after_main.stop_residual;
+    res->final_residual = fin.residual;
+    res->objective = fin.objective;
+    res->nu = fin.nu_kkt;
+    res->lambda = fin.lambda_kkt;
+    res->alpha = fin.alpha;
+    res->lipschitz = fin.lipschitz;
+    res->time_ms = ms_since(t0);
+    res->time_to_tol_ms = tol_ms;
+    res->setup_ms = setup_ms;
+    res->sweep_ms = tm.samples ? tm.total_ms / tm.samples : 0.0;
+    res->sweep_samples = tm.samples;
+  }
+  return status;
+}
+
+int npga_project(const double *v, const double *mu, int64_t n, double r, double *x, double *nu_tau,
+                 void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!v || !mu || !x || n < 1 || n > NPGA_MAX_N || !is_fin(r)) return NPGA_ERR_INVALID;
+  npga_options o;
+  npga_default_options(&o);
+  const SolveLayout lay = npga::solve_layout(n, 1, NPGA_PATH_GEMV);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  DevState *st = reinterpret_cast<DevState *>(static_cast<char *>(ws) + lay.off_state);
+  npga_factor f{n, 1, (n + 3) / 4 * 4, reinterpret_cast<const float *>(ws), mu, 0.0};
+  pin[2] = initial_state(&f, r, o);
+  HIPCHK(hipMemcpyAsync(st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  SolveArgs a{};
+  a.mu = mu;
+  a.n = n;
+  a.st = st;
+  LAUNCHCHK(npga::launch_prepare(a, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pin[3].n_nonfinite > 0) return NPGA_ERR_NUMERIC;
+  if (r > pin[3].mu_max) return NPGA_ERR_INFEASIBLE;
+  LAUNCHCHK(npga::launch_set_tolphi(st, o.proj_tol, stream));
+  LAUNCHCHK(npga::launch_project_only(v, mu, n, x, st, lay.slots, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (nu_tau) {
+    nu_tau[0] = pin[3].nu;
+    nu_tau[1] = pin[3].tau;
+  }
+  if (pin[3].proj_flags & 2) return NPGA_ERR_BRACKET;
+  return NPGA_OK;
+}
+
+int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out, void *ws,
+                  size_t ws_bytes, hipStream_t stream) {
+  if (!factor_valid(f) || !x || !g) return NPGA_ERR_INVALID;
+  if (!aligned(g, 8)) return NPGA_ERR_INVALID;
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  npga_options o;
+  npga_default_options(&o);
+  Carved c = carve(f, lay, ws, NPGA_PATH_GEMV);
+  c.a.mode = npga::kTailGrad;
+  c.a.gbuf0 = g;
+  pin[2] = initial_state(f, 0.0, o);
+  HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_set_vector(c.a.xbuf0, x, nullptr, f->n, 0.0, c.a.xs, stream));
+  LAUNCHCHK(npga::launch_sweep(c.a, lay.slots, stream));
+  LAUNCHCHK(npga::launch_reduce_tail(c.a, lay.slots, stream));
+  if (f_out) {
+    HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *f_out = pin[3].objective;
+  }
+  return NPGA_OK;
+}
+
+int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, double *out, void *ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  if (!factor_valid(f) || !out || iters < 1) return NPGA_ERR_INVALID;
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  npga_options o;
+  npga_default_options(&o);
+  Carved c = carve(f, lay, ws, NPGA_PATH_GEMV);
+  c.a.mode = npga::kTailPower;
+  pin[2] = initial_state(f, 0.0, o);
+  HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, seed, stream));
+  for (int i = 0; i < iters; ++i) {
+    LAUNCHCHK(npga::launch_sweep(c.a, lay.slots, stream));
+    LAUNCHCHK(npga::launch_reduce_tail(c.a, lay.slots, stream));
+  }
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  *out = pin[3].rho2;
+  return NPGA_OK;
+}
+
+int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
+              hipStream_t stream) {
+  if (!L || !Sigma || n < 1 || T < 1 || ld < n || (ld % 4) != 0 || lds < n || (lds % 4) != 0)
+    return NPGA_ERR_INVALID;
+  if (!aligned(L, 16) || !aligned(Sigma, 16)) return NPGA_ERR_INVALID;
+  LAUNCHCHK(npga::launch_syrk(L, n, T, ld, Sigma, lds, stream));
+  return NPGA_OK;
+}
+
+size_t npga_build_factor_workspace_size(int64_t n, int64_t T) {
+  if (n < 1 || n > NPGA_MAX_N || T < 2) return 0;
+  const int slots = npga::slots_for(n);
+  const int grid = npga::sweep_grid_for(T);
+  return align_up(sizeof(double) * ((size_t)grid * 256 * slots + grid + 8), 256);
+}
+
+int npga_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *L, int64_t ldl,
+                      double *mu_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!R || !L || !mu_out || n < 1 || n > NPGA_MAX_N || T < 2) return NPGA_ERR_INVALID;
+  if (ldr < n || ldl < n || (ldr % 4) != 0 || (ldl % 4) != 0) return NPGA_ERR_INVALID;
+  if (!aligned(R, 16) || !aligned(L, 16) || !aligned(mu_out, 8)) return NPGA_ERR_INVALID;
+  if (R == L && ldr != ldl) return NPGA_ERR_INVALID;
+  const size_t need = npga_build_factor_workspace_size(n, T);
+  if (!ws || !aligned(ws, 256) || ws_bytes < need) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  const int grid = npga::sweep_grid_for(T);
+  const int slots = npga::slots_for(n);
+  double *part = static_cast<double *>(ws);
+  double *nonfinite = part + (size_t)grid * 256 * slots + grid;
+  LAUNCHCHK(npga::launch_build_factor(R, n, T, ldr, L, ldl, mu_out, part, grid, nonfinite, stream));
+  double *h = reinterpret_cast<double *>(&pin[3]);
+  HIPCHK(hipMemcpyAsync(h, nonfinite, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (*h > 0) return NPGA_ERR_NUMERIC;
+  return NPGA_OK;
+}
+
+size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell) {
+  (void)n;
+  (void)T;
+  (void)k;
+  (void)ell;
+  return 0;
+}
+
+int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k, int64_t ell,
+                    double ridge_coef, uint64_t seed, const float *S_opt, float *Leff, int64_t ldle,
+                    float *sigma, double *gamma_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  (void)L; (void)n; (void)T; (void)ldl; (void)k; (void)ell; (void)ridge_coef; (void)seed;
+  (void)S_opt; (void)Leff; (void)ldle; (void)sigma; (void)gamma_out; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return NPGA_ERR_UNSUPPORTED;
+}
+
+size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt) {
+  (void)n; (void)cols; (void)m; (void)opt;
+  return 0;
+}
+
+int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
+                       const npga_options *opt, float *X, npga_result *res, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  (void)f; (void)r_targets; (void)m; (void)opt; (void)X; (void)res; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return NPGA_ERR_UNSUPPORTED;
+}
+
+int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,
+                  double *dl_dmu, float *dl_dL, void *ws, size_t ws_bytes, hipStream_t stream) {
+  (void)f; (void)r; (void)x_star; (void)dl_dx; (void)dl_dmu; (void)dl_dL; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return NPGA_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Device helpers: deterministic wavefront/workgroup reductions and the
+// exact projection onto F = {x >= 0, 1^T x = 1, mu^T x >= r} (paper Sec. 3.1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "npga_internal.h"
+
+namespace npga {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Workgroup-wide sum of K doubles for a 256-thread workgroup.  Every thread
+// receives bitwise identical totals: the XOR butterfly pairs commutative
+// additions, and the four wave totals are combined in a fixed order.  Two
+// LDS buffers alternate so a single barrier per call suffices.
+template <int K>
+struct BlockReducer {
+  double *buf;  // shared: 2 * 4 * K doubles
+  int parity;
+
+  __device__ __forceinline__ void sum(double (&a)[K]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = wave_sum_f64(a[k]);
+    double *b = buf + parity * (4 * K);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) b[wave * K + k] = a[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = ((b[k] + b[K + k]) + b[2 * K + k]) + b[3 * K + k];
+    parity ^= 1;
+  }
+};
+
+// Sums over the support S = {i : v_i + nu mu_i > tau} of one pass.
+struct PassSums {
+  double c, sv, sm, smm, smv;
+};
+
+// Projection of the n-vector held in registers (thread t owns entries
+// i = t + 256 j, j < E; invalid entries carry v = -1e300, mu = 0).
+//
+// Pi_F(v) = Pi_Delta(v + nu mu) for the nu >= 0 that satisfies the
+// complementarity of the return constraint (eq. projF-dualpath), with
+// Pi_Delta(w)_i = max(w_i - tau, 0) and sum_i max(w_i - tau, 0) = 1
+// (eq. simplex-tau / simplex-proj).
+//
+// tau(nu) is found without sorting by the monotone Newton (Michelot)
+// iteration tau <- (sum_{w_i > tau} w_i - 1) / #{w_i > tau}: from a point
+// left of the root it increases to the root in finitely many steps; from a
+// point right of it the first step lands left of it.  The loop ends when
+// the recomputed tau repeats bitwise, which happens exactly when the
+// support is unchanged, so the final tau is the exact threshold of that
+// support.  A correct guess costs one pass.
+//
+// The outer search solves phi(nu) = mu^T x(nu) = r.  phi is nondecreasing
+// and affine between support changes: on a fixed support S,
+// phi(nu) = sum_S mu v + nu sum_S mu^2 - tau(nu) sum_S mu with
+// tau(nu) = (sum_S v + nu sum_S mu - 1)/|S|, so a Newton step from any
+// evaluated point is exact if the support does not change.  Newton steps
+// are safeguarded by the bracket lo < nu* <= hi (phi(lo) < r <= phi(hi))
+// and replaced by bisection (or doubling while hi is unknown) when they
+// leave it.  A positive nu with |phi(nu) - r| <= tolphi satisfies the KKT
+// conditions of the projection, so the search can start from the previous
+// call's nu without first evaluating nu = 0.
+struct ProjResult {
+  double nu, tau;
+  int32_t passes;
+  int32_t flags;  // bit 0: pass cap hit, bit 1: bracket failure
+};
+
+template <int E>
+__device__ __forceinline__ PassSums proj_pass(const double (&v)[E], const double (&mu)[E], double nu,
+                                              double tau, BlockReducer<5> &red) {
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const double w = fma(nu, mu[j], v[j]);
+    const double m = (w > tau) ? 1.0 : 0.0;
+    a[0] += m;
+    a[1] = fma(m, v[j], a[1]);
+    a[2] = fma(m, mu[j], a[2]);
+    a[3] = fma(m * mu[j], mu[j], a[3]);
+    a[4] = fma(m * mu[j], v[j], a[4]);
+  }
+  red.sum(a);
+  return PassSums{a[0], a[1], a[2], a[3], a[4]};
+}
+
+__device__ __forceinline__ double tau_of(const PassSums &s, double nu) {
+  return (fma(nu, s.sm, s.sv) - 1.0) / s.c;
+}
+
+template <int E>
+__device__ __forceinline__ double simplex_tau(const double (&v)[E], const double (&mu)[E], double nu,
+                                              double guess, PassSums &s, BlockReducer<5> &red,
+                                              int &passes, int &flags) {
+  double tau = guess;
+  for (int it = 0; it < 96; ++it) {
+    s = proj_pass<E>(v, mu, nu, tau, red);
+    ++passes;
+    if (s.c < 0.5) {  // guess at or above max w: restart from the full set
+      tau = -1.0e300;
+      continue;
+    }
+    const double tn = tau_of(s, nu);
+    if (tn == tau) return tau;
+    tau = tn;
+  }
+  flags |= 1;
+  return tau;
+}
+
+template <int E>
+__device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r, double tolphi,
+                                double nu_warm, double tau_warm, BlockReducer<5> &red) {
+  ProjResult out{0.0, 0.0, 0, 0};
+  int passes = 0, flags = 0;
+  PassSums s;
+  const double INF = 1.0e308;
+  double nu = (nu_warm > 0.0) ? nu_warm : 0.0;
+  double tau = simplex_tau<E>(v, mu, nu, tau_warm, s, red, passes, flags);
+  double phi = fma(nu, s.smm, s.smv) - tau * s.sm;
+  bool done = false;
+  double lo = 0.0, hi = INF, tau_hi = 0.0;
+  bool lo_known = false;
+  if (nu == 0.0) {
+    if (phi >= r - tolphi) done = true;
+    lo_known = true;
+  } else {
+    if (fabs(phi - r) <= tolphi) {
+      done = true;
+    } else if (phi < r) {
+      lo = nu;
+      lo_known = true;
+    } else {
+      hi = nu;
+      tau_hi = tau;
+    }
+  }
+  for (int it = 0; it < 200 && !done; ++it) {
+    const double slope = s.smm - s.sm * (s.sm / s.c);
+    const double nun = (slope > 0.0) ? nu + (r - phi) / slope : -1.0;
+    double cand;
+    if (slope > 0.0 && nun > lo && nun < hi) {
+      cand = nun;
+    } else if (!lo_known) {
+      cand = 0.0;
+    } else if (hi < INF) {
+      cand = 0.5 * (lo + hi);
+    } else {
+      cand = (nu > 0.0) ? 2.0 * nu : 1.0;
+      if (cand > 1.0e300) {
+        flags |= 2;
+        break;
+      }
+    }
+    // affine prediction of tau(cand) from the current support
+    const double guess = tau_of(s, cand);
+    tau = simplex_tau<E>(v, mu, cand, guess, s, red, passes, flags);
+    nu = cand;
+    phi = fma(nu, s.smm, s.smv) - tau * s.sm;
+    if (nu == 0.0) {
+      lo_known = true;
+      if (phi >= r - tolphi) {
+        done = true;
+        break;
+      }
+      lo = 0.0;
+    } else if (fabs(phi - r) <= tolphi) {
+      done = true;
+      break;
+    } else if (phi < r) {
+      lo = nu;
+      lo_known = true;
+    } else {
+      hi = nu;
+      tau_hi = tau;
+    }
+    if (lo_known && hi < INF && (hi - lo) <= 4.0e-16 * hi) {
+      // the bracket has collapsed to rounding: take the feasible end
+      nu = hi;
+      tau = tau_hi;
+      done = true;
+      break;
+    }
+  }
+  if (!done && hi < INF) {  // iteration cap: return the feasible end
+    nu = hi;
+    tau = tau_hi;
+    flags |= 1;
+  } else if (!done) {
+    flags |= 2;
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = fmax(fma(nu, mu[j], v[j]) - tau, 0.0);
+  out.nu = nu;
+  out.tau = tau;
+  out.passes = passes;
+  out.flags = flags;
+  return out;
+}
+
+}  // namespace npga

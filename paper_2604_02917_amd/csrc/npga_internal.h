@@ -1,0 +1,150 @@
+// Internal declarations shared by the host orchestration (npga_api.cpp) and
+// the HIP kernels (*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "npga.h"
+
+namespace npga {
+
+constexpr int kThreads = 256;               // workgroup size of the solver kernels
+constexpr int kMaxSlots = NPGA_MAX_N / 256; // per-thread entries of an n-vector
+
+// Termination codes kept in DevState::done.
+enum DoneCode : int32_t {
+  kRunning = 0,
+  kConverged = 1,
+  kMaxIter = 2,
+  kNumeric = 3,
+  kBracket = 4,
+};
+
+// Tail modes of the reduce-and-update kernel.
+enum TailMode : int32_t {
+  kTailNpga = 0,   // NPGA step (Algorithm 1) with the periodic stopping test
+  kTailPower = 1,  // power-method step
+  kTailGrad = 2,   // gradient and objective only (no update)
+};
+
+// Solver state resident in the workspace.  Written only by the single
+// "tail" workgroup of a launch and read by every workgroup of later
+// launches, so kernel boundaries order all accesses.
+struct alignas(256) DevState {
+  int32_t done;         // DoneCode
+  int32_t iter;         // k: index of the current iterate x^k
+  int32_t stop_iter;    // k at which the stopping test passed in the main phase
+  int32_t max_iter;     // last iteration index allowed in the current phase
+  uint32_t ticket;      // last-workgroup counter of the reduce kernel
+  int32_t check_every;
+  int32_t restart;      // adaptive restart on/off in the current phase
+  int32_t proj_flags;   // bit 0: a projection hit its pass cap; bit 1: bracket failure
+  double t;             // FISTA t_k
+  double beta;          // beta_{k-1} (0 at k = 0)
+  double alpha;         // fixed step
+  double gamma;         // ridge
+  double r;             // target return
+  double tol;           // stopping tolerance of the current phase
+  double tolphi;        // absolute tolerance of |mu^T x - r| in the dual search
+  double nu, tau;       // warm start of the step projection
+  double nu_c, tau_c;   // warm start of the stopping-test projection
+  double residual;      // last stopping residual
+  double stop_residual; // residual when the main test passed
+  double usq;           // ||L_eff^T x^k||^2 from the last sweep (float64 sum)
+  double objective;     // f(x^k) at the last test
+  double rho2;          // power method: ||L_eff^T u||^2 (Rayleigh value)
+  double mu_max, mu_absmax;
+  double n_nonfinite;   // count of non-finite inputs seen by the prepare kernel
+  int32_t n_restarts;
+  int32_t support;
+  double lambda_kkt, nu_kkt; // multipliers recovered from the stopping-test projection
+  double lipschitz;     // estimated L_f
+  double pad[3];
+};
+
+// Host-visible status block copied back once per chunk of iterations.
+struct alignas(64) HostStatus {
+  int32_t done;
+  int32_t iter;
+  int32_t stop_iter;
+  int32_t proj_flags;
+  double residual;
+  double mu_max;
+  double n_nonfinite;
+  double rho2;
+};
+
+// Everything a solver kernel needs, passed by value.
+struct SolveArgs {
+  const float *L;      // n x cols, leading dim ld (float32)
+  int64_t ld;
+  int64_t n;
+  int64_t cols;
+  const double *mu;    // n
+  float *xs;           // sweep input, float32, padded to 256 * slots with zeros
+  double *xbuf0;       // iterate ping-pong buffers (float64, n)
+  double *xbuf1;
+  double *gbuf0;       // gradient ping-pong buffers (float64, n)
+  double *gbuf1;
+  float *partials;     // sweep partial sums, [grid][ldp]
+  double *usq_part;    // per-workgroup partial ||L^T x||^2, [grid]
+  int64_t ldp;         // leading dimension of partials (>= 256 * slots)
+  int32_t sweep_grid;  // number of workgroups of the sweep launch
+  int32_t mode;        // TailMode
+  DevState *st;
+  // refinement anchor (all null outside the refinement phase): the sweep
+  // runs on d = x - xa and adds the float64 anchor terms
+  const double *xa;    // anchor x_a (n)
+  const double *ga;    // 2 L (L^T x_a), float64 products (n)
+  const double *ua;    // L^T x_a, float64 products (cols; factor path only)
+};
+
+// Workspace carving for a solve.
+struct SolveLayout {
+  size_t off_state, off_status_dev, off_xs, off_x0, off_x1, off_g0, off_g1, off_part, off_usq,
+      off_sigma, off_vecs, off_xa, off_ga, off_ua, total;
+  int32_t slots;
+  int32_t sweep_grid;
+  int64_t ldp;
+};
+
+int slots_for(int64_t n);
+SolveLayout solve_layout(int64_t n, int64_t cols, int path);
+int sweep_grid_for(int64_t cols);
+
+// ---- launchers (defined in the .hip files; return hipError_t as int) ----
+int launch_prepare(const SolveArgs &a, hipStream_t s);
+int launch_set_vector(double *dst, const float *src32, const double *src64, int64_t n, double fill,
+                      float *xs, hipStream_t s);
+int launch_random_unit(double *u, float *xs, int64_t n, uint64_t seed, hipStream_t s);
+int launch_sweep(const SolveArgs &a, int slots, hipStream_t s);
+int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s);
+int launch_project_init(const SolveArgs &a, int slots, int use_x0, hipStream_t s);
+int launch_project_only(const double *v, const double *mu, int64_t n, double *x, DevState *st,
+                        int slots, hipStream_t s);
+int launch_finalize(const SolveArgs &a, float *x_out, int slots, hipStream_t s);
+int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter, int32_t restart,
+                 hipStream_t s);
+int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
+int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);
+
+// Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.
+int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
+                hipStream_t s);
+int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int slots,
+                     hipStream_t s);
+
+// Float64 anchor gradient for the refinement phase.
+int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
+                            double *part, int slots, hipStream_t s);
+int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s);
+
+// Factor build.
+int launch_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *L, int64_t ldl,
+                        double *mu_out, double *part, int grid, double *nonfinite,
+                        hipStream_t s);
+
+}  // namespace npga

@@ -1,0 +1,496 @@
+// NPGA solver kernels for gfx950 (paper Sec. 3.1, Algorithm 1).
+//
+// One NPGA iteration on the factor path is two launches:
+//   k_sweep        : every wavefront streams whole columns of L_eff and
+//                    computes u_t = L_{:,t}^T x (wavefront sum), accumulates
+//                    ||u||^2 and the partial gradient sum_t L_{:,t} u_t in
+//                    registers; each workgroup writes one partial n-vector.
+//                    L_eff is read from HBM exactly once per iteration.
+//   k_reduce_tail  : row blocks sum the partial vectors in a fixed order
+//                    (deterministic), giving g_k = 2 L(L^T x_k) + 2 gamma x_k;
+//                    the last workgroup to finish (atomic ticket, no spin
+//                    wait) runs the serial tail: stopping test, momentum
+//                    extrapolation, gradient step and the exact projection.
+//
+// The sweep evaluates the gradient at the iterate x_k rather than at the
+// extrapolated point y_k: the gradient is affine in x, so
+//   grad f(y_k) = g_k + beta_{k-1} (g_k - g_{k-1}),  y_k = x_k + beta_{k-1}(x_k - x_{k-1}),
+// which is Algorithm 1's gradient at y_k, and the stopping test of Sec. 3.1
+// (which needs grad f(x_k)) costs one extra projection and no extra sweep.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "npga_device.h"
+#include "npga_internal.h"
+#include "npga_tail.h"
+
+namespace npga {
+
+// --------------------------------------------------------------------------
+// small kernels
+// --------------------------------------------------------------------------
+
+// Statistics of mu and a finiteness check of mu, one workgroup.
+__global__ __launch_bounds__(256) void k_prepare(const double *mu, int64_t n, DevState *st) {
+  __shared__ double sh[2 * 4 * 5];
+  double mx = -1.0e308, amx = 0.0, bad = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double m = mu[i];
+    if (!isfinite(m)) {
+      bad += 1.0;
+    } else {
+      mx = fmax(mx, m);
+      amx = fmax(amx, fabs(m));
+    }
+  }
+  // max reductions by butterfly, then across waves
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    amx = fmax(amx, __shfl_xor(amx, off, 64));
+    bad += __shfl_xor(bad, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wave * 3 + 0] = mx;
+    sh[wave * 3 + 1] = amx;
+    sh[wave * 3 + 2] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = sh[0], b = sh[1], c = sh[2];
+    for (int w = 1; w < 4; ++w) {
+      a = fmax(a, sh[w * 3 + 0]);
+      b = fmax(b, sh[w * 3 + 1]);
+      c += sh[w * 3 + 2];
+    }
+    st->mu_max = a;
+    st->mu_absmax = b;
+    st->n_nonfinite = c;
+  }
+}
+
+// dst = src (float32 or float64) or fill; also the padded float32 copy xs.
+__global__ __launch_bounds__(256) void k_set_vector(double *dst, const float *s32, const double *s64,
+                                                    int64_t n, double fill, float *xs, int64_t npad) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npad; i += (int64_t)gridDim.x * 256) {
+    if (i < n) {
+      const double v = s32 ? (double)s32[i] : (s64 ? s64[i] : fill);
+      dst[i] = v;
+      if (xs) xs[i] = (float)v;
+    } else if (xs) {
+      xs[i] = 0.0f;
+    }
+  }
+}
+
+// splitmix64 finaliser (Steele, Lea and Flood, 2014) as a counter hash.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// u = r / ||r||, r_i ~ N(0, 1) by Box-Muller on hashed counters (power-method start).
+template <int E>
+__global__ __launch_bounds__(256) void k_random_unit(double *u, float *xs, int64_t n, uint64_t seed) {
+  __shared__ double sh[2 * 4 * 5];
+  BlockReducer<5> red{sh, 0};
+  double val[E];
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = threadIdx.x + 256 * j;
+    val[j] = 0.0;
+    if (i < n) {
+      const uint64_t h1 = mix64(seed * 0x100000001B3ull + 2 * (uint64_t)i);
+      const uint64_t h2 = mix64(seed * 0x100000001B3ull + 2 * (uint64_t)i + 1);
+      const double a = ((double)(h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+      const double b = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
+      val[j] = sqrt(-2.0 * log(a)) * cos(6.283185307179586 * b);
+      acc[0] = fma(val[j], val[j], acc[0]);
+    }
+  }
+  red.sum(acc);
+  const double inv = 1.0 / sqrt(acc[0]);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = threadIdx.x + 256 * j;
+    if (i < n) {
+      u[i] = val[j] * inv;
+      xs[i] = (float)(val[j] * inv);
+    }
+  }
+}
+
+__global__ void k_set_tolphi(DevState *st, double proj_tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->tolphi = proj_tol * fmax(fabs(st->r), st->mu_absmax);
+}
+
+// alpha = 1 / (safety * L_f_hat), L_f_hat = 2 (rho^2 + gamma) (Sec. 3.1 "Fixed step").
+__global__ void k_set_alpha(DevState *st, double safety) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double lf = 2.0 * (st->rho2 + st->gamma);
+    st->lipschitz = lf;
+    st->alpha = (lf > 0.0) ? 1.0 / (safety * lf) : 1.0;
+  }
+}
+
+// Start of the refinement phase: momentum restarts from x_k (t = 1, beta = 0).
+__global__ void k_phase_reset(DevState *st, double tol, int32_t max_iter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->done = kRunning;
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->restart = 1;
+    st->t = 1.0;
+    st->beta = 0.0;
+  }
+}
+
+__global__ void k_phase(DevState *st, double tol, int32_t max_iter, int32_t restart) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->done = kRunning;
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->restart = restart;
+  }
+}
+
+// --------------------------------------------------------------------------
+// fused gradient sweep
+// --------------------------------------------------------------------------
+template <int E>
+__global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
+  if (a.st->done != kRunning) return;
+  __shared__ f4 sh[4 * 64 * E];
+  __shared__ double shu[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = a.n;
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+  const bool ragged = (n & 3) != 0;
+
+  f4 xr[E], g[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    xr[j] = *reinterpret_cast<const f4 *>(a.xs + 4 * lane + 256 * j);
+    g[j] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  double usq = 0.0;
+
+  auto load = [&](f4(&c)[E], int64_t col) {
+    const f4 *p = reinterpret_cast<const f4 *>(a.L + col * a.ld) + lane;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t row0 = 4 * lane + 256 * j;
+      c[j] = (row0 < n) ? __builtin_nontemporal_load(p + 64 * j) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (ragged) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t row0 = 4 * lane + 256 * j;
+        if (row0 + 1 >= n) c[j].y = 0.f;
+        if (row0 + 2 >= n) c[j].z = 0.f;
+        if (row0 + 3 >= n) c[j].w = 0.f;
+      }
+    }
+  };
+  int64_t col_cur = 0;
+  auto process = [&](const f4(&c)[E]) {
+    float d = 0.f;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      d = fmaf(c[j].x, xr[j].x, d);
+      d = fmaf(c[j].y, xr[j].y, d);
+      d = fmaf(c[j].z, xr[j].z, d);
+      d = fmaf(c[j].w, xr[j].w, d);
+    }
+    d = wave_sum_f32(d);
+    // with a refinement anchor, u_t = (L^T x_a)_t + (L^T d)_t
+    const double ut = a.ua ? a.ua[col_cur] + (double)d : (double)d;
+    usq = fma(ut, ut, usq);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      g[j].x = fmaf(c[j].x, d, g[j].x);
+      g[j].y = fmaf(c[j].y, d, g[j].y);
+      g[j].z = fmaf(c[j].z, d, g[j].z);
+      g[j].w = fmaf(c[j].w, d, g[j].w);
+    }
+  };
+
+  f4 c0[E], c1[E];
+  int64_t col = gw;
+  if (col < a.cols) load(c0, col);
+  while (col < a.cols) {
+    const int64_t col1 = col + W;
+    if (col1 < a.cols) load(c1, col1);
+    col_cur = col;
+    process(c0);
+    if (col1 >= a.cols) break;
+    const int64_t col2 = col1 + W;
+    if (col2 < a.cols) load(c0, col2);
+    col_cur = col1;
+    process(c1);
+    col = col2;
+  }
+
+  // combine the four wavefronts in a fixed order
+#pragma unroll
+  for (int j = 0; j < E; ++j) sh[wave * 64 * E + lane + 64 * j] = g[j];
+  if (lane == 0) shu[wave] = usq;
+  __syncthreads();
+  float *out = a.partials + (int64_t)blockIdx.x * a.ldp;
+  for (int q = threadIdx.x; q < 64 * E; q += 256) {
+    f4 s = sh[q];
+    s += sh[64 * E + q];
+    s += sh[2 * 64 * E + q];
+    s += sh[3 * 64 * E + q];
+    *reinterpret_cast<f4 *>(out + 4 * q) = s;
+  }
+  if (threadIdx.x == 0) a.usq_part[blockIdx.x] = ((shu[0] + shu[1]) + shu[2]) + shu[3];
+}
+
+// Row blocks of 64 sum the sweep partials; the last workgroup runs the tail.
+template <int E>
+__global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  __shared__ double red[4][64];
+  __shared__ double redbuf[2 * 4 * 5];
+  __shared__ uint32_t ticket_sh;
+  const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + r;
+  const int G = a.sweep_grid;
+  double s = 0.0;
+  if (i < a.n) {
+    const float *p = a.partials + i;
+#pragma unroll 16
+    for (int w = q; w < G; w += 4) s += (double)p[(int64_t)w * a.ldp];
+  }
+  red[q][r] = s;
+  __syncthreads();
+  const int cur = (a.mode == kTailNpga) ? (st->iter & 1) : 0;
+  if (q == 0 && i < a.n) {
+    const double tot = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+    if (a.mode == kTailNpga) {
+      const double *xk = cur ? a.xbuf1 : a.xbuf0;
+      double *gk = cur ? a.gbuf1 : a.gbuf0;
+      gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
+    } else if (a.mode == kTailGrad) {
+      a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.xbuf0[i];
+    } else {
+      a.gbuf0[i] = tot;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) ticket_sh = atomicAdd(&st->ticket, 1u);
+  __syncthreads();
+  if (ticket_sh != gridDim.x - 1) return;
+  __threadfence();
+  // last workgroup: total ||L^T x||^2 (one partial per thread, then the
+  // fixed-order workgroup sum), then the tail
+  double usq;
+  {
+    BlockReducer<5> red5{redbuf, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int w = threadIdx.x; w < G; w += 256) acc[0] += a.usq_part[w];
+    red5.sum(acc);
+    usq = acc[0];
+  }
+  __syncthreads();
+  if (a.mode == kTailNpga)
+    tail_npga<E>(a, usq, redbuf);
+  else if (a.mode == kTailPower)
+    tail_power<E>(a, usq, redbuf);
+  else
+    tail_grad<E>(a, usq, redbuf);
+  if (threadIdx.x == 0) st->ticket = 0u;
+}
+
+// x0 = Pi_F(xbuf0) (Algorithm 1 requires x^0 in F); initialises the iteration.
+template <int E>
+__global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
+  DevState *st = a.st;
+  __shared__ double redbuf[2 * 4 * 5];
+  BlockReducer<5> red{redbuf, 0};
+  const int tid = threadIdx.x;
+  double mu[E], v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    mu[j] = (i < a.n) ? a.mu[i] : 0.0;
+    v[j] = (i < a.n) ? a.xbuf0[i] : -1.0e300;
+  }
+  const ProjResult pr = project_F<E>(v, mu, st->r, st->tolphi, 0.0, -1.0e300, red);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    if (i < a.n) {
+      a.xbuf0[i] = v[j];
+      a.xbuf1[i] = v[j];
+      a.gbuf0[i] = 0.0;
+      a.gbuf1[i] = 0.0;
+      a.xs[i] = (float)v[j];
+    }
+  }
+  if (tid == 0) {
+    st->iter = 0;
+    st->t = 1.0;
+    st->beta = 0.0;
+    st->nu = pr.nu;
+    st->tau = pr.tau;
+    st->nu_c = pr.nu;
+    st->tau_c = pr.tau;
+    st->proj_flags |= pr.flags;
+    st->ticket = 0u;
+    if (pr.flags & 2) st->done = kBracket;
+  }
+}
+
+// Standalone projection (npga_project entry point).
+template <int E>
+__global__ __launch_bounds__(256) void k_project_only(const double *vin, const double *muin, int64_t n,
+                                                      double *xout, DevState *st) {
+  __shared__ double redbuf[2 * 4 * 5];
+  BlockReducer<5> red{redbuf, 0};
+  const int tid = threadIdx.x;
+  double mu[E], v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    mu[j] = (i < n) ? muin[i] : 0.0;
+    v[j] = (i < n) ? vin[i] : -1.0e300;
+  }
+  const ProjResult pr = project_F<E>(v, mu, st->r, st->tolphi, 0.0, -1.0e300, red);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    if (i < n) xout[i] = v[j];
+  }
+  if (tid == 0) {
+    st->nu = pr.nu;
+    st->tau = pr.tau;
+    st->proj_flags = pr.flags;
+    st->iter = pr.passes;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(SolveArgs a, float *x_out) {
+  const DevState *st = a.st;
+  const double *x = (st->iter & 1) ? a.xbuf1 : a.xbuf0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256)
+    x_out[i] = (float)x[i];
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+#define NPGA_SLOT_SWITCH(slots, CALL)                                 \
+  switch (slots) {                                                   \
+    case 1: CALL(1); break;                                          \
+    case 2: CALL(2); break;                                          \
+    case 4: CALL(4); break;                                          \
+    case 8: CALL(8); break;                                          \
+    case 12: CALL(12); break;                                        \
+    case 16: CALL(16); break;                                        \
+    case 22: CALL(22); break;                                        \
+    case 28: CALL(28); break;                                        \
+    case 32: CALL(32); break;                                        \
+    default: return (int)hipErrorInvalidValue;                      \
+  }
+
+int slots_for(int64_t n) {
+  const int64_t need = (n + 255) / 256;
+  static const int buckets[] = {1, 2, 4, 8, 12, 16, 22, 28, 32};
+  for (int b : buckets)
+    if (need <= b) return b;
+  return -1;
+}
+
+int launch_prepare(const SolveArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, s, a.mu, a.n, a.st);
+  return (int)hipGetLastError();
+}
+
+int launch_set_vector(double *dst, const float *src32, const double *src64, int64_t n, double fill,
+                      float *xs, hipStream_t s) {
+  const int slots = slots_for(n);
+  const int64_t npad = xs ? (int64_t)256 * slots : n;  // xs holds 256 * slots floats
+  const int grid = (int)((npad + 255) / 256);
+  hipLaunchKernelGGL(k_set_vector, dim3(grid), dim3(256), 0, s, dst, src32, src64, n, fill, xs,
+                     npad);
+  return (int)hipGetLastError();
+}
+
+int launch_random_unit(double *u, float *xs, int64_t n, uint64_t seed, hipStream_t s) {
+  const int slots = slots_for(n);
+#define CALL(E) hipLaunchKernelGGL(k_random_unit<E>, dim3(1), dim3(256), 0, s, u, xs, n, seed)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_sweep<E>, dim3(a.sweep_grid), dim3(256), 0, s, a)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
+  const int grid = (int)((a.n + 63) / 64);
+#define CALL(E) hipLaunchKernelGGL(k_reduce_tail<E>, dim3(grid), dim3(256), 0, s, a)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_project_init(const SolveArgs &a, int slots, int /*use_x0*/, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_project_init<E>, dim3(1), dim3(256), 0, s, a)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_project_only(const double *v, const double *mu, int64_t n, double *x, DevState *st,
+                        int slots, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_project_only<E>, dim3(1), dim3(256), 0, s, v, mu, n, x, st)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_finalize(const SolveArgs &a, float *x_out, int /*slots*/, hipStream_t s) {
+  const int grid = (int)((a.n + 255) / 256);
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(256), 0, s, a, x_out);
+  return (int)hipGetLastError();
+}
+
+int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_reset, dim3(1), dim3(64), 0, s, st, tol, max_iter);
+  return (int)hipGetLastError();
+}
+
+int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_tolphi, dim3(1), dim3(64), 0, s, st, proj_tol);
+  return (int)hipGetLastError();
+}
+
+int launch_set_alpha(DevState *st, double step_safety, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_alpha, dim3(1), dim3(64), 0, s, st, step_safety);
+  return (int)hipGetLastError();
+}
+
+int launch_phase(DevState *st, int32_t /*phase_kind*/, double tol, int32_t max_iter, int32_t restart,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_phase, dim3(1), dim3(64), 0, s, st, tol, max_iter, restart);
+  return (int)hipGetLastError();
+}
+
+}  // namespace npga

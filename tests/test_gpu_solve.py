@@ -1,0 +1,155 @@
+"""GPU NPGA solves (Algorithm 1 + refinement) against the exact FP64
+minimiser of eq. mv computed by the oracle.
+
+Bar (float32 storage): relative objective error <= 1e-6 (objective of
+the GPU x re-evaluated in float64 by the oracle, and the GPU's own
+reported objective), ||x - x*||_inf <= 1e-5, x >= 0 exactly,
+|1^T x - 1| <= 1e-6, mu^T x >= r - 1e-6 max(1, |r|).
+
+The GPU side builds L and mu from the float32 returns with
+npga_build_factor; the oracle builds them in float64 from the same
+float32 returns.  The two factors differ by float32 rounding of L
+(relative 6e-8), far inside the bar.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import gen
+from oracle import factor as ofactor
+from oracle import qp
+from oracle.reference import exact_mv_factor, factor_objective
+from tests.gpu_util import banner, spec_with, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def npga():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_02917_amd as p
+    return p
+
+
+def _check_parity(x, info, L, mu, r, gamma, ref, tag):
+    x64 = x.astype(np.float64)
+    f_gpu = factor_objective(L, gamma, x64)
+    f_ref = ref["f"]
+    assert x.min() >= 0.0, tag
+    assert abs(x64.sum() - 1.0) <= 1e-6, tag
+    assert mu @ x64 >= r - 1e-6 * max(1.0, abs(r)), tag
+    assert abs(f_gpu - f_ref) <= 1e-6 * abs(f_ref), (tag, f_gpu, f_ref)
+    assert abs(info["objective"] - f_ref) <= 1e-6 * abs(f_ref), (tag, info["objective"], f_ref)
+    assert np.abs(x64 - ref["x"]).max() <= 1e-5, (tag, np.abs(x64 - ref["x"]).max())
+
+
+def _case(spec, q=None, gamma=0.0):
+    Rt = gen.returns_TxN(spec)
+    r = gen.target_return(spec, Rt) if q is None else None
+    mu_ref, L_ref = ofactor.build_factor(Rt.T)
+    if q is not None:
+        r = float(np.quantile(Rt.astype(np.float64).mean(axis=0), q))
+        if q == 1.0:  # stay clear of max(mu) by more than the summation-order rounding
+            r -= 1e-9 * abs(r)
+    ref = exact_mv_factor(L_ref, gamma, mu_ref, r)
+    return Rt, r, mu_ref, L_ref, ref
+
+
+@pytest.mark.parametrize("path", ["gemv", "syrk"])
+def test_c1_parity(npga, path):
+    spec = gen.SPECS["c1"]
+    banner(f"c1 parity path={path}")
+    Rt, r, mu_ref, L_ref, ref = _case(spec)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, path=path)
+    assert info["status"] == 0 and info["refined"] == 1, info
+    _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, 0.0, ref, f"c1-{path}")
+    assert info["residual"] <= 1e-6
+
+
+@pytest.mark.parametrize("n,T,q,gamma,path", [
+    (5, 40, 0.5, 0.0, "gemv"),
+    (63, 500, 0.9, 0.0, "gemv"),
+    (130, 700, 0.2, 0.0, "syrk"),
+    (257, 2000, 0.6, 0.0, "gemv"),
+    (257, 2000, 0.6, 0.0, "syrk"),
+    (300, 200, 0.6, 1e-4, "gemv"),   # T < n: ridge makes the model strongly convex
+    (1000, 6000, 0.6, 0.0, "gemv"),
+    (1000, 6000, 0.0, 0.0, "gemv"),  # return constraint slack
+    (777, 3000, 1.0, 0.0, "gemv"),   # r = max mu: a single feasible vertex
+])
+def test_parity_shapes(npga, n, T, q, gamma, path):
+    banner(f"parity n={n} T={T} q={q} gamma={gamma} path={path}")
+    spec = spec_with("c2", n, T, seed=31 + n)
+    Rt, r, mu_ref, L_ref, ref = _case(spec, q=q)
+    if gamma:
+        gamma = gamma * float(np.trace(L_ref @ L_ref.T)) / n
+        ref = exact_mv_factor(L_ref, gamma, mu_ref, r)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, gamma=gamma, path=path)
+    assert info["status"] == 0, info
+    _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, gamma, ref, f"{n}x{T}")
+
+
+def test_certificate_and_multipliers(npga):
+    spec = spec_with("c2", 400, 3000, seed=9)
+    Rt, r, mu_ref, L_ref, ref = _case(spec, q=0.7)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, refine_tol=1e-11)
+    H = 2 * (L_ref @ L_ref.T)
+    xg = x.cpu().numpy().astype(np.float64)
+    # x is float32: the return slack is known to float32 rounding only
+    rep = qp.kkt_report(H, np.zeros(400), mu_ref, r, xg, act_tol=1e-6 * max(abs(r), np.abs(mu_ref).max()))
+    assert rep["support"] == int((ref["x"] > 0).sum())
+    assert rep["stat_support"] <= 1e-4 and rep["dual_offsupport"] >= -1e-4, rep
+    assert info["return_active"] == (ref["nu"] > 0)
+    assert abs(info["nu"] - ref["nu"]) <= 1e-3 * abs(ref["nu"]) + 1e-9
+    assert abs(info["lambda"] - ref["lam"]) <= 1e-3 * abs(ref["lam"])
+
+
+def test_deterministic(npga):
+    spec = spec_with("c2", 500, 4000, seed=12)
+    Rt = gen.returns_TxN(spec)
+    r = gen.target_return(spec, Rt)
+    L, mu = npga.build_factor(to_dev(Rt))
+    xa, ia = npga.solve(L, mu, r)
+    xb, ib = npga.solve(L, mu, r)
+    assert torch.equal(xa, xb)
+    assert ia["iters"] == ib["iters"] and ia["objective"] == ib["objective"]
+
+
+def test_errors(npga):
+    spec = gen.SPECS["c1"]
+    Rt = gen.returns_TxN(spec)
+    L, mu = npga.build_factor(to_dev(Rt))
+    with pytest.raises(npga.NpgaError) as e:
+        npga.solve(L, mu, float(mu.max().item()) + 1e-3)
+    assert e.value.code == 2
+    mu_bad = mu.clone()
+    mu_bad[3] = float("nan")
+    with pytest.raises(npga.NpgaError) as e:
+        npga.solve(L, mu_bad, 0.0)
+    assert e.value.code == 5
+    with pytest.raises(npga.NpgaError) as e:
+        npga.solve(L, mu, 0.0, tol=-1.0)
+    assert e.value.code == 1
+    # max_iter reached: NOT_CONVERGED, and the returned x still lies in F
+    r = gen.target_return(spec, Rt)
+    x, info = npga.solve(L, mu, r, max_iter=2, tol=1e-14)
+    assert info["status"] == 3
+    xn = x.cpu().numpy().astype(np.float64)
+    assert xn.min() >= 0 and abs(xn.sum() - 1) < 1e-6
+    assert mu.cpu().numpy() @ xn >= r - 1e-6 * max(1, abs(r))
+
+
+def test_warm_start_from_solution(npga):
+    spec = spec_with("c2", 300, 2000, seed=14)
+    Rt = gen.returns_TxN(spec)
+    r = gen.target_return(spec, Rt)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r)
+    x2, info2 = npga.solve(L, mu, r, x0=x)
+    assert info2["iters"] <= 5
+    assert torch.allclose(x, x2, atol=1e-6)
