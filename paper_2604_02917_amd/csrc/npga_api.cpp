@@ -399,22 +399,25 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   int refined = 0;
   int refine_iters = 0;
   if (main_done == npga::kConverged && o.refine && o.refine_max_iter > 0) {
-    // anchor x_a = x_k; float64 gradient there; iterate on d = x - x_a
+    // float64 gradient at the stopping point, then conjugate gradients on
+    // the identified face (the gradient is carried by linearity from there)
     char *base = static_cast<char *>(ws);
     double *xa = reinterpret_cast<double *>(base + lay.off_xa);
     double *ga = reinterpret_cast<double *>(base + lay.off_ga);
     double *ua = reinterpret_cast<double *>(base + lay.off_ua);
-    double *scratch = reinterpret_cast<double *>(base + lay.off_vecs);
+    double *vecs = reinterpret_cast<double *>(base + lay.off_vecs);
+    const int64_t npad = (int64_t)256 * slots;
     const double *xk = (after_main.iter & 1) ? c.a.xbuf1 : c.a.xbuf0;
     HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
     LAUNCHCHK(npga::launch_precise_gradient(c.a, xa, ua, ga, reinterpret_cast<double *>(c.a.partials),
                                             slots, stream));
-    LAUNCHCHK(npga::launch_set_vector(scratch, nullptr, nullptr, f->n, 0.0, c.a.xs, stream));
-    c.a.xa = xa;
     c.a.ga = ga;
-    c.a.ua = (path == NPGA_PATH_GEMV) ? ua : nullptr;
-    const int32_t cap = after_main.iter + o.refine_max_iter;
-    LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, cap, stream));
+    c.a.pvec = vecs;
+    c.a.fvec = vecs + npad;
+    c.a.gvec = vecs + 2 * npad;
+    c.a.mode = npga::kTailCG;
+    LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, stream));
+    LAUNCHCHK(npga::launch_cg_init(c.a, slots, stream));
     double rms = 0.0;
     const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
     e = run_phase(c, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
@@ -425,7 +428,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   const DevState &fin = pin[3];
-  refine_iters = (main_done == npga::kConverged) ? fin.iter - after_main.iter : 0;
+  refine_iters = (main_done == npga::kConverged && o.refine) ? fin.cg_iter : 0;
 
   int status = map_done(main_done);
   if (main_done == npga::kConverged && done != npga::kConverged && done != npga::kMaxIter)

@@ -50,6 +50,42 @@ struct BlockReducer {
   }
 };
 
+// Workgroup-wide minimum of (value, index) pairs; ties go to the smaller
+// index, so every thread receives the same pair.
+struct MinLoc {
+  double v;
+  int64_t i;
+};
+
+__device__ __forceinline__ MinLoc minloc_pick(MinLoc a, MinLoc b) {
+  if (b.v < a.v || (b.v == a.v && b.i < a.i)) return b;
+  return a;
+}
+
+__device__ __forceinline__ MinLoc block_minloc(MinLoc m, double *buf /* 8 doubles */, int64_t *ibuf /* 8 */,
+                                               int &parity) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    MinLoc o;
+    o.v = __shfl_xor(m.v, off, 64);
+    o.i = __shfl_xor(m.i, off, 64);
+    m = minloc_pick(m, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double *b = buf + parity * 4;
+  int64_t *bi = ibuf + parity * 4;
+  if (lane == 0) {
+    b[wave] = m.v;
+    bi[wave] = m.i;
+  }
+  __syncthreads();
+  MinLoc r{b[0], bi[0]};
+#pragma unroll
+  for (int w = 1; w < 4; ++w) r = minloc_pick(r, MinLoc{b[w], bi[w]});
+  parity ^= 1;
+  return r;
+}
+
 // Sums over the support S = {i : v_i + nu mu_i > tau} of one pass.
 struct PassSums {
   double c, sv, sm, smm, smv;

@@ -28,6 +28,7 @@ enum TailMode : int32_t {
   kTailNpga = 0,   // NPGA step (Algorithm 1) with the periodic stopping test
   kTailPower = 1,  // power-method step
   kTailGrad = 2,   // gradient and objective only (no update)
+  kTailCG = 3,     // refinement: conjugate gradient on the identified face
 };
 
 // Solver state resident in the workspace.  Written only by the single
@@ -62,7 +63,16 @@ struct alignas(256) DevState {
   int32_t support;
   double lambda_kkt, nu_kkt; // multipliers recovered from the stopping-test projection
   double lipschitz;     // estimated L_f
-  double pad[3];
+  // face conjugate-gradient refinement
+  double cg_rr;         // ||r_k||^2 of the projected gradient on the face
+  double cg_rr0;        // ||r||^2 at the start of the current CG cycle
+  int32_t cg_active;    // return constraint held as an equality on the face
+  int32_t cg_restart;   // next direction is the projected gradient
+  int32_t cg_iter;      // refinement iterations so far
+  int32_t cg_cycles;    // CG restarts (active-set changes)
+  int32_t cg_released;  // indices released from the zero set
+  int32_t cg_blocked;   // indices fixed at zero by a blocking step
+  double pad[2];
 };
 
 // Host-visible status block copied back once per chunk of iterations.
@@ -100,6 +110,10 @@ struct SolveArgs {
   const double *xa;    // anchor x_a (n)
   const double *ga;    // 2 L (L^T x_a), float64 products (n)
   const double *ua;    // L^T x_a, float64 products (cols; factor path only)
+  // face conjugate-gradient refinement vectors (float64, n)
+  double *pvec;        // search direction p
+  double *fvec;        // 1 where x_i is free on the face, 0 where x_i is fixed at 0
+  double *gvec;        // gradient maintained by linearity
 };
 
 // Workspace carving for a solve.
@@ -141,6 +155,7 @@ int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int sl
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
                             double *part, int slots, hipStream_t s);
 int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s);
+int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s);
 
 // Factor build.
 int launch_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *L, int64_t ldl,

@@ -262,6 +262,8 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
   if (st->done != kRunning) return;
   __shared__ double red[4][64];
   __shared__ double redbuf[2 * 4 * 5];
+  __shared__ double mbuf[8];
+  __shared__ int64_t ibuf[8];
   __shared__ uint32_t ticket_sh;
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
@@ -283,6 +285,8 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
       gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
     } else if (a.mode == kTailGrad) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.xbuf0[i];
+    } else if (a.mode == kTailCG) {
+      a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.pvec[i];
     } else {
       a.gbuf0[i] = tot;
     }
@@ -306,6 +310,8 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
   __syncthreads();
   if (a.mode == kTailNpga)
     tail_npga<E>(a, usq, redbuf);
+  else if (a.mode == kTailCG)
+    tail_cg<E>(a, redbuf, mbuf, ibuf);
   else if (a.mode == kTailPower)
     tail_power<E>(a, usq, redbuf);
   else
@@ -350,6 +356,60 @@ __global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
     st->proj_flags |= pr.flags;
     st->ticket = 0u;
     if (pr.flags & 2) st->done = kBracket;
+  }
+}
+
+// Start of the face-CG refinement: x = x_k (= the anchor), g = g_a + 2 gamma x,
+// free set = support of x, return constraint held if the last stopping-test
+// projection had nu > 0; p = projected gradient.
+template <int E>
+__global__ __launch_bounds__(256) void k_cg_init(SolveArgs a) {
+  DevState *st = a.st;
+  __shared__ double redbuf[2 * 4 * 5];
+  BlockReducer<5> red{redbuf, 0};
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  const double *x_p = (st->iter & 1) ? a.xbuf1 : a.xbuf0;
+  double x[E], g[E], mu[E], fr[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    const bool ok = i < n;
+    x[j] = ok ? x_p[i] : 0.0;
+    g[j] = ok ? a.ga[i] + 2.0 * st->gamma * x[j] : 0.0;
+    mu[j] = ok ? a.mu[i] : 0.0;
+    fr[j] = (ok && x[j] > 0.0) ? 1.0 : 0.0;
+  }
+  const bool active = st->nu_c > 0.0;
+  double lam, nu;
+  face_multipliers<E>(g, mu, fr, active, red, lam, nu);
+  double acc[5] = {0, 0, 0, 0, 0};
+  double p[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    p[j] = (fr[j] > 0.0) ? -(g[j] - lam - nu * mu[j]) : 0.0;
+    acc[0] = fma(p[j], p[j], acc[0]);
+  }
+  red.sum(acc);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    if (i < n) {
+      a.gvec[i] = g[j];
+      a.pvec[i] = p[j];
+      a.fvec[i] = fr[j];
+      a.xs[i] = (float)p[j];
+    }
+  }
+  if (tid == 0) {
+    st->cg_rr = acc[0];
+    st->cg_rr0 = acc[0];
+    st->cg_active = active ? 1 : 0;
+    st->cg_iter = 0;
+    st->cg_cycles = 0;
+    st->cg_released = 0;
+    st->cg_blocked = 0;
+    st->ticket = 0u;
   }
 }
 
@@ -453,6 +513,13 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
 
 int launch_project_init(const SolveArgs &a, int slots, int /*use_x0*/, hipStream_t s) {
 #define CALL(E) hipLaunchKernelGGL(k_project_init<E>, dim3(1), dim3(256), 0, s, a)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_cg_init<E>, dim3(1), dim3(256), 0, s, a)
   NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
   return (int)hipGetLastError();

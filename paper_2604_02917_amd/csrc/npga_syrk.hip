@@ -166,6 +166,8 @@ __global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__r
   DevState *st = a.st;
   if (st->done != kRunning) return;
   __shared__ double redbuf[2 * 4 * 5];
+  __shared__ double mbuf[8];
+  __shared__ int64_t ibuf[8];
   __shared__ uint32_t ticket_sh;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -178,6 +180,7 @@ __global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__r
   const int cur = (a.mode == kTailNpga) ? (st->iter & 1) : 0;
   const double *xk = cur ? a.xbuf1 : a.xbuf0;
   double *gk = (a.mode == kTailNpga) ? (cur ? a.gbuf1 : a.gbuf0) : a.gbuf0;
+  const double *pv = a.pvec;
   for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < n; col += W) {
     const f4 *p = reinterpret_cast<const f4 *>(S + col * lds) + lane;
     float d = 0.f;
@@ -201,6 +204,8 @@ __global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__r
     if (lane == 0) {
       if (a.mode == kTailPower)
         gk[col] = (double)d;
+      else if (a.mode == kTailCG)
+        gk[col] = 2.0 * (double)d + 2.0 * st->gamma * pv[col];
       else
         gk[col] = 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col];
     }
@@ -213,6 +218,8 @@ __global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__r
   __threadfence();
   if (a.mode == kTailNpga)
     tail_npga<E>(a, -1.0, redbuf);
+  else if (a.mode == kTailCG)
+    tail_cg<E>(a, redbuf, mbuf, ibuf);
   else
     tail_power<E>(a, -1.0, redbuf);
   if (threadIdx.x == 0) st->ticket = 0u;

@@ -179,4 +179,231 @@ __device__ void tail_power(const SolveArgs &a, double usq_total, double *redbuf)
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Float64 KKT refinement by conjugate gradients on the identified face.
+//
+// After the NPGA stopping test the support S of x and the state of the
+// return constraint identify a face of F:
+//     {x : x_i = 0 (i fixed), 1^T x = 1, mu^T x = r (if held)}.
+// On that affine set f is a quadratic, minimised by conjugate gradients on
+// the projected gradient r = -(g - lam 1 - nu mu) restricted to the free
+// entries, where (lam, nu) are the least-squares multipliers of the free
+// entries of g (the projector onto the face's direction space).  Active-set
+// rules keep x in F and reach the KKT point of eq. mv:
+//   * a step that would make a free x_i negative stops at x_i = 0 and fixes i;
+//   * a step that would drop mu^T x below r stops there and holds the
+//     return constraint;
+//   * once the face problem is nearly solved, a fixed index with negative
+//     reduced cost g_i - lam - nu mu_i is freed, and a held return
+//     constraint with nu < 0 is released.
+// Every change of the face restarts CG from the projected gradient.  The
+// gradient is carried by linearity, g <- g + a H p, from a float64 anchor
+// gradient; H p comes from the float32 sweep on the search direction.  The
+// stopping test is the NPGA residual ||Pi_F(x - alpha g) - x|| of Sec. 3.1.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ void face_multipliers(const double (&g)[E], const double (&mu)[E],
+                                                 const double (&fr)[E], bool active, BlockReducer<5> &red,
+                                                 double &lam, double &nu) {
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    acc[0] += fr[j];
+    acc[1] = fma(fr[j], mu[j], acc[1]);
+    acc[2] = fma(fr[j] * mu[j], mu[j], acc[2]);
+    acc[3] = fma(fr[j], g[j], acc[3]);
+    acc[4] = fma(fr[j] * mu[j], g[j], acc[4]);
+  }
+  red.sum(acc);
+  const double c = acc[0], sm = acc[1], smm = acc[2], sg = acc[3], smg = acc[4];
+  lam = (c > 0.0) ? sg / c : 0.0;
+  nu = 0.0;
+  if (active && c > 1.5) {
+    const double det = c * smm - sm * sm;
+    if (det > 1e-30 * c * smm) {
+      lam = (smm * sg - sm * smg) / det;
+      nu = (c * smg - sm * sg) / det;
+    }
+  }
+}
+
+template <int E>
+__device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_t *ibuf) {
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  const int cur = st->iter & 1;
+  double *x_p = cur ? a.xbuf1 : a.xbuf0;
+  BlockReducer<5> red{redbuf, 0};
+  int mpar = 0;
+  const double INF = 1.0e308;
+
+  double x[E], g[E], p[E], hp[E], mu[E], fr[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    const bool ok = i < n;
+    x[j] = ok ? x_p[i] : 0.0;
+    g[j] = ok ? a.gvec[i] : 0.0;
+    p[j] = ok ? a.pvec[i] : 0.0;
+    hp[j] = ok ? a.gbuf0[i] : 0.0;
+    mu[j] = ok ? a.mu[i] : 0.0;
+    fr[j] = ok ? a.fvec[i] : 0.0;
+  }
+  bool active = st->cg_active != 0;
+  const double r = st->r;
+  const double rr = st->cg_rr;
+
+  // (1) step length along p, limited by x_i >= 0 and mu^T x >= r
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    acc[0] = fma(fr[j] * p[j], hp[j], acc[0]);
+    acc[1] = fma(mu[j], p[j], acc[1]);
+    acc[2] = fma(mu[j], x[j], acc[2]);
+  }
+  red.sum(acc);
+  const double php = acc[0], mp = acc[1], mx = acc[2];
+  double step = (php > 0.0 && rr > 0.0) ? rr / php : 0.0;
+  MinLoc m{INF, n};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (fr[j] > 0.0 && p[j] < 0.0) m = minloc_pick(m, MinLoc{x[j] / (-p[j]), (int64_t)(tid + 256 * j)});
+  }
+  m = block_minloc(m, mbuf, ibuf, mpar);
+  int block = 0;
+  if (m.v < step) {
+    step = m.v;
+    block = 1;
+  }
+  if (!active && mp < 0.0) {
+    const double sr = fmax(mx - r, 0.0) / (-mp);
+    if (sr < step) {
+      step = sr;
+      block = 2;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    x[j] = fma(step, p[j], x[j]);
+    g[j] = fma(step, hp[j], g[j]);
+    if (block == 1 && (int64_t)(tid + 256 * j) == m.i) {
+      x[j] = 0.0;
+      fr[j] = 0.0;
+    }
+    if (fr[j] == 0.0) x[j] = 0.0;
+  }
+  bool restart = block != 0;
+  if (block == 2) active = true;
+
+  // (2) multipliers, projected gradient, reduced costs of the fixed entries
+  double lam, nu;
+  face_multipliers<E>(g, mu, fr, active, red, lam, nu);
+  double rv[E];
+  MinLoc dm{INF, n};
+  double acc2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    const double d = g[j] - lam - nu * mu[j];
+    rv[j] = (fr[j] > 0.0) ? -d : 0.0;
+    acc2[0] = fma(rv[j], rv[j], acc2[0]);
+    acc2[1] = fma(g[j], g[j], acc2[1]);
+    if (i < n && fr[j] == 0.0) dm = minloc_pick(dm, MinLoc{d, i});
+  }
+  red.sum(acc2);
+  dm = block_minloc(dm, mbuf, ibuf, mpar);
+  double rr_new = acc2[0];
+  const double gscale = sqrt(acc2[1] / (double)n) + 1e-300;
+
+  // (3) face changes once the face problem is nearly solved
+  const bool nearly = rr_new <= 1e-12 * st->cg_rr0;
+  if (dm.v < -1e-13 * gscale && (nearly || sqrt(rr_new) <= 1e-2 * (-dm.v))) {
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if ((int64_t)(tid + 256 * j) == dm.i) fr[j] = 1.0;
+    restart = true;
+    if (tid == 0) st->cg_released += 1;
+  } else if (active && nu < 0.0 && (nearly || sqrt(rr_new) <= 1e-2 * (-nu) * st->mu_absmax)) {
+    active = false;
+    restart = true;
+  }
+  if (restart) {
+    face_multipliers<E>(g, mu, fr, active, red, lam, nu);
+    double acc3[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const double d = g[j] - lam - nu * mu[j];
+      rv[j] = (fr[j] > 0.0) ? -d : 0.0;
+      acc3[0] = fma(rv[j], rv[j], acc3[0]);
+    }
+    red.sum(acc3);
+    rr_new = acc3[0];
+  }
+
+  // (4) stopping test of Sec. 3.1 on the maintained gradient
+  const int it = st->cg_iter + 1;
+  bool stop = false;
+  if (it % st->check_every == 0) {
+    double w[E];
+    const double alpha = st->alpha;
+#pragma unroll
+    for (int j = 0; j < E; ++j) w[j] = (tid + 256 * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
+    const ProjResult pr = project_F<E>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    double acc4[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const double d = w[j] - x[j];
+      acc4[0] = fma(d, d, acc4[0]);
+      acc4[1] = fma(x[j], g[j], acc4[1]);
+      acc4[2] += (x[j] > 0.0) ? 1.0 : 0.0;
+    }
+    red.sum(acc4);
+    const double res = sqrt(acc4[0]);
+    if (tid == 0) {
+      st->residual = res;
+      st->nu_c = pr.nu;
+      st->tau_c = pr.tau;
+      st->objective = 0.5 * acc4[1];
+      st->support = (int32_t)acc4[2];
+      st->lambda_kkt = -pr.tau / alpha;
+      st->nu_kkt = pr.nu / alpha;
+      st->proj_flags |= pr.flags;
+      if (!isfinite(res)) {
+        st->done = kNumeric;
+      } else if (res <= st->tol) {
+        st->done = kConverged;
+      }
+    }
+    stop = !isfinite(res) || res <= st->tol;
+  }
+  if (!stop && it >= st->max_iter && tid == 0) st->done = kMaxIter;
+
+  // (5) next direction
+  const double beta = (!restart && rr > 0.0) ? rr_new / rr : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    p[j] = fma(beta, p[j], rv[j]);
+    if (i < n) {
+      x_p[i] = x[j];
+      a.gvec[i] = g[j];
+      a.pvec[i] = p[j];
+      a.fvec[i] = fr[j];
+      a.xs[i] = (float)p[j];
+    }
+  }
+  if (tid == 0) {
+    st->cg_iter = it;
+    st->cg_rr = rr_new;
+    if (restart) {
+      st->cg_rr0 = rr_new;
+      st->cg_cycles += 1;
+    }
+    if (block == 1) st->cg_blocked += 1;
+    st->cg_active = active ? 1 : 0;
+  }
+}
+
 }  // namespace npga
