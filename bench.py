@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--path", default="gemv", choices=["gemv", "syrk", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-syrk-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -59,7 +60,7 @@ def cpu_baseline(Rt, r, gpu_grad_evals, budget_s):
     onpga.npga(model, mu, r, alpha, x0, tol=1e-300, check_every=5, max_iter=1)
     t1 = time.perf_counter()
     per_first = t1 - t0
-    k = max(5, min(200, int(budget_s / max(per_first / 2.0, 1e-3))))
+    k = max(5, min(2000, int(budget_s / max(per_first / 2.0, 1e-3))))
     t0 = time.perf_counter()
     onpga.npga(model, mu, r, alpha, x0, tol=1e-300, check_every=5, max_iter=k)
     dt = time.perf_counter() - t0
@@ -177,6 +178,26 @@ def main():
         },
         "generator_s": t_gen,
     }
+    # the covariance path (Sigma = L L^T by MFMA, then a SYMV per iteration),
+    # reported beside the timed path; not part of the timed steps
+    if args.path == "gemv" and not args.no_syrk_compare:
+        L, mu = npga.build_factor(R)
+        sy = []
+        for _ in range(2):
+            _, info_s = npga.solve(L, mu, r, path="syrk")
+            sy.append(info_s)
+        s_last = sy[-1]
+        out["syrk_path"] = {
+            "time_to_tol_s": s_last["time_to_tol_ms"] / 1e3,
+            "solve_ms_incl_refinement": s_last["time_ms"],
+            "setup_ms_incl_syrk": s_last["setup_ms"],
+            "iters_to_tol": s_last["iters"],
+            "refine_iters": s_last["refine_iters"],
+            "symv_ms": s_last["sweep_ms"],
+            "symv_effective_GBs": 4.0 * n * n / (s_last["sweep_ms"] * 1e-3) / 1e9 if s_last["sweep_ms"] else None,
+            "objective": s_last["objective"],
+            "status": s_last["status_name"],
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Rt, r, grad_evals, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -217,11 +217,13 @@ int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max
       if (i == 0 && tm) {
         // time the first gradient launch of every chunk on this stream
         if (hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
-        const int e = (path == NPGA_PATH_SYRK) ? npga::launch_symv_tail(c.a, c.sigma, c.lds, slots, s)
+        const int e = (path == NPGA_PATH_SYRK) ? npga::launch_symv(c.a, c.sigma, c.lds, slots, s)
                                                : npga::launch_sweep(c.a, slots, s);
         if (e) return NPGA_ERR_HIP;
         if (hipEventRecord(tm->b[slot], s) != hipSuccess) return NPGA_ERR_HIP;
-        if (path != NPGA_PATH_SYRK && npga::launch_reduce_tail(c.a, slots, s)) return NPGA_ERR_HIP;
+        const int e2 = (path == NPGA_PATH_SYRK) ? npga::launch_tail(c.a, slots, 1, s)
+                                                : npga::launch_reduce_tail(c.a, slots, s);
+        if (e2) return NPGA_ERR_HIP;
         continue;
       }
       if (step(c, path, slots, s)) return NPGA_ERR_HIP;

@@ -165,12 +165,76 @@ __device__ __forceinline__ double simplex_tau(const double (&v)[E], const double
   return tau;
 }
 
+// One pass that also counts membership changes against the previous pass
+// (per-thread bit masks, E <= 32).
+template <int E>
+__device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const double (&mu)[E], double nu,
+                                                     double tau, uint32_t &mask, double &changed,
+                                                     double *buf) {
+  // buf holds 64 doubles: BlockReducer<5> uses [0, 40); this pass uses
+  // [40, 64) and is followed by a barrier before its next use
+  BlockReducer<6> red6{buf + 40, 0};
+  double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  uint32_t nm = 0u;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const double w = fma(nu, mu[j], v[j]);
+    const bool in = w > tau;
+    nm |= (in ? 1u : 0u) << j;
+    const double m = in ? 1.0 : 0.0;
+    a[0] += m;
+    a[1] = fma(m, v[j], a[1]);
+    a[2] = fma(m, mu[j], a[2]);
+    a[3] = fma(m * mu[j], mu[j], a[3]);
+    a[4] = fma(m * mu[j], v[j], a[4]);
+  }
+  a[5] = (double)__popc(nm ^ mask);
+  mask = nm;
+  red6.sum(a);
+  changed = a[5];
+  return PassSums{a[0], a[1], a[2], a[3], a[4]};
+}
+
 template <int E>
 __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r, double tolphi,
                                 double nu_warm, double tau_warm, BlockReducer<5> &red) {
   ProjResult out{0.0, 0.0, 0, 0};
   int passes = 0, flags = 0;
   PassSums s;
+  // Fast path from a warm start with the return constraint binding: joint
+  // Newton on (tau, nu).  On a support S the two conditions
+  //   |S| tau - nu sum_S mu = sum_S v - 1,  tau sum_S mu - nu sum_S mu^2 = sum_S mu v - r
+  // are linear; if the support at the solution (tau', nu') is again S and
+  // nu' > 0, every KKT condition of the projection holds, so the point is
+  // exact.  Otherwise the safeguarded search below takes over.
+  if (nu_warm > 0.0) {
+    uint32_t mask = 0u;
+    double changed = 0.0;
+    s = proj_pass_masked<E>(v, mu, nu_warm, tau_warm, mask, changed, red.buf);
+    ++passes;
+    __syncthreads();
+    for (int it = 0; it < 4; ++it) {
+      if (s.c < 1.5) break;
+      const double det = s.c * s.smm - s.sm * s.sm;
+      if (!(det > 1e-30 * s.c * s.smm)) break;
+      const double b1 = s.sv - 1.0, b2 = s.smv - r;
+      const double tn = (b1 * s.smm - s.sm * b2) / det;
+      const double nn = (s.sm * b1 - s.c * b2) / det;
+      if (!(nn > 0.0) || !isfinite(tn)) break;
+      s = proj_pass_masked<E>(v, mu, nn, tn, mask, changed, red.buf);
+      ++passes;
+      __syncthreads();
+      if (changed == 0.0) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = fmax(fma(nn, mu[j], v[j]) - tn, 0.0);
+        out.nu = nn;
+        out.tau = tn;
+        out.passes = passes;
+        out.flags = flags;
+        return out;
+      }
+    }
+  }
   const double INF = 1.0e308;
   double nu = (nu_warm > 0.0) ? nu_warm : 0.0;
   double tau = simplex_tau<E>(v, mu, nu, tau_warm, s, red, passes, flags);

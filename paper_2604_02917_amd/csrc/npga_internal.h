@@ -39,7 +39,7 @@ struct alignas(256) DevState {
   int32_t iter;         // k: index of the current iterate x^k
   int32_t stop_iter;    // k at which the stopping test passed in the main phase
   int32_t max_iter;     // last iteration index allowed in the current phase
-  uint32_t ticket;      // last-workgroup counter of the reduce kernel
+  uint32_t ticket;      // unused (kept for layout)
   int32_t check_every;
   int32_t restart;      // adaptive restart on/off in the current phase
   int32_t proj_flags;   // bit 0: a projection hit its pass cap; bit 1: bracket failure
@@ -136,6 +136,7 @@ int launch_set_vector(double *dst, const float *src32, const double *src64, int6
 int launch_random_unit(double *u, float *xs, int64_t n, uint64_t seed, hipStream_t s);
 int launch_sweep(const SolveArgs &a, int slots, hipStream_t s);
 int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s);
+int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s);
 int launch_project_init(const SolveArgs &a, int slots, int use_x0, hipStream_t s);
 int launch_project_only(const double *v, const double *mu, int64_t n, double *x, DevState *st,
                         int slots, hipStream_t s);
@@ -150,6 +151,7 @@ int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, 
                 hipStream_t s);
 int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int slots,
                      hipStream_t s);
+int launch_symv(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, hipStream_t s);
 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,

@@ -34,7 +34,7 @@ namespace npga {
 
 // Statistics of mu and a finiteness check of mu, one workgroup.
 __global__ __launch_bounds__(256) void k_prepare(const double *mu, int64_t n, DevState *st) {
-  __shared__ double sh[2 * 4 * 5];
+  __shared__ double sh[64];
   double mx = -1.0e308, amx = 0.0, bad = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const double m = mu[i];
@@ -97,7 +97,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 // u = r / ||r||, r_i ~ N(0, 1) by Box-Muller on hashed counters (power-method start).
 template <int E>
 __global__ __launch_bounds__(256) void k_random_unit(double *u, float *xs, int64_t n, uint64_t seed) {
-  __shared__ double sh[2 * 4 * 5];
+  __shared__ double sh[64];
   BlockReducer<5> red{sh, 0};
   double val[E];
   double acc[5] = {0, 0, 0, 0, 0};
@@ -255,16 +255,15 @@ __global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
   if (threadIdx.x == 0) a.usq_part[blockIdx.x] = ((shu[0] + shu[1]) + shu[2]) + shu[3];
 }
 
-// Row blocks of 64 sum the sweep partials; the last workgroup runs the tail.
-template <int E>
-__global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
+// Row blocks of 64 sum the sweep partials in a fixed order (deterministic)
+// and assemble the gradient of the current mode.  No cross-workgroup
+// signalling: the serial tail is a separate one-workgroup launch, so the
+// kernel boundary orders the writes (a per-workgroup device-scope fence
+// costs more than that launch).
+__global__ __launch_bounds__(256) void k_reduce(SolveArgs a) {
   DevState *st = a.st;
   if (st->done != kRunning) return;
   __shared__ double red[4][64];
-  __shared__ double redbuf[2 * 4 * 5];
-  __shared__ double mbuf[8];
-  __shared__ int64_t ibuf[8];
-  __shared__ uint32_t ticket_sh;
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
   const int G = a.sweep_grid;
@@ -276,10 +275,10 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
   }
   red[q][r] = s;
   __syncthreads();
-  const int cur = (a.mode == kTailNpga) ? (st->iter & 1) : 0;
   if (q == 0 && i < a.n) {
     const double tot = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
     if (a.mode == kTailNpga) {
+      const int cur = st->iter & 1;
       const double *xk = cur ? a.xbuf1 : a.xbuf0;
       double *gk = cur ? a.gbuf1 : a.gbuf0;
       gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
@@ -291,23 +290,27 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
       a.gbuf0[i] = tot;
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) ticket_sh = atomicAdd(&st->ticket, 1u);
-  __syncthreads();
-  if (ticket_sh != gridDim.x - 1) return;
-  __threadfence();
-  // last workgroup: total ||L^T x||^2 (one partial per thread, then the
-  // fixed-order workgroup sum), then the tail
-  double usq;
-  {
+}
+
+// The serial tail of one iteration (one workgroup).  `covariance` selects
+// the objective source: the sweep's ||L^T x||^2 partials on the factor path,
+// 1/2 x^T g on the covariance path.
+template <int E>
+__global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  __shared__ double redbuf[64];
+  __shared__ double mbuf[8];
+  __shared__ int64_t ibuf[8];
+  double usq = -1.0;
+  if (!covariance && (a.mode == kTailNpga || a.mode == kTailPower || a.mode == kTailGrad)) {
     BlockReducer<5> red5{redbuf, 0};
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int w = threadIdx.x; w < G; w += 256) acc[0] += a.usq_part[w];
+    for (int w = threadIdx.x; w < a.sweep_grid; w += 256) acc[0] += a.usq_part[w];
     red5.sum(acc);
     usq = acc[0];
+    __syncthreads();
   }
-  __syncthreads();
   if (a.mode == kTailNpga)
     tail_npga<E>(a, usq, redbuf);
   else if (a.mode == kTailCG)
@@ -316,14 +319,13 @@ __global__ __launch_bounds__(256) void k_reduce_tail(SolveArgs a) {
     tail_power<E>(a, usq, redbuf);
   else
     tail_grad<E>(a, usq, redbuf);
-  if (threadIdx.x == 0) st->ticket = 0u;
 }
 
 // x0 = Pi_F(xbuf0) (Algorithm 1 requires x^0 in F); initialises the iteration.
 template <int E>
 __global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
   DevState *st = a.st;
-  __shared__ double redbuf[2 * 4 * 5];
+  __shared__ double redbuf[64];
   BlockReducer<5> red{redbuf, 0};
   const int tid = threadIdx.x;
   double mu[E], v[E];
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
 template <int E>
 __global__ __launch_bounds__(256) void k_cg_init(SolveArgs a) {
   DevState *st = a.st;
-  __shared__ double redbuf[2 * 4 * 5];
+  __shared__ double redbuf[64];
   BlockReducer<5> red{redbuf, 0};
   const int tid = threadIdx.x;
   const int64_t n = a.n;
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(256) void k_cg_init(SolveArgs a) {
 template <int E>
 __global__ __launch_bounds__(256) void k_project_only(const double *vin, const double *muin, int64_t n,
                                                       double *xout, DevState *st) {
-  __shared__ double redbuf[2 * 4 * 5];
+  __shared__ double redbuf[64];
   BlockReducer<5> red{redbuf, 0};
   const int tid = threadIdx.x;
   double mu[E], v[E];
@@ -505,7 +507,13 @@ int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
 
 int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
   const int grid = (int)((a.n + 63) / 64);
-#define CALL(E) hipLaunchKernelGGL(k_reduce_tail<E>, dim3(grid), dim3(256), 0, s, a)
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, s, a);
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  return launch_tail(a, slots, 0, s);
+}
+
+int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_tail<E>, dim3(1), dim3(256), 0, s, a, covariance)
   NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
   return (int)hipGetLastError();

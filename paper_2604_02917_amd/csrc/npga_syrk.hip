@@ -20,7 +20,6 @@
 
 #include "npga_device.h"
 #include "npga_internal.h"
-#include "npga_tail.h"
 
 namespace npga {
 
@@ -160,15 +159,11 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64
       }
 }
 
-// g = 2 Sigma x (+ 2 gamma x), then the serial tail in the last workgroup.
+// g = 2 Sigma x (+ 2 gamma x); the serial tail runs as a separate launch.
 template <int E>
-__global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__restrict__ S, int64_t lds) {
+__global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restrict__ S, int64_t lds) {
   DevState *st = a.st;
   if (st->done != kRunning) return;
-  __shared__ double redbuf[2 * 4 * 5];
-  __shared__ double mbuf[8];
-  __shared__ int64_t ibuf[8];
-  __shared__ uint32_t ticket_sh;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
@@ -210,19 +205,6 @@ __global__ __launch_bounds__(256) void k_symv_tail(SolveArgs a, const float *__r
         gk[col] = 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col];
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) ticket_sh = atomicAdd(&st->ticket, 1u);
-  __syncthreads();
-  if (ticket_sh != gridDim.x - 1) return;
-  __threadfence();
-  if (a.mode == kTailNpga)
-    tail_npga<E>(a, -1.0, redbuf);
-  else if (a.mode == kTailCG)
-    tail_cg<E>(a, redbuf, mbuf, ibuf);
-  else
-    tail_power<E>(a, -1.0, redbuf);
-  if (threadIdx.x == 0) st->ticket = 0u;
 }
 
 int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
@@ -248,11 +230,16 @@ int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, 
     default: return (int)hipErrorInvalidValue;   \
   }
 
-int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, hipStream_t s) {
-#define CALL(E) hipLaunchKernelGGL(k_symv_tail<E>, dim3(a.sweep_grid), dim3(256), 0, s, a, Sigma, lds)
+int launch_symv(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_symv<E>, dim3(a.sweep_grid), dim3(256), 0, s, a, Sigma, lds)
   SYMV_SLOT_SWITCH(slots, CALL)
 #undef CALL
   return (int)hipGetLastError();
+}
+
+int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, hipStream_t s) {
+  if (launch_symv(a, Sigma, lds, slots, s)) return (int)hipErrorLaunchFailure;
+  return launch_tail(a, slots, 1, s);
 }
 
 }  // namespace npga
