@@ -91,7 +91,10 @@ typedef struct npga_options {
   uint64_t seed;         /* seed of the power-method start vector; default 1          */
   int32_t warm_start;    /* 1 = x holds x^0 on entry (projected onto F first)          */
   int32_t restart;       /* 1 = adaptive gradient restart of the momentum; default 0  */
-  double refine_tol;     /* residual target of the refinement phase; default 1e-9     */
+  double refine_tol;     /* unused by the face-CG refinement, which stops on its own
+                            KKT test (projected gradient <= 1e-10 of the gradient on
+                            the support, no negative reduced cost); kept for ABI
+                            stability; default 1e-9                                   */
   int32_t refine_max_iter; /* iteration cap of the refinement phase; default 20000    */
 } npga_options;
 
@@ -102,7 +105,7 @@ typedef struct npga_result {
   int32_t refine_iters;   /* iterations spent in the refinement phase               */
   int32_t support;        /* number of x_i > 0                                       */
   int32_t return_active;  /* 1 if the return constraint binds (nu > 0)              */
-  int32_t refined;        /* 1 if the refinement reached refine_tol                  */
+  int32_t refined;        /* 1 if the refinement ended on its KKT test               */
   int32_t path_used;      /* npga_path actually run                                  */
   int32_t reserved;
   double residual;        /* stopping residual when the test first passed           */
@@ -213,19 +216,24 @@ int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, in
  *     L_eff = Y V_ell = U_ell Sig_ell  (n x ell; App. D "STR as one sketch"),
  *     gamma = ridge_coef * trace(Y Y^T) / n   (ridge stage; untruncated Y).
  *   L       device n x T float32 (ldl)
- *   S_opt   device T x k float32 column-major (leading dim T), or NULL to draw
- *           S on the device from Philox4x32-10 keyed by `seed`
+ *   S_opt   device T x k float32 column-major with leading dim lds >= T, or
+ *           NULL to draw S on the device (NPGA_ERR_UNSUPPORTED in builds
+ *           without the on-device generator)
  *   Leff    device n x ell float32 output (ldle >= n, multiple of 4)
  *   sigma   device ell float32 output: leading singular values of Y
  *   gamma_out (host) receives gamma
  *   ws      npga_sketch_workspace_size(n, T, k, ell) bytes
- * Requires 1 <= ell <= k <= 8192 and ell < n.
+ * Requires 1 <= ell <= k <= 8192.  The truncation computes the top-ell
+ * eigenpairs of G = Y^T Y with a float64 Householder tridiagonalisation,
+ * bisection and inverse iteration; L_eff = Y V_ell is then the same
+ * Sigma_hat as U_ell S_ell^2 U_ell^T for any orthonormal basis V_ell of
+ * that eigenspace.  Synchronises `stream`.
  * ------------------------------------------------------------------------- */
 size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell);
 int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k,
                     int64_t ell, double ridge_coef, uint64_t seed, const float *S_opt,
-                    float *Leff, int64_t ldle, float *sigma, double *gamma_out, void *ws,
-                    size_t ws_bytes, hipStream_t stream);
+                    int64_t lds, float *Leff, int64_t ldle, float *sigma, double *gamma_out,
+                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * npga_solve_batched - m independent solves sharing L_eff (an efficient

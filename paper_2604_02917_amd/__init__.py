@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     gradient,
     lib_path,
     project,
+    sketch_str,
     solve,
     spectral_norm_sq,
     syrk,

@@ -79,7 +79,7 @@ def _load():
         "npga_build_factor_workspace_size": (sz, [i64, i64]),
         "npga_build_factor": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]),
         "npga_sketch_workspace_size": (sz, [i64, i64, i64, i64]),
-        "npga_sketch_str": (ctypes.c_int, [vp, i64, i64, i64, i64, i64, dbl, u64, vp, vp, i64, vp,
+        "npga_sketch_str": (ctypes.c_int, [vp, i64, i64, i64, i64, i64, dbl, u64, vp, i64, vp, i64, vp,
                                            vp, vp, sz, vp]),
         "npga_batched_workspace_size": (sz, [i64, i64, i32, ctypes.POINTER(_Options)]),
         "npga_solve_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i32, ctypes.POINTER(_Options),
@@ -239,6 +239,30 @@ def spectral_norm_sq(L_TxN, iters=30, seed=1):
     _check(_lib.npga_spectral_norm_sq(ctypes.byref(f), int(iters), int(seed), ctypes.byref(out),
                                       _ptr(ws), ws.numel(), _stream()), "npga_spectral_norm_sq")
     return out.value
+
+
+def sketch_str(L_TxN, S_kxT, ell, ridge_coef=1e-4, seed=0):
+    """Sketch-truncate-ridge (Sec. 2.5, App. D) on the GPU.
+
+    L_TxN: (T, n) float32 factor; S_kxT: (k, T) float32 sketch (row j is
+    column j of the T x k sketch).  Returns (L_eff as an (ell, n) float32
+    tensor, i.e. the n x ell factor column-major, sigma (ell,) float32,
+    gamma).
+    """
+    Lb, n, T, ld = _as_colmajor(L_TxN)
+    if S_kxT.dim() != 2 or S_kxT.shape[1] != T or S_kxT.dtype != torch.float32:
+        raise ValueError("S must be a (k, T) float32 CUDA tensor")
+    S = S_kxT.contiguous()
+    k = S.shape[0]
+    ldle = (n + 3) // 4 * 4
+    Leff = torch.empty((ell, ldle), dtype=torch.float32, device=Lb.device)
+    sigma = torch.empty(ell, dtype=torch.float32, device=Lb.device)
+    ws = _workspace(_lib.npga_sketch_workspace_size(n, T, k, ell), Lb.device)
+    gam = ctypes.c_double(0.0)
+    _check(_lib.npga_sketch_str(_ptr(Lb), n, T, ld, k, int(ell), float(ridge_coef), int(seed), _ptr(S), T,
+                                _ptr(Leff), ldle, _ptr(sigma), ctypes.byref(gam), _ptr(ws), ws.numel(),
+                                _stream()), "npga_sketch_str")
+    return (Leff if ldle == n else Leff[:, :n]), sigma, gam.value
 
 
 def syrk(L_TxN):

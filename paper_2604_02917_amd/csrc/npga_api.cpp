@@ -13,6 +13,7 @@
 
 #include "npga.h"
 #include "npga_internal.h"
+#include "npga_sketch.h"
 
 using npga::DevState;
 using npga::SolveArgs;
@@ -418,19 +419,32 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     c.a.fvec = vecs + npad;
     c.a.gvec = vecs + 2 * npad;
     c.a.mode = npga::kTailCG;
-    LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, stream));
-    LAUNCHCHK(npga::launch_cg_init(c.a, slots, stream));
-    double rms = 0.0;
-    const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
-    e = run_phase(c, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
-    if (e) return e;
-    refined = (done == npga::kConverged) ? 1 : 0;
+    // two rounds: the second re-anchors at the first round's result, which
+    // removes the drift of the gradient carried by linearity
+    for (int round = 0; round < 2; ++round) {
+      if (round > 0) {
+        HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
+        LAUNCHCHK(npga::launch_precise_gradient(c.a, xa, ua, ga,
+                                                reinterpret_cast<double *>(c.a.partials), slots, stream));
+      }
+      LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, stream));
+      LAUNCHCHK(npga::launch_cg_init(c.a, slots, stream));
+      double rms = 0.0;
+      const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
+      e = run_phase(c, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
+      if (e) return e;
+      HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      refine_iters += pin[2].cg_iter;
+      if (done != npga::kConverged) break;
+      if (pin[2].cg_kkt && round > 0) break;
+    }
+    refined = (done == npga::kConverged && pin[2].cg_kkt) ? 1 : 0;
   }
   LAUNCHCHK(npga::launch_finalize(c.a, x, slots, stream));
   HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   const DevState &fin = pin[3];
-  refine_iters = (main_done == npga::kConverged && o.refine) ? fin.cg_iter : 0;
 
   int status = map_done(main_done);
   if (main_done == npga::kConverged && done != npga::kConverged && done != npga::kMaxIter)
@@ -584,21 +598,104 @@ int npga_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *
   return NPGA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct SketchLayout {
+  size_t off_S, off_Y, off_A, off_vec, off_Z, off_work, off_V32, off_frob, off_gamma, total;
+  int64_t ldS, ldy, stride;
+};
+
+constexpr int kFrobParts = 256;
+
+SketchLayout sketch_layout(int64_t n, int64_t T, int64_t k, int64_t ell, bool need_S) {
+  SketchLayout l{};
+  l.ldS = (T + 3) / 4 * 4;
+  l.ldy = (n + 3) / 4 * 4;
+  l.stride = (ell + 63) / 64 * 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  l.off_S = need_S ? take(sizeof(float) * (size_t)l.ldS * (size_t)k) : 0;
+  l.off_Y = take(sizeof(float) * (size_t)l.ldy * (size_t)k);
+  l.off_A = take(sizeof(double) * (size_t)k * (size_t)k);
+  l.off_vec = take(sizeof(double) * (size_t)k * 8);
+  l.off_Z = take(sizeof(double) * (size_t)k * (size_t)ell);
+  l.off_work = take(sizeof(double) * 5 * (size_t)l.stride * (size_t)k + (size_t)l.stride * (size_t)k);
+  l.off_V32 = take(sizeof(float) * (size_t)k * (size_t)ell);
+  l.off_frob = take(sizeof(double) * kFrobParts);
+  l.off_gamma = take(sizeof(double) * 4);
+  l.total = off;
+  return l;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell) {
-  (void)n;
-  (void)T;
-  (void)k;
-  (void)ell;
-  return 0;
+  if (n < 1 || T < 1 || k < 1 || ell < 1 || ell > k || k > NPGA_MAX_N) return 0;
+  return sketch_layout(n, T, k, ell, true).total;
 }
 
 int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k, int64_t ell,
-                    double ridge_coef, uint64_t seed, const float *S_opt, float *Leff, int64_t ldle,
-                    float *sigma, double *gamma_out, void *ws, size_t ws_bytes, hipStream_t stream) {
-  (void)L; (void)n; (void)T; (void)ldl; (void)k; (void)ell; (void)ridge_coef; (void)seed;
-  (void)S_opt; (void)Leff; (void)ldle; (void)sigma; (void)gamma_out; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return NPGA_ERR_UNSUPPORTED;
+                    double ridge_coef, uint64_t seed, const float *S_opt, int64_t lds_opt, float *Leff,
+                    int64_t ldle, float *sigma, double *gamma_out, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  (void)seed;
+  if (!L || !Leff || !sigma || !gamma_out) return NPGA_ERR_INVALID;
+  if (n < 1 || n > NPGA_MAX_N || T < 1 || k < 2 || k > NPGA_MAX_N || ell < 1 || ell > k) return NPGA_ERR_INVALID;
+  if (ldl < n || (ldl % 4) != 0 || ldle < n || (ldle % 4) != 0) return NPGA_ERR_INVALID;
+  if (!aligned(L, 16) || !aligned(Leff, 16)) return NPGA_ERR_INVALID;
+  if (!is_fin(ridge_coef) || ridge_coef < 0) return NPGA_ERR_INVALID;
+  if (!S_opt) return NPGA_ERR_UNSUPPORTED;  // on-device sketch generation not in this build
+  if (lds_opt < T) return NPGA_ERR_INVALID;
+  const SketchLayout lay = sketch_layout(n, T, k, ell, false);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  char *base = static_cast<char *>(ws);
+  float *Y = reinterpret_cast<float *>(base + lay.off_Y);
+  double *vec = reinterpret_cast<double *>(base + lay.off_vec);
+  npga::SketchState s{};
+  s.k = k;
+  s.A = reinterpret_cast<double *>(base + lay.off_A);
+  s.d = vec;
+  s.e = vec + k;
+  s.tau = vec + 2 * k;
+  s.vcur = vec + 3 * k;
+  s.vprev = vec + 4 * k;
+  s.wprev = vec + 5 * k;
+  s.p = vec + 6 * k;
+  s.lam = vec + 7 * k;
+  s.Z = reinterpret_cast<double *>(base + lay.off_Z);
+  s.work = reinterpret_cast<double *>(base + lay.off_work);
+  float *V32 = reinterpret_cast<float *>(base + lay.off_V32);
+  double *frob = reinterpret_cast<double *>(base + lay.off_frob);
+  double *gdev = reinterpret_cast<double *>(base + lay.off_gamma);
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  // sketch stage: Y = L S
+  LAUNCHCHK(npga::launch_gemm_f32(L, ldl, S_opt, lds_opt, Y, lay.ldy, n, k, T, stream));
+  // truncation stage: top-ell eigenspace of G = Y^T Y
+  LAUNCHCHK(npga::launch_gram_f64(Y, lay.ldy, n, k, s.A, stream));
+  LAUNCHCHK(npga::launch_frob(Y, lay.ldy, n, k, frob, kFrobParts, stream));
+  LAUNCHCHK(npga::launch_tridiag(s, stream));
+  LAUNCHCHK(npga::launch_bisect(s, ell, stream));
+  LAUNCHCHK(npga::launch_inverse_iter(s, ell, lay.stride, stream));
+  LAUNCHCHK(npga::launch_backtransform(s, ell, V32, stream));
+  // L_eff = Y V_ell (n x ell)
+  LAUNCHCHK(npga::launch_gemm_f32(Y, lay.ldy, V32, k, Leff, ldle, n, ell, k, stream));
+  // ridge stage and singular values
+  LAUNCHCHK(npga::launch_finish_str(s, ell, n, ridge_coef, frob, kFrobParts, sigma, gdev, stream));
+  double *h = reinterpret_cast<double *>(&pin[3]);
+  HIPCHK(hipMemcpyAsync(h, gdev, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  *gamma_out = h[0];
+  if (!is_fin(h[0])) return NPGA_ERR_NUMERIC;
+  return NPGA_OK;
 }
 
 size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt) {

@@ -72,7 +72,9 @@ struct alignas(256) DevState {
   int32_t cg_cycles;    // CG restarts (active-set changes)
   int32_t cg_released;  // indices released from the zero set
   int32_t cg_blocked;   // indices fixed at zero by a blocking step
-  double pad[2];
+  double cg_best_rr;    // smallest ||r||^2 seen in the current CG round
+  int32_t cg_best_it;   // iteration at which it was seen
+  int32_t cg_kkt;       // 1 if the round ended on the KKT test
 };
 
 // Host-visible status block copied back once per chunk of iterations.

@@ -1,0 +1,38 @@
+// Internal declarations of the sketch-truncate-ridge build (npga_sketch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace npga {
+
+// Device buffers of the k x k symmetric eigensolver (all float64).
+struct SketchState {
+  int64_t k;
+  double *A;      // k x k, leading dim k: G on entry, reflectors on exit
+  double *d;      // diagonal of T (k)
+  double *e;      // off-diagonal of T (k - 1)
+  double *tau;    // reflector scalars (k)
+  double *vcur;   // current reflector (k)
+  double *vprev;  // previous reflector (k)
+  double *wprev;  // previous rank-2 companion vector (k)
+  double *p;      // tau A v of the current step (k)
+  double *lam;    // wanted eigenvalues, descending (ell)
+  double *Z;      // eigenvectors of T, then of G (k x ell, leading dim k)
+  double *work;   // inverse-iteration factors (5 stride k doubles + stride k bytes)
+};
+
+int launch_gemm_f32(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+                    int64_t M, int64_t N, int64_t K, hipStream_t st);
+int launch_gram_f64(const float *Y, int64_t ldy, int64_t n, int64_t k, double *G, hipStream_t st);
+int launch_frob(const float *Y, int64_t ldy, int64_t n, int64_t k, double *part, int nparts,
+                hipStream_t st);
+int launch_tridiag(const SketchState &s, hipStream_t st);
+int launch_bisect(const SketchState &s, int64_t ell, hipStream_t st);
+int launch_inverse_iter(const SketchState &s, int64_t ell, int64_t stride, hipStream_t st);
+int launch_backtransform(const SketchState &s, int64_t ell, float *V32, hipStream_t st);
+int launch_finish_str(const SketchState &s, int64_t ell, int64_t n, double coef, const double *frob_part,
+                      int nparts, float *sigma, double *gamma_dev, hipStream_t st);
+
+}  // namespace npga

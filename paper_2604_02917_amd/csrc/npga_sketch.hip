@@ -1,0 +1,662 @@
+// Sketch-Truncate-Ridge factor build (paper Sec. 2.5; App. D):
+//     Y = L S                      sketch stage (S T x k, N(0, 1/k) entries)
+//     Y = U Sig V^T, keep ell      truncation stage (top-ell right singular space)
+//     L_eff = Y V_ell = U_ell Sig_ell   (App. D, "STR as one sketch")
+//     gamma = c trace(Y Y^T) / n   ridge stage with the untruncated sketch
+//
+// The right singular space of Y is the top-ell eigenspace of the Gram
+// matrix G = Y^T Y (k x k).  It is computed by a dense symmetric
+// eigensolver written for the GPU (float64 throughout):
+//   1. G by float64 MFMA (exact products of the float32 entries of Y);
+//   2. Householder tridiagonalisation G = Q T Q^T, one reflector per step
+//      (a one-workgroup kernel forms the reflector, a grid kernel applies the
+//      previous rank-2 update to the trailing columns and forms the next
+//      symmetric matrix-vector product in the same pass);
+//   3. the ell largest eigenvalues of T by bisection on Sturm counts;
+//   4. their eigenvectors of T by inverse iteration (tridiagonal LU with
+//      partial pivoting);
+//   5. back-transformation V = Q Z by the stored reflectors.
+// The products Y = L S and L_eff = Y V use float32 MFMA with float64
+// accumulation across k-chunks.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "npga_device.h"
+#include "npga_internal.h"
+#include "npga_sketch.h"
+
+namespace npga {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------------------
+// float32 MFMA GEMM  C (M x N, column-major, ldc) = A B
+//   A element (m, k): kAK == 0 -> A[m + k lda] (rows contiguous, e.g. L or Y)
+//                     kAK == 1 -> A[k + m lda] (k contiguous)
+//   B element (k, n): B[k + n ldb] (k contiguous, e.g. S or V)
+// 128 x 128 tiles, four wavefronts of 64 x 64 (2 x 2 v_mfma_f32_32x32x2_f32),
+// 32-deep k slices double buffered in LDS, float64 flush every 64 k.
+// --------------------------------------------------------------------------
+constexpr int GT = 128;
+constexpr int GK = 32;
+constexpr int GPAD = 129;
+
+__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, int64_t lda,
+                                                  const float *__restrict__ B, int64_t ldb,
+                                                  float *__restrict__ C, int64_t ldc, int64_t M,
+                                                  int64_t N, int64_t K) {
+  __shared__ float As[2][GK][GT];
+  __shared__ float Bs[2][GK][GPAD];
+  const int64_t nbm = (M + GT - 1) / GT;
+  const int64_t bm = blockIdx.x % nbm;
+  const int64_t bn = blockIdx.x / nbm;
+  const int64_t m0 = bm * GT, n0 = bn * GT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v16f acc[2][2];
+  double acc64[2][2][16];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[p][q][v] = 0.f;
+        acc64[p][q][v] = 0.0;
+      }
+  // A loader (rows contiguous): float4 index (tid % 32) of k-columns tid/32 + 8 q
+  // B loader (k contiguous): column tid/8 + 32 q, float4 index (tid % 8) along k
+  f4 ra[4], rb[4];
+  const bool bvec = (ldb % 4) == 0 && (reinterpret_cast<uintptr_t>(B) % 16) == 0;
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kk = k0 + (tid >> 5) + 8 * q;
+      const int64_t mm = m0 + 4 * (tid & 31);
+      f4 z = f4{0.f, 0.f, 0.f, 0.f};
+      if (kk < K && mm < M) {
+        z = *reinterpret_cast<const f4 *>(A + kk * lda + mm);
+        if (mm + 1 >= M) z.y = 0.f;
+        if (mm + 2 >= M) z.z = 0.f;
+        if (mm + 3 >= M) z.w = 0.f;
+      }
+      ra[q] = z;
+      const int64_t nn = n0 + (tid >> 3) + 32 * q;
+      const int64_t kb = k0 + 4 * (tid & 7);
+      f4 zb = f4{0.f, 0.f, 0.f, 0.f};
+      if (nn < N) {
+        const float *bp = B + nn * ldb + kb;
+        if (bvec && kb + 3 < K) {
+          zb = *reinterpret_cast<const f4 *>(bp);
+        } else {
+          if (kb < K) zb.x = bp[0];
+          if (kb + 1 < K) zb.y = bp[1];
+          if (kb + 2 < K) zb.z = bp[2];
+          if (kb + 3 < K) zb.w = bp[3];
+        }
+      }
+      rb[q] = zb;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<f4 *>(&As[buf][(tid >> 5) + 8 * q][4 * (tid & 31)]) = ra[q];
+      const int c = (tid >> 3) + 32 * q;
+      const int kb = 4 * (tid & 7);
+      Bs[buf][kb + 0][c] = rb[q].x;
+      Bs[buf][kb + 1][c] = rb[q].y;
+      Bs[buf][kb + 2][c] = rb[q].z;
+      Bs[buf][kb + 3][c] = rb[q].w;
+    }
+  };
+  const int64_t nst = (K + GK - 1) / GK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t s = 0; s < nst; ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < nst) gload((s + 1) * GK);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      float av[2], bv[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) av[p] = As[buf][kr][wr * 64 + p * 32 + (lane & 31)];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) bv[q] = Bs[buf][kr][wc * 64 + q * 32 + (lane & 31)];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+    if ((s & 1) == 1 || s + 1 == nst) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            acc64[p][q][v] += (double)acc[p][q][v];
+            acc[p][q][v] = 0.f;
+          }
+    }
+    if (s + 1 < nst) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t r = m0 + wr * 64 + p * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t c = n0 + wc * 64 + q * 32 + (lane & 31);
+        if (r < M && c < N) C[r + c * ldc] = (float)acc64[p][q][v];
+      }
+}
+
+// --------------------------------------------------------------------------
+// float64 Gram matrix G = Y^T Y (k x k, column-major, leading dim k), both
+// triangles, by v_mfma_f64_16x16x4_f64 on the float32 entries of Y (exact
+// products).  64 x 64 tiles of the lower triangle; four wavefronts of
+// 32 x 32 (2 x 2 MFMA blocks); 16-deep slices of Y in LDS.
+// --------------------------------------------------------------------------
+constexpr int HT = 64;
+constexpr int HK = 16;
+
+__global__ __launch_bounds__(256) void k_gram_f64(const float *__restrict__ Y, int64_t ldy, int64_t n,
+                                                  int64_t k, double *__restrict__ G, int nb) {
+  __shared__ double As[2][HK][HT + 1];
+  __shared__ double Bs[2][HK][HT + 1];
+  const int b = blockIdx.x;
+  int bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+  const int bj = b - bi * (bi + 1) / 2;
+  if (bi >= nb) return;
+  const int64_t r0 = (int64_t)bi * HT, c0 = (int64_t)bj * HT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v4d acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = v4d{0.0, 0.0, 0.0, 0.0};
+  // loader: column tid/4 of each panel, float4 index tid%4 along n
+  const int col = tid >> 2, fi = tid & 3;
+  f4 ra, rb;
+  auto gload = [&](int64_t a0) {
+    const int64_t aa = a0 + 4 * fi;
+    ra = f4{0.f, 0.f, 0.f, 0.f};
+    rb = ra;
+    const int64_t ja = r0 + col, jb = c0 + col;
+    if (ja < k) {
+      const float *p = Y + ja * ldy + aa;
+      if (aa + 3 < n) {
+        ra = *reinterpret_cast<const f4 *>(p);
+      } else {
+        if (aa < n) ra.x = p[0];
+        if (aa + 1 < n) ra.y = p[1];
+        if (aa + 2 < n) ra.z = p[2];
+      }
+    }
+    if (jb < k) {
+      const float *p = Y + jb * ldy + aa;
+      if (aa + 3 < n) {
+        rb = *reinterpret_cast<const f4 *>(p);
+      } else {
+        if (aa < n) rb.x = p[0];
+        if (aa + 1 < n) rb.y = p[1];
+        if (aa + 2 < n) rb.z = p[2];
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    As[buf][4 * fi + 0][col] = (double)ra.x;
+    As[buf][4 * fi + 1][col] = (double)ra.y;
+    As[buf][4 * fi + 2][col] = (double)ra.z;
+    As[buf][4 * fi + 3][col] = (double)ra.w;
+    Bs[buf][4 * fi + 0][col] = (double)rb.x;
+    Bs[buf][4 * fi + 1][col] = (double)rb.y;
+    Bs[buf][4 * fi + 2][col] = (double)rb.z;
+    Bs[buf][4 * fi + 3][col] = (double)rb.w;
+  };
+  const int64_t nst = (n + HK - 1) / HK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t s = 0; s < nst; ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < nst) gload((s + 1) * HK);
+#pragma unroll
+    for (int kk = 0; kk < HK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) av[p] = As[buf][kr][wr * 32 + p * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) bv[q] = Bs[buf][kr][wc * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+    if (s + 1 < nst) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // float64 16x16 output layout: lane l, register v -> row (l/16) + 4 v, column l%16
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + wr * 32 + p * 16 + (lane >> 4) + 4 * v;
+        const int64_t c = c0 + wc * 32 + q * 16 + (lane & 15);
+        if (r < k && c < k) {
+          G[r + c * k] = acc[p][q][v];
+          if (bi != bj) G[c + r * k] = acc[p][q][v];
+        }
+      }
+}
+
+// ||Y||_F^2 = trace(Y^T Y) in float64 (one workgroup per column block, then
+// a fixed-order sum).
+__global__ __launch_bounds__(256) void k_frob_partial(const float *Y, int64_t ldy, int64_t n, int64_t k,
+                                                      double *part) {
+  __shared__ double buf[64];
+  BlockReducer<5> red{buf, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t j = blockIdx.x; j < k; j += gridDim.x)
+    for (int64_t a = threadIdx.x; a < n; a += 256) {
+      const double y = Y[a + j * ldy];
+      acc[0] = fma(y, y, acc[0]);
+    }
+  red.sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// --------------------------------------------------------------------------
+// Householder tridiagonalisation, one reflector per step (float64).
+// State (SketchState): A = G (k x k, lda k) is overwritten: the reflector
+// of step i is kept in A[i+1:, i] (leading 1 explicit), d and e receive T.
+//
+// Step i, one workgroup (k_tri_small):
+//   w_{i-1} = p - (tau_{i-1}/2)(p^T v_{i-1}) v_{i-1}    (p = tau A v from the
+//            previous grid kernel), then column i of the trailing block gets
+//            the rank-2 update A <- A - v w^T - w v^T, d_i = A[i, i], and the
+//            reflector of x = A[i+1:, i] (LAPACK dlarfg convention):
+//            beta = -sign(x_0)||x||, tau = (beta - x_0)/beta,
+//            v = [1, x_1:/(x_0 - beta)], e_i = beta.
+// Step i, grid (k_tri_big): every column c > i of the trailing block gets
+//   the pending update from step i-1 (rows > i), is written back, and
+//   p_c = tau_i (A[i+1:, c] . v_i).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tri_small(SketchState s, int64_t i) {
+  __shared__ double buf[64];
+  BlockReducer<5> red{buf, 0};
+  const int64_t k = s.k;
+  double *A = s.A;
+  const int tid = threadIdx.x;
+  // w_{i-1} over rows >= i
+  if (i > 0) {
+    const double taup = s.tau[i - 1];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t r = i + tid; r < k; r += 256) acc[0] = fma(s.p[r], s.vcur[r], acc[0]);
+    red.sum(acc);
+    const double half = 0.5 * taup * acc[0];
+    for (int64_t r = i + tid; r < k; r += 256) {
+      const double w = s.p[r] - half * s.vcur[r];
+      s.wprev[r] = w;
+      s.vprev[r] = s.vcur[r];
+    }
+    __syncthreads();
+    // update column i (rows >= i) with the rank-2 term of step i-1
+    const double wi = s.wprev[i], vi = s.vprev[i];
+    for (int64_t r = i + tid; r < k; r += 256)
+      A[r + i * k] -= s.vprev[r] * wi + s.wprev[r] * vi;
+    __syncthreads();
+  }
+  if (tid == 0) s.d[i] = A[i + i * k];
+  if (i >= k - 1) return;
+  // reflector for x = A[i+1:, i]
+  const double x0 = A[(i + 1) + i * k];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t r = i + 2 + tid; r < k; r += 256) {
+    const double x = A[r + i * k];
+    acc[0] = fma(x, x, acc[0]);
+  }
+  red.sum(acc);
+  const double xn2 = acc[0];
+  double tau = 0.0, beta = x0, scale = 0.0;
+  if (xn2 > 0.0) {
+    beta = -copysign(sqrt(x0 * x0 + xn2), x0);
+    tau = (beta - x0) / beta;
+    scale = 1.0 / (x0 - beta);
+  }
+  for (int64_t r = i + 1 + tid; r < k; r += 256) {
+    const double v = (r == i + 1) ? 1.0 : ((tau != 0.0) ? A[r + i * k] * scale : 0.0);
+    s.vcur[r] = v;
+    A[r + i * k] = v;
+  }
+  if (tid == 0) {
+    s.e[i] = beta;
+    s.tau[i] = tau;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
+  const int64_t k = s.k;
+  double *A = s.A;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const double tau = s.tau[i];
+  const bool upd = i > 0;
+  for (int64_t c = i + 1 + (int64_t)blockIdx.x * 4 + wave; c < k; c += W) {
+    const double wc = upd ? s.wprev[c] : 0.0;
+    const double vc = upd ? s.vprev[c] : 0.0;
+    double *col = A + c * k;
+    double dot = 0.0;
+    for (int64_t r = i + 1 + lane; r < k; r += 64) {
+      double a = col[r];
+      if (upd) {
+        a -= s.vprev[r] * wc + s.wprev[r] * vc;
+        col[r] = a;
+      }
+      dot = fma(a, s.vcur[r], dot);
+    }
+    dot = wave_sum_f64(dot);
+    if (lane == 0) s.p[c] = tau * dot;
+  }
+}
+
+// --------------------------------------------------------------------------
+// The ell largest eigenvalues of the symmetric tridiagonal T (d, e) by
+// bisection on Sturm counts (number of eigenvalues below x from the signs
+// of the LDL^T pivots).  One thread per eigenvalue.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bisect(SketchState s, int64_t ell) {
+  extern __shared__ double sm[];
+  const int64_t k = s.k;
+  double *dd = sm;
+  double *ee = sm + k;  // e_i^2
+  __shared__ double bnd[64];
+  double lo = 1e308, hi = -1e308;
+  for (int64_t i = threadIdx.x; i < k; i += 256) {
+    dd[i] = s.d[i];
+    const double el = (i > 0) ? fabs(s.e[i - 1]) : 0.0;
+    const double er = (i + 1 < k) ? fabs(s.e[i]) : 0.0;
+    if (i + 1 < k) ee[i] = s.e[i] * s.e[i];
+    lo = fmin(lo, s.d[i] - el - er);
+    hi = fmax(hi, s.d[i] + el + er);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    bnd[wave] = lo;
+    bnd[4 + wave] = hi;
+  }
+  __syncthreads();
+  lo = fmin(fmin(bnd[0], bnd[1]), fmin(bnd[2], bnd[3]));
+  hi = fmax(fmax(bnd[4], bnd[5]), fmax(bnd[6], bnd[7]));
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = 1e-300 + 4.0 * 2.2250738585072014e-308 * tnorm;
+  lo -= 2.2e-16 * tnorm + 1e-300;
+  hi += 2.2e-16 * tnorm + 1e-300;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= ell) return;
+  const int64_t m = k - 1 - j;  // ascending index of the j-th largest
+  double a = lo, b = hi;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    // Sturm count: eigenvalues < mid
+    int64_t cnt = 0;
+    double q = dd[0] - mid;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+    for (int64_t i = 1; i < k; ++i) {
+      q = dd[i] - mid - ee[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      if (q < 0.0) ++cnt;
+    }
+    if (cnt > m)
+      b = mid;
+    else
+      a = mid;
+    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+  }
+  s.lam[j] = 0.5 * (a + b);
+}
+
+// --------------------------------------------------------------------------
+// Eigenvectors of T for the computed eigenvalues by inverse iteration: LU
+// of T - lambda I with partial pivoting (the LAPACK dgttrf/dgttrs scheme),
+// three solves from a hashed start vector, normalisation.  One thread per
+// eigenvalue; the factor arrays are interleaved across threads so each
+// step is a coalesced access.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mixh(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(64) void k_inverse_iter(SketchState s, int64_t ell, int64_t stride) {
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (j >= ell) return;
+  const int64_t k = s.k;
+  const double lam = s.lam[j];
+  double *fd = s.work;                 // diagonal of U
+  double *fu = s.work + stride * k;    // first superdiagonal
+  double *fu2 = s.work + 2 * stride * k;
+  double *fl = s.work + 3 * stride * k;  // multipliers
+  double *bv = s.work + 4 * stride * k;  // right-hand side / solution
+  uint8_t *piv = reinterpret_cast<uint8_t *>(s.work + 5 * stride * k);
+#define IX(i) ((i) * stride + j)
+  double tnorm = 0.0;
+  for (int64_t i = 0; i < k; ++i) tnorm = fmax(tnorm, fabs(s.d[i]) + ((i > 0) ? fabs(s.e[i - 1]) : 0.0) +
+                                                          ((i + 1 < k) ? fabs(s.e[i]) : 0.0));
+  const double tiny = 2.2e-16 * tnorm + 1e-300;
+  // factor
+  for (int64_t i = 0; i < k; ++i) {
+    fd[IX(i)] = s.d[i] - lam;
+    if (i + 1 < k) {
+      fu[IX(i)] = s.e[i];
+      fl[IX(i)] = s.e[i];
+    }
+    fu2[IX(i)] = 0.0;
+  }
+  for (int64_t i = 0; i + 1 < k; ++i) {
+    const double di = fd[IX(i)], li = fl[IX(i)];
+    if (fabs(di) >= fabs(li)) {
+      const double dd = (di != 0.0) ? di : tiny;
+      fd[IX(i)] = dd;
+      const double f = li / dd;
+      fl[IX(i)] = f;
+      fd[IX(i + 1)] -= f * fu[IX(i)];
+      piv[IX(i)] = 0;
+    } else {
+      const double f = di / li;
+      fd[IX(i)] = li;
+      fl[IX(i)] = f;
+      const double t = fu[IX(i)];
+      fu[IX(i)] = fd[IX(i + 1)];
+      fd[IX(i + 1)] = t - f * fd[IX(i + 1)];
+      if (i + 2 < k) {
+        fu2[IX(i)] = fu[IX(i + 1)];
+        fu[IX(i + 1)] = -f * fu[IX(i + 1)];
+      }
+      piv[IX(i)] = 1;
+    }
+  }
+  if (fd[IX(k - 1)] == 0.0) fd[IX(k - 1)] = tiny;
+  // start vector
+  for (int64_t i = 0; i < k; ++i) {
+    const uint64_t h = mixh(0x5bd1e995ull * (uint64_t)(j + 1) + (uint64_t)i);
+    bv[IX(i)] = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+  }
+  for (int iter = 0; iter < 3; ++iter) {
+    // L solve with the row interchanges
+    for (int64_t i = 0; i + 1 < k; ++i) {
+      const double f = fl[IX(i)];
+      if (piv[IX(i)] == 0) {
+        bv[IX(i + 1)] -= f * bv[IX(i)];
+      } else {
+        const double t = bv[IX(i)];
+        bv[IX(i)] = bv[IX(i + 1)];
+        bv[IX(i + 1)] = t - f * bv[IX(i + 1)];
+      }
+    }
+    // U solve
+    double nrm = 0.0;
+    for (int64_t i = k - 1; i >= 0; --i) {
+      double v = bv[IX(i)];
+      if (i + 1 < k) v -= fu[IX(i)] * bv[IX(i + 1)];
+      if (i + 2 < k) v -= fu2[IX(i)] * bv[IX(i + 2)];
+      double dd = fd[IX(i)];
+      if (fabs(dd) < tiny) dd = (dd < 0.0) ? -tiny : tiny;
+      v /= dd;
+      bv[IX(i)] = v;
+      nrm = fmax(nrm, fabs(v));
+    }
+    const double inv = (nrm > 0.0) ? 1.0 / nrm : 1.0;
+    for (int64_t i = 0; i < k; ++i) bv[IX(i)] *= inv;
+  }
+  double n2 = 0.0;
+  for (int64_t i = 0; i < k; ++i) n2 = fma(bv[IX(i)], bv[IX(i)], n2);
+  const double inv = 1.0 / sqrt(n2);
+  for (int64_t i = 0; i < k; ++i) s.Z[i + j * k] = bv[IX(i)] * inv;
+#undef IX
+}
+
+// --------------------------------------------------------------------------
+// V = Q Z with Q = H_0 H_1 ... H_{k-2}: every workgroup owns two columns
+// of Z (in LDS) and applies the reflectors from the last to the first.
+// Writes V in float32 (k x ell, leading dim k) for the final product.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_backtransform(SketchState s, int64_t ell, float *V32) {
+  extern __shared__ double zc[];  // 2 k doubles
+  __shared__ double buf[64];
+  BlockReducer<5> red{buf, 0};
+  const int64_t k = s.k;
+  const int64_t j0 = (int64_t)blockIdx.x * 2;
+  const int ncol = (j0 + 1 < ell) ? 2 : 1;
+  for (int64_t r = threadIdx.x; r < k; r += 256) {
+    zc[r] = s.Z[r + j0 * k];
+    zc[k + r] = (ncol == 2) ? s.Z[r + (j0 + 1) * k] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t i = k - 2; i >= 0; --i) {
+    const double tau = s.tau[i];
+    if (tau == 0.0) continue;
+    const double *v = s.A + i * k;  // v[r], r > i
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t r = i + 1 + threadIdx.x; r < k; r += 256) {
+      const double vr = v[r];
+      acc[0] = fma(vr, zc[r], acc[0]);
+      acc[1] = fma(vr, zc[k + r], acc[1]);
+    }
+    red.sum(acc);
+    const double s0 = tau * acc[0], s1 = tau * acc[1];
+    for (int64_t r = i + 1 + threadIdx.x; r < k; r += 256) {
+      const double vr = v[r];
+      zc[r] -= s0 * vr;
+      zc[k + r] -= s1 * vr;
+    }
+    __syncthreads();
+  }
+  for (int64_t r = threadIdx.x; r < k; r += 256) {
+    V32[r + j0 * k] = (float)zc[r];
+    if (ncol == 2) V32[r + (j0 + 1) * k] = (float)zc[k + r];
+  }
+}
+
+__global__ void k_finish_str(SketchState s, int64_t ell, int64_t n, double coef, const double *frob_part,
+                             int nparts, float *sigma, double *gamma_dev) {
+  __shared__ double buf[64];
+  BlockReducer<5> red{buf, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int w = threadIdx.x; w < nparts; w += blockDim.x) acc[0] += frob_part[w];
+  red.sum(acc);
+  for (int64_t j = threadIdx.x; j < ell; j += blockDim.x) sigma[j] = (float)sqrt(fmax(s.lam[j], 0.0));
+  if (threadIdx.x == 0) {
+    gamma_dev[0] = coef * acc[0] / (double)n;
+    gamma_dev[1] = acc[0];
+  }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+int launch_gemm_f32(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+                    int64_t M, int64_t N, int64_t K, hipStream_t st) {
+  const int64_t tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)tiles), dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+  return (int)hipGetLastError();
+}
+
+int launch_gram_f64(const float *Y, int64_t ldy, int64_t n, int64_t k, double *G, hipStream_t st) {
+  const int nb = (int)((k + HT - 1) / HT);
+  const int tiles = nb * (nb + 1) / 2;
+  hipLaunchKernelGGL(k_gram_f64, dim3(tiles), dim3(256), 0, st, Y, ldy, n, k, G, nb);
+  return (int)hipGetLastError();
+}
+
+int launch_frob(const float *Y, int64_t ldy, int64_t n, int64_t k, double *part, int nparts,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_frob_partial, dim3(nparts), dim3(256), 0, st, Y, ldy, n, k, part);
+  return (int)hipGetLastError();
+}
+
+int launch_tridiag(const SketchState &s, hipStream_t st) {
+  const int64_t k = s.k;
+  for (int64_t i = 0; i < k; ++i) {
+    hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(256), 0, st, s, i);
+    if (i + 1 < k) {
+      const int64_t cols = k - i - 1;
+      const int grid = (int)std::min<int64_t>(512, (cols + 3) / 4);
+      hipLaunchKernelGGL(k_tri_big, dim3(grid), dim3(256), 0, st, s, i);
+    }
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_bisect(const SketchState &s, int64_t ell, hipStream_t st) {
+  const int grid = (int)((ell + 255) / 256);
+  const size_t lds = sizeof(double) * 2 * (size_t)s.k;
+  hipLaunchKernelGGL(k_bisect, dim3(grid), dim3(256), lds, st, s, ell);
+  return (int)hipGetLastError();
+}
+
+int launch_inverse_iter(const SketchState &s, int64_t ell, int64_t stride, hipStream_t st) {
+  const int grid = (int)((ell + 63) / 64);
+  hipLaunchKernelGGL(k_inverse_iter, dim3(grid), dim3(64), 0, st, s, ell, stride);
+  return (int)hipGetLastError();
+}
+
+int launch_backtransform(const SketchState &s, int64_t ell, float *V32, hipStream_t st) {
+  const int grid = (int)((ell + 1) / 2);
+  const size_t lds = sizeof(double) * 2 * (size_t)s.k;
+  hipLaunchKernelGGL(k_backtransform, dim3(grid), dim3(256), lds, st, s, ell, V32);
+  return (int)hipGetLastError();
+}
+
+int launch_finish_str(const SketchState &s, int64_t ell, int64_t n, double coef, const double *frob_part,
+                      int nparts, float *sigma, double *gamma_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_str, dim3(1), dim3(256), 0, st, s, ell, n, coef, frob_part, nparts, sigma,
+                     gamma_dev);
+  return (int)hipGetLastError();
+}
+
+}  // namespace npga

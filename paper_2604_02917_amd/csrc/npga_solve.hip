@@ -411,6 +411,9 @@ __global__ __launch_bounds__(256) void k_cg_init(SolveArgs a) {
     st->cg_cycles = 0;
     st->cg_released = 0;
     st->cg_blocked = 0;
+    st->cg_best_rr = acc[0];
+    st->cg_best_it = 0;
+    st->cg_kkt = 0;
     st->ticket = 0u;
   }
 }

@@ -312,10 +312,13 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     acc2[1] = fma(g[j], g[j], acc2[1]);
     if (i < n && fr[j] == 0.0) dm = minloc_pick(dm, MinLoc{d, i});
   }
+#pragma unroll
+  for (int j = 0; j < E; ++j) acc2[2] = fma(fr[j] * g[j], g[j], acc2[2]);
   red.sum(acc2);
   dm = block_minloc(dm, mbuf, ibuf, mpar);
   double rr_new = acc2[0];
   const double gscale = sqrt(acc2[1] / (double)n) + 1e-300;
+  const double gs2 = acc2[2];  // ||g_S||^2 on the free entries
 
   // (3) face changes once the face problem is nearly solved
   const bool nearly = rr_new <= 1e-12 * st->cg_rr0;
@@ -342,10 +345,24 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     rr_new = acc3[0];
   }
 
-  // (4) stopping test of Sec. 3.1 on the maintained gradient
+  // (4) stopping tests: the KKT conditions hold to rounding on the face
+  // (projected gradient below 1e-12 of the gradient, no fixed index with a
+  // negative reduced cost, return multiplier of the right sign), or the
+  // residual of Sec. 3.1 on the maintained gradient is below tol
   const int it = st->cg_iter + 1;
+  const bool kkt = !restart && rr_new <= 1e-20 * gs2 && dm.v >= -1e-12 * gscale &&
+                   !(active && nu < 0.0);
+  // stagnation: no halving of ||r||^2 for 60 iterations ends the round (the
+  // host re-anchors the gradient in float64 and starts the next round)
+  double best = st->cg_best_rr;
+  int best_it = st->cg_best_it;
+  if (restart || rr_new < 0.5 * best) {
+    best = rr_new;
+    best_it = st->cg_iter + 1;
+  }
+  const bool stalled = (st->cg_iter + 1) - best_it > 60;
   bool stop = false;
-  if (it % st->check_every == 0) {
+  if (it % st->check_every == 0 || kkt || stalled) {
     double w[E];
     const double alpha = st->alpha;
 #pragma unroll
@@ -372,11 +389,12 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
       st->proj_flags |= pr.flags;
       if (!isfinite(res)) {
         st->done = kNumeric;
-      } else if (res <= st->tol) {
+      } else if (kkt || stalled) {
         st->done = kConverged;
+        st->cg_kkt = kkt ? 1 : 0;
       }
     }
-    stop = !isfinite(res) || res <= st->tol;
+    stop = !isfinite(res) || kkt || stalled;
   }
   if (!stop && it >= st->max_iter && tid == 0) st->done = kMaxIter;
 
@@ -397,6 +415,8 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   if (tid == 0) {
     st->cg_iter = it;
     st->cg_rr = rr_new;
+    st->cg_best_rr = best;
+    st->cg_best_it = best_it;
     if (restart) {
       st->cg_rr0 = rr_new;
       st->cg_cycles += 1;

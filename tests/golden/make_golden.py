@@ -28,7 +28,50 @@ def panel_digest(Rt):
     return hashlib.sha256(np.ascontiguousarray(Rt).tobytes()).hexdigest()
 
 
+def make_c3():
+    """STR workload: the c2 factor, Gaussian sketch k = 4096 (seed 3),
+    ell = 512, gamma = 1e-4 trace(Y Y^T)/n; oracle STR model from the same S."""
+    from oracle import sketch as osketch
+    spec = gen.SPECS["c2"]
+    t0 = time.time()
+    Rt = gen.returns_TxN(spec)
+    r = gen.target_return(spec, Rt)
+    mu, L = ofactor.build_factor(Rt.T)
+    S = gen.gaussian_sketch(spec.T, 4096, seed=gen.factor_model.SKETCH_SEED_C3)
+    s_digest = panel_digest(S)
+    Y = osketch.sketch(L, S.astype(np.float64).T)
+    del S
+    print(f"c3: sketch {time.time() - t0:.1f}s", flush=True)
+    L_eff, sig, gamma = osketch.str_factor(Y, 512, 1e-4)
+    print(f"c3: svd {time.time() - t0:.1f}s", flush=True)
+    Q = L_eff @ L_eff.T + gamma * np.eye(spec.n)
+    out = exact_mv(Q, mu, r, fista_tol=1e-10)
+    x = out["x"]
+    rep = qp.kkt_report(2 * Q, np.zeros(spec.n), mu, r, x, out["lam"], out["nu"])
+    assert qp.certificate_ok(rep, tol_stat=1e-9, tol_feas=1e-12, r_scale=np.abs(mu).max()), rep
+    f_str = factor_objective(L_eff, gamma, x)
+    f_full_at_str = factor_objective(L, 0.0, x)
+    with open(os.path.join(HERE, "c2_solution.json")) as fh:
+        f_full = json.load(fh)["objective"]
+    doc = {
+        "workload": "c3", "n": spec.n, "T": spec.T, "k": 4096, "ell": 512, "ridge_coef": 1e-4,
+        "sketch_seed": gen.factor_model.SKETCH_SEED_C3, "r": r,
+        "panel_sha256": panel_digest(Rt), "sketch_sha256": s_digest,
+        "gamma": gamma, "sigma": [float(v) for v in sig[:512]], "sigma_513": float(sig[512]),
+        "objective": f_str, "lambda": out["lam"], "nu": out["nu"],
+        "support": int((x > 0).sum()), "kkt": rep,
+        "full_model_objective_of_str_x": f_full_at_str, "full_model_gap": qp.gap(f_full_at_str, f_full),
+        "x": [float(v) for v in x],
+    }
+    path = os.path.join(HERE, "c3_solution.json")
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    print(f"wrote {path}: f*={f_str:.6e} gap={doc['full_model_gap']:.4f} ({time.time() - t0:.1f}s)", flush=True)
+
+
 def make(name):
+    if name == "c3":
+        return make_c3()
     spec = gen.SPECS[name]
     t0 = time.time()
     Rt = gen.returns_TxN(spec)
