@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--path", default="gemv", choices=["gemv", "syrk", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-syrk-compare", action="store_true")
+    ap.add_argument("--no-str", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -197,6 +198,40 @@ def main():
             "symv_effective_GBs": 4.0 * n * n / (s_last["sweep_ms"] * 1e-3) / 1e9 if s_last["sweep_ms"] else None,
             "objective": s_last["objective"],
             "status": s_last["status_name"],
+        }
+    # Sketch-truncate-ridge workload (k = 4096, ell = 512, gamma = 1e-4 tr(YY^T)/n):
+    # build time, STR solve and the full-model gap of Sec. 5.1, beside the timed path
+    if not args.no_str:
+        from gen.factor_model import SKETCH_SEED_C3
+        S = gen.gaussian_sketch(T, 4096, seed=SKETCH_SEED_C3)
+        Sd = torch.from_numpy(S).to(dev)
+        del S
+        L, mu = npga.build_factor(R)
+        builds = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            Leff, sigma, gamma = npga.sketch_str(L, Sd, 512, ridge_coef=1e-4)
+            torch.cuda.synchronize()
+            builds.append((time.perf_counter() - tb) * 1e3)
+        del Sd
+        xs_, info_str = npga.solve(Leff, mu, r, gamma=gamma)
+        _, f_full_str = npga.gradient(L, xs_, 0.0)
+        f_full = last["objective"]
+        out["str"] = {
+            "workload": "c2 factor, Gaussian sketch k=4096 (seed 3), ell=512, gamma=1e-4 tr(YY^T)/n",
+            "build_ms": builds[-1],
+            "time_to_tol_s": info_str["time_to_tol_ms"] / 1e3,
+            "solve_ms_incl_refinement": info_str["time_ms"],
+            "iters_to_tol": info_str["iters"],
+            "refine_iters": info_str["refine_iters"],
+            "sweep_ms": info_str["sweep_ms"],
+            "gamma": gamma,
+            "sigma_1": float(sigma[0].item()),
+            "sigma_512": float(sigma[-1].item()),
+            "objective_str": info_str["objective"],
+            "full_model_gap": max(f_full_str - f_full, 0.0) / max(abs(f_full), 1e-12),
+            "status": info_str["status_name"],
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Rt, r, grad_evals, args.cpu_seconds)

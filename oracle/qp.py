@@ -44,6 +44,10 @@ def face_solve(H, c, mu, r, free, active):
         rhs[k + 1] = r
     try:
         sol = np.linalg.solve(K, rhs)
+        if np.all(np.isfinite(sol)):
+            # one step of iterative refinement (ill-conditioned faces, e.g. a
+            # rank-ell covariance plus a small ridge)
+            sol = sol + np.linalg.solve(K, rhs - K @ sol)
     except np.linalg.LinAlgError:
         return None
     if not np.all(np.isfinite(sol)):
