@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-syrk-compare", action="store_true")
     ap.add_argument("--no-str", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -199,6 +200,30 @@ def main():
             "objective": s_last["objective"],
             "status": s_last["status_name"],
         }
+    # bfloat16 storage of L (float32 accumulation): the same solve reading
+    # half the bytes; quantisation gap measured in the float32 model
+    if not args.no_bf16:
+        L, mu = npga.build_factor(R)
+        Lb = npga.to_bf16(L)
+        bi = []
+        for _ in range(2):
+            xb, info_b = npga.solve(Lb, mu, r)
+            bi.append(info_b)
+        b_last = bi[-1]
+        _, f32_at_b = npga.gradient(L, xb, 0.0)
+        out["bf16_path"] = {
+            "time_to_tol_s": b_last["time_to_tol_ms"] / 1e3,
+            "solve_ms_incl_refinement": b_last["time_ms"],
+            "iters_to_tol": b_last["iters"],
+            "refine_iters": b_last["refine_iters"],
+            "sweep_ms": b_last["sweep_ms"],
+            "sweep_GBs": 2.0 * n * T / (b_last["sweep_ms"] * 1e-3) / 1e9 if b_last["sweep_ms"] else None,
+            "objective_bf16_model": b_last["objective"],
+            "quantisation_gap_vs_f32_model": max(f32_at_b - last["objective"], 0.0) / last["objective"],
+            "max_abs_x_diff_vs_f32": float((xb - x).abs().max().item()),
+            "status": b_last["status_name"],
+        }
+        del Lb
     # Sketch-truncate-ridge workload (k = 4096, ell = 512, gamma = 1e-4 tr(YY^T)/n):
     # build time, STR solve and the full-model gap of Sec. 5.1, beside the timed path
     if not args.no_str:

@@ -66,13 +66,21 @@ typedef enum npga_path {
 
 /* Effective factor L_eff and ridge gamma of the unified model
  * (Sec. 3.1, Tab. model-mapping): L (full), L Phi (sketch) or U_ell S_ell (STR). */
+typedef enum npga_dtype {
+  NPGA_F32 = 0,   /* float32 factor                                            */
+  NPGA_BF16 = 1   /* bfloat16 factor (16-bit storage, float32 accumulation)    */
+} npga_dtype;
+
 typedef struct npga_factor {
   int64_t n;         /* assets: 1 <= n <= NPGA_MAX_N                              */
   int64_t cols;      /* columns of L_eff (T, s or ell), >= 1                      */
   int64_t ld;        /* leading dimension in elements, >= n, multiple of 4       */
-  const float *L;    /* device, column-major n x cols, float32                    */
+  const void *L;     /* device, column-major n x cols: float32, or bfloat16 bits
+                        (16-byte aligned for float32, 8-byte for bfloat16)        */
   const double *mu;  /* device, n expected returns (float64)                      */
   double gamma;      /* ridge >= 0                                                */
+  int32_t dtype;     /* npga_dtype of L; the covariance (SYRK) path needs F32     */
+  int32_t reserved;
 } npga_factor;
 
 /* Solver options (host).  npga_default_options fills the defaults shown. */
@@ -149,6 +157,15 @@ size_t npga_build_factor_workspace_size(int64_t n, int64_t T);
 int npga_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr,
                       float *L, int64_t ldl, double *mu_out, void *ws, size_t ws_bytes,
                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * npga_to_bf16 - Lb = bfloat16(L) by round-to-nearest-even, the storage of
+ * a reduced-precision factor (sweeps then read half the bytes and
+ * accumulate in float32).  L device float32 n x T (ld, multiple of 4), Lb
+ * device 16-bit n x T (ldb >= n, multiple of 4, 8-byte aligned).
+ * ------------------------------------------------------------------------- */
+int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,
+                 hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * npga_solve - Algorithm 1 (NPGA, Sec. 3.1) with the fixed step

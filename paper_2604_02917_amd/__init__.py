@@ -16,5 +16,6 @@ from .api import (  # noqa: F401
     solve,
     spectral_norm_sq,
     syrk,
+    to_bf16,
     status_string,
 )

@@ -32,7 +32,8 @@ class NpgaError(RuntimeError):
 
 class _Factor(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
-                ("L", ctypes.c_void_p), ("mu", ctypes.c_void_p), ("gamma", ctypes.c_double)]
+                ("L", ctypes.c_void_p), ("mu", ctypes.c_void_p), ("gamma", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
@@ -76,6 +77,7 @@ def _load():
         "npga_gradient": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp, sz, vp]),
         "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, vp, vp, sz, vp]),
         "npga_syrk": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
+        "npga_to_bf16": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
         "npga_build_factor_workspace_size": (sz, [i64, i64]),
         "npga_build_factor": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]),
         "npga_sketch_workspace_size": (sz, [i64, i64, i64, i64]),
@@ -145,14 +147,15 @@ def _check(code, where):
 
 
 def _as_colmajor(M):
-    """(cols, n) float32 CUDA tensor -> (tensor with row stride ld, n, cols, ld)."""
-    if M.dim() != 2 or M.dtype != torch.float32 or not M.is_cuda:
-        raise ValueError("expected a 2-D float32 CUDA tensor of shape (cols, n)")
+    """(cols, n) float32 or bfloat16 CUDA tensor -> (tensor with row stride ld, n, cols, ld)."""
+    if M.dim() != 2 or M.dtype not in (torch.float32, torch.bfloat16) or not M.is_cuda:
+        raise ValueError("expected a 2-D float32 or bfloat16 CUDA tensor of shape (cols, n)")
     cols, n = M.shape
     ld = (n + 3) // 4 * 4
-    if M.is_contiguous() and ld == n and M.data_ptr() % 16 == 0:
+    align = 16 if M.dtype == torch.float32 else 8
+    if M.is_contiguous() and ld == n and M.data_ptr() % align == 0:
         return M, n, cols, ld
-    buf = torch.zeros((cols, ld), dtype=torch.float32, device=M.device)
+    buf = torch.zeros((cols, ld), dtype=M.dtype, device=M.device)
     buf[:, :n].copy_(M)
     return buf, n, cols, ld
 
@@ -162,7 +165,8 @@ def _workspace(nbytes, device):
 
 
 def _factor(Lb, n, cols, ld, mu, gamma):
-    return _Factor(n, cols, ld, Lb.data_ptr(), mu.data_ptr(), float(gamma))
+    dtype = 1 if Lb.dtype == torch.bfloat16 else 0
+    return _Factor(n, cols, ld, Lb.data_ptr(), mu.data_ptr(), float(gamma), dtype, 0)
 
 
 def build_factor(R_TxN):
@@ -263,6 +267,17 @@ def sketch_str(L_TxN, S_kxT, ell, ridge_coef=1e-4, seed=0):
                                 _ptr(Leff), ldle, _ptr(sigma), ctypes.byref(gam), _ptr(ws), ws.numel(),
                                 _stream()), "npga_sketch_str")
     return (Leff if ldle == n else Leff[:, :n]), sigma, gam.value
+
+
+def to_bf16(L_TxN):
+    """bfloat16 copy of a (T, n) float32 factor, rounded to nearest even by
+    the library's conversion kernel.  Returns a (T, n) torch.bfloat16 tensor."""
+    Lb, n, T, ld = _as_colmajor(L_TxN)
+    if Lb.dtype != torch.float32:
+        raise ValueError("to_bf16 expects a float32 factor")
+    out = torch.empty((T, ld), dtype=torch.bfloat16, device=Lb.device)
+    _check(_lib.npga_to_bf16(_ptr(Lb), n, T, ld, _ptr(out), ld, _stream()), "npga_to_bf16")
+    return out if ld == n else out[:, :n]
 
 
 def syrk(L_TxN):

@@ -125,7 +125,8 @@ bool factor_valid(const npga_factor *f) {
   if (!f || !f->L || !f->mu) return false;
   if (f->n < 1 || f->n > NPGA_MAX_N || f->cols < 1) return false;
   if (f->ld < f->n || (f->ld % 4) != 0) return false;
-  if (!aligned(f->L, 16) || !aligned(f->mu, 8)) return false;
+  if (f->dtype != NPGA_F32 && f->dtype != NPGA_BF16) return false;
+  if (!aligned(f->L, f->dtype == NPGA_F32 ? 16 : 8) || !aligned(f->mu, 8)) return false;
   if (!is_fin(f->gamma) || f->gamma < 0) return false;
   return true;
 }
@@ -142,6 +143,7 @@ Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
   Carved c{};
   SolveArgs &a = c.a;
   a.L = f->L;
+  a.dtype = f->dtype;
   a.ld = f->ld;
   a.n = f->n;
   a.cols = f->cols;
@@ -328,6 +330,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   if (opt) o = *opt;
   if (!factor_valid(f) || !x || !is_fin(r) || !options_valid(o)) return NPGA_ERR_INVALID;
   const int path = resolve_path(o.path, f->n, f->cols);
+  if (path == NPGA_PATH_SYRK && f->dtype != NPGA_F32) return NPGA_ERR_UNSUPPORTED;
   const SolveLayout lay = npga::solve_layout(f->n, f->cols, path);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   DevState *pin = pinned_status();
@@ -369,7 +372,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
 
   // explicit covariance (SYRK path): Sigma = L L^T once
   if (path == NPGA_PATH_SYRK)
-    LAUNCHCHK(npga::launch_syrk(f->L, f->n, f->cols, f->ld, c.sigma, c.lds, stream));
+    LAUNCHCHK(npga::launch_syrk(static_cast<const float *>(f->L), f->n, f->cols, f->ld, c.sigma, c.lds, stream));
 
   // step size: power method on L_eff (Sec. 3.1 Remark), alpha = 1/(safety L_f_hat)
   LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, o.seed, stream));
@@ -486,7 +489,7 @@ int npga_project(const double *v, const double *mu, int64_t n, double r, double 
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
   DevState *st = reinterpret_cast<DevState *>(static_cast<char *>(ws) + lay.off_state);
-  npga_factor f{n, 1, (n + 3) / 4 * 4, reinterpret_cast<const float *>(ws), mu, 0.0};
+  npga_factor f{n, 1, (n + 3) / 4 * 4, ws, mu, 0.0, NPGA_F32, 0};
   pin[2] = initial_state(&f, r, o);
   HIPCHK(hipMemcpyAsync(st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
   SolveArgs a{};
@@ -566,6 +569,15 @@ int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, in
     return NPGA_ERR_INVALID;
   if (!aligned(L, 16) || !aligned(Sigma, 16)) return NPGA_ERR_INVALID;
   LAUNCHCHK(npga::launch_syrk(L, n, T, ld, Sigma, lds, stream));
+  return NPGA_OK;
+}
+
+int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,
+                 hipStream_t stream) {
+  if (!L || !Lb || n < 1 || T < 1 || ld < n || ldb < n || (ld % 4) != 0 || (ldb % 4) != 0)
+    return NPGA_ERR_INVALID;
+  if (!aligned(L, 16) || !aligned(Lb, 8)) return NPGA_ERR_INVALID;
+  LAUNCHCHK(npga::launch_to_bf16(L, n, T, ld, Lb, ldb, stream));
   return NPGA_OK;
 }
 

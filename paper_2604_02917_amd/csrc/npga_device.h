@@ -12,6 +12,33 @@ namespace npga {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Element types of the factor L: float32, or bfloat16 kept as its 16 bits.
+struct bf16_t {
+  uint16_t bits;
+};
+
+// Four consecutive entries of a column as float32 (the address is 16-byte
+// aligned for float32 and 8-byte aligned for bfloat16).
+template <typename TL>
+__device__ __forceinline__ f4 load4_nt(const TL *p);
+
+template <>
+__device__ __forceinline__ f4 load4_nt<float>(const float *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+}
+
+template <>
+__device__ __forceinline__ f4 load4_nt<bf16_t>(const bf16_t *p) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 w = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p));
+  f4 r;
+  r.x = __uint_as_float(w.x << 16);
+  r.y = __uint_as_float(w.x & 0xffff0000u);
+  r.z = __uint_as_float(w.y << 16);
+  r.w = __uint_as_float(w.y & 0xffff0000u);
+  return r;
+}
+
 __device__ __forceinline__ float wave_sum_f32(float v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

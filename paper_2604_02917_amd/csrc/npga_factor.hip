@@ -130,6 +130,30 @@ __global__ __launch_bounds__(256) void k_center(const float *R, int64_t n, int64
   }
 }
 
+// float32 -> bfloat16 with round-to-nearest-even (NaN kept quiet): the
+// storage format of the reduced-precision factor.
+__global__ __launch_bounds__(256) void k_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb,
+                                                 int64_t ldb) {
+  const int64_t total = n * T;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+    const int64_t t = q / n, i = q - t * n;
+    const uint32_t u = __float_as_uint(L[i + t * ld]);
+    uint16_t b;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      b = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+      const uint32_t lsb = (u >> 16) & 1u;
+      b = (uint16_t)((u + 0x7fffu + lsb) >> 16);
+    }
+    Lb[i + t * ldb] = b;
+  }
+}
+
+int launch_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, s, L, n, T, ld, Lb, ldb);
+  return (int)hipGetLastError();
+}
+
 #define FACTOR_SLOT_SWITCH(slots, CALL) \
   switch (slots) {                     \
     case 1: CALL(1); break;            \

@@ -91,7 +91,8 @@ struct alignas(64) HostStatus {
 
 // Everything a solver kernel needs, passed by value.
 struct SolveArgs {
-  const float *L;      // n x cols, leading dim ld (float32)
+  const void *L;       // n x cols, leading dim ld (float32 or bfloat16 bits)
+  int32_t dtype;       // NPGA_F32 or NPGA_BF16
   int64_t ld;
   int64_t n;
   int64_t cols;
@@ -162,6 +163,8 @@ int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s
 int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s);
 
 // Factor build.
+int launch_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,
+                   hipStream_t s);
 int launch_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *L, int64_t ldl,
                         double *mu_out, double *part, int grid, double *nonfinite,
                         hipStream_t s);

@@ -15,16 +15,16 @@
 
 namespace npga {
 
-template <int E>
-__device__ __forceinline__ void load_col_masked(const float *L, int64_t ld, int64_t n, int64_t col, int lane,
+template <int E, typename TL>
+__device__ __forceinline__ void load_col_masked(const TL *L, int64_t ld, int64_t n, int64_t col, int lane,
                                                 f4 (&c)[E]) {
-  const f4 *p = reinterpret_cast<const f4 *>(L + col * ld) + lane;
+  const TL *p = L + col * ld + 4 * lane;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t row0 = 4 * lane + 256 * j;
     f4 v = f4{0.f, 0.f, 0.f, 0.f};
     if (row0 < n) {
-      v = __builtin_nontemporal_load(p + 64 * j);
+      v = load4_nt<TL>(p + 256 * j);
       if (row0 + 1 >= n) v.y = 0.f;
       if (row0 + 2 >= n) v.z = 0.f;
       if (row0 + 3 >= n) v.w = 0.f;
@@ -33,8 +33,8 @@ __device__ __forceinline__ void load_col_masked(const float *L, int64_t ld, int6
   }
 }
 
-template <int E>
-__global__ __launch_bounds__(256) void k_precise_u(const float *L, int64_t ld, int64_t n, int64_t cols,
+template <int E, typename TL>
+__global__ __launch_bounds__(256) void k_precise_u(const TL *L, int64_t ld, int64_t n, int64_t cols,
                                                    const double *x, double *u) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_precise_u(const float *L, int64_t ld, i
     }
   for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < cols; col += W) {
     f4 c[E];
-    load_col_masked<E>(L, ld, n, col, lane, c);
+    load_col_masked<E, TL>(L, ld, n, col, lane, c);
     double d = 0.0;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_precise_u(const float *L, int64_t ld, i
   }
 }
 
-template <int E>
-__global__ __launch_bounds__(256) void k_precise_g(const float *L, int64_t ld, int64_t n, int64_t cols,
+template <int E, typename TL>
+__global__ __launch_bounds__(256) void k_precise_g(const TL *L, int64_t ld, int64_t n, int64_t cols,
                                                    const double *u, double *part, int64_t ldp) {
   __shared__ double sh[256 * E];
   const int lane = threadIdx.x & 63;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_precise_g(const float *L, int64_t ld, i
   for (int j = 0; j < 4 * E; ++j) g[j] = 0.0;
   for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < cols; col += W) {
     f4 c[E];
-    load_col_masked<E>(L, ld, n, col, lane, c);
+    load_col_masked<E, TL>(L, ld, n, col, lane, c);
     const double uc = u[col];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -132,14 +132,25 @@ __global__ __launch_bounds__(256) void k_precise_reduce(const double *part, int 
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
                             double *part, int slots, hipStream_t s) {
   const int G = sweep_grid_for(a.cols);
-#define CALL(E) hipLaunchKernelGGL(k_precise_u<E>, dim3(G), dim3(256), 0, s, a.L, a.ld, a.n, a.cols, x, u_out)
-  PRECISE_SLOT_SWITCH(slots, CALL)
+  if (a.dtype == NPGA_BF16) {
+    const bf16_t *L = static_cast<const bf16_t *>(a.L);
+#define CALL(E) hipLaunchKernelGGL((k_precise_u<E, bf16_t>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, x, u_out)
+    PRECISE_SLOT_SWITCH(slots, CALL)
 #undef CALL
-  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
 #define CALL(E) \
-  hipLaunchKernelGGL(k_precise_g<E>, dim3(G), dim3(256), 0, s, a.L, a.ld, a.n, a.cols, u_out, part, a.ldp)
-  PRECISE_SLOT_SWITCH(slots, CALL)
+  hipLaunchKernelGGL((k_precise_g<E, bf16_t>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, u_out, part, a.ldp)
+    PRECISE_SLOT_SWITCH(slots, CALL)
 #undef CALL
+  } else {
+    const float *L = static_cast<const float *>(a.L);
+#define CALL(E) hipLaunchKernelGGL((k_precise_u<E, float>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, x, u_out)
+    PRECISE_SLOT_SWITCH(slots, CALL)
+#undef CALL
+#define CALL(E) \
+  hipLaunchKernelGGL((k_precise_g<E, float>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, u_out, part, a.ldp)
+    PRECISE_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  }
   if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
   hipLaunchKernelGGL(k_precise_reduce, dim3((unsigned)((a.n + 63) / 64)), dim3(256), 0, s, part, G, a.ldp,
                      a.n, g_out);

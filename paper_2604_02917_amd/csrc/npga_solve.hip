@@ -163,7 +163,7 @@ __global__ void k_phase(DevState *st, double tol, int32_t max_iter, int32_t rest
 // --------------------------------------------------------------------------
 // fused gradient sweep
 // --------------------------------------------------------------------------
-template <int E>
+template <int E, typename TL>
 __global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
   if (a.st->done != kRunning) return;
   __shared__ f4 sh[4 * 64 * E];
@@ -183,12 +183,13 @@ __global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
   }
   double usq = 0.0;
 
+  const TL *Lt = static_cast<const TL *>(a.L);
   auto load = [&](f4(&c)[E], int64_t col) {
-    const f4 *p = reinterpret_cast<const f4 *>(a.L + col * a.ld) + lane;
+    const TL *p = Lt + col * a.ld + 4 * lane;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int64_t row0 = 4 * lane + 256 * j;
-      c[j] = (row0 < n) ? __builtin_nontemporal_load(p + 64 * j) : f4{0.f, 0.f, 0.f, 0.f};
+      c[j] = (row0 < n) ? load4_nt<TL>(p + 256 * j) : f4{0.f, 0.f, 0.f, 0.f};
     }
     if (ragged) {
 #pragma unroll
@@ -502,9 +503,15 @@ int launch_random_unit(double *u, float *xs, int64_t n, uint64_t seed, hipStream
 }
 
 int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
-#define CALL(E) hipLaunchKernelGGL(k_sweep<E>, dim3(a.sweep_grid), dim3(256), 0, s, a)
-  NPGA_SLOT_SWITCH(slots, CALL)
+  if (a.dtype == NPGA_BF16) {
+#define CALL(E) hipLaunchKernelGGL((k_sweep<E, bf16_t>), dim3(a.sweep_grid), dim3(256), 0, s, a)
+    NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
+  } else {
+#define CALL(E) hipLaunchKernelGGL((k_sweep<E, float>), dim3(a.sweep_grid), dim3(256), 0, s, a)
+    NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  }
   return (int)hipGetLastError();
 }
 

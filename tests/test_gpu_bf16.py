@@ -1,0 +1,75 @@
+"""bfloat16 factor storage (float32 accumulation): conversion, fused sweep
+and solve against the FP64 oracle run on the same bfloat16 values (solver
+error), plus the quantisation error against the oracle on the float32
+factor (reported, loosely bounded)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import gen
+from oracle import factor as ofactor
+from oracle import quantize as oq
+from oracle.reference import exact_mv_factor, factor_objective
+from tests.gpu_util import U32, banner, spec_with, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def npga():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_02917_amd as p
+    return p
+
+
+@pytest.mark.parametrize("n,T", [(64, 256), (257, 1031), (5440, 777)])
+def test_to_bf16_bit_exact(npga, n, T):
+    spec = spec_with("c2", n, T, seed=60 + n)
+    Rt = gen.returns_TxN(spec)
+    Rt[3, 5] = np.float32(1.00390625)   # a rounding tie
+    Rb = npga.to_bf16(to_dev(Rt))
+    bits = Rb.view(torch.int16).cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(bits, oq.to_bf16_bits(Rt))
+
+
+@pytest.mark.parametrize("n,T", [(64, 256), (1000, 4000), (5440, 2000)])
+def test_bf16_gradient(npga, n, T):
+    spec = spec_with("c2", n, T, seed=70 + n)
+    Rt = gen.returns_TxN(spec)
+    x = gen.random_vector(n, 5, "uniform")
+    x = (x / x.sum()).astype(np.float32)
+    g, f = npga.gradient(npga.to_bf16(to_dev(Rt)), to_dev(x), 0.0)
+    L = oq.round_to_bf16(Rt).reshape(Rt.shape).T        # n x T, the bfloat16 values
+    u = L.T @ x.astype(np.float64)
+    g_ref = 2 * (L @ u)
+    B = 2 * (np.abs(L) @ (np.abs(L).T @ np.abs(x.astype(np.float64))))
+    assert np.all(np.abs(g.cpu().numpy() - g_ref) <= (n + T) * U32 * B)
+    assert abs(f - u @ u) <= 1e-5 * (u @ u)
+
+
+@pytest.mark.parametrize("n,T,q", [(64, 256, 0.5), (300, 3000, 0.6), (1000, 6000, 0.6)])
+def test_bf16_solve(npga, n, T, q):
+    banner(f"bf16 solve n={n} T={T}")
+    spec = spec_with("c2", n, T, seed=80 + n)
+    Rt = gen.returns_TxN(spec)
+    mu_o, L_o = ofactor.build_factor(Rt.T)
+    r = float(np.quantile(Rt.astype(np.float64).mean(axis=0), q))
+    L, mu = npga.build_factor(to_dev(Rt))
+    Lb = npga.to_bf16(L)
+    x, info = npga.solve(Lb, mu, r)
+    assert info["status"] == 0 and info["refined"] == 1, info
+    xg = x.cpu().numpy().astype(np.float64)
+    # solver error: oracle on the same bfloat16 values of the float32 factor
+    Lq = oq.round_to_bf16(L_o.astype(np.float32).T).reshape(L_o.shape[1], n).T
+    ref = exact_mv_factor(Lq, 0.0, mu_o, r)
+    fq = factor_objective(Lq, 0.0, xg)
+    assert abs(fq - ref["f"]) <= 1e-6 * ref["f"]
+    assert np.abs(xg - ref["x"]).max() <= 1e-5
+    # quantisation error: against the oracle on the float32-exact factor
+    full = exact_mv_factor(L_o, 0.0, mu_o, r)
+    f_full = factor_objective(L_o, 0.0, xg)
+    gap = (f_full - full["f"]) / full["f"]
+    banner(f"bf16 n={n}: quantisation gap {gap:.2e}, max|x - x*_fp32| {np.abs(xg - full['x']).max():.2e}")
+    assert 0.0 <= gap <= 1e-2
