@@ -16,8 +16,11 @@
  *     leading dimension ld is at p[i + j * ld].  For the factor L (n x T)
  *     period t's n-vector is contiguous.
  *   - Float32 matrices must be 16-byte aligned and ld must be a multiple of
- *     4 (the kernels load float4).  The caller's buffer must hold ld * cols
- *     elements; rows n..ld-1 are never read as data.
+ *     4 (the kernels load float4).  Bfloat16 factors must be 8-byte aligned
+ *     with ld a multiple of 4; with 16-byte alignment and ld a multiple of 8
+ *     the gradient sweep loads 8 entries per lane (the fast layout).  The
+ *     caller's buffer must hold ld * cols elements; rows n..ld-1 may be read
+ *     but are masked and never used as data.
  *   - All work is enqueued on `stream`.  Entry points that fill a host
  *     result struct synchronise `stream` before returning.
  *   - The library never allocates device memory.  Scratch space is the

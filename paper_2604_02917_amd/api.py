@@ -151,8 +151,10 @@ def _as_colmajor(M):
     if M.dim() != 2 or M.dtype not in (torch.float32, torch.bfloat16) or not M.is_cuda:
         raise ValueError("expected a 2-D float32 or bfloat16 CUDA tensor of shape (cols, n)")
     cols, n = M.shape
-    ld = (n + 3) // 4 * 4
-    align = 16 if M.dtype == torch.float32 else 8
+    # float32: float4 loads; bfloat16: 8 entries (16 bytes) per load
+    q = 4 if M.dtype == torch.float32 else 8
+    ld = (n + q - 1) // q * q
+    align = 16
     if M.is_contiguous() and ld == n and M.data_ptr() % align == 0:
         return M, n, cols, ld
     buf = torch.zeros((cols, ld), dtype=M.dtype, device=M.device)
@@ -275,9 +277,10 @@ def to_bf16(L_TxN):
     Lb, n, T, ld = _as_colmajor(L_TxN)
     if Lb.dtype != torch.float32:
         raise ValueError("to_bf16 expects a float32 factor")
-    out = torch.empty((T, ld), dtype=torch.bfloat16, device=Lb.device)
-    _check(_lib.npga_to_bf16(_ptr(Lb), n, T, ld, _ptr(out), ld, _stream()), "npga_to_bf16")
-    return out if ld == n else out[:, :n]
+    ldb = (n + 7) // 8 * 8
+    out = torch.empty((T, ldb), dtype=torch.bfloat16, device=Lb.device)
+    _check(_lib.npga_to_bf16(_ptr(Lb), n, T, ld, _ptr(out), ldb, _stream()), "npga_to_bf16")
+    return out if ldb == n else out[:, :n]
 
 
 def syrk(L_TxN):

@@ -256,6 +256,121 @@ __global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
   if (threadIdx.x == 0) a.usq_part[blockIdx.x] = ((shu[0] + shu[1]) + shu[2]) + shu[3];
 }
 
+// Bfloat16 sweep with 16-byte loads: lane l holds rows 8l + 512j .. +7 of
+// slot j, kept as raw 16-bit pairs in the double buffer (half the registers
+// of converted values) and widened to float32 only when used.  Same partial
+// layout as k_sweep: the float4 group q = 2l + h + 128j covers rows 4q..4q+3.
+// Requires 16-byte alignment of L and ld % 8 == 0 (checked by the launcher);
+// rows n..ld-1 of a column are read and masked to zero.
+template <int E2, bool RAGGED>
+__global__ __launch_bounds__(256) void k_sweep_b16(SolveArgs a) {
+  constexpr int E = 2 * E2;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  if (a.st->done != kRunning) return;
+  __shared__ f4 sh[4 * 64 * E];
+  __shared__ double shu[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = a.n;
+  const int64_t W = (int64_t)gridDim.x * 4;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+
+  f4 xr[E], g[E];
+#pragma unroll
+  for (int j = 0; j < E2; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      xr[2 * j + h] = *reinterpret_cast<const f4 *>(a.xs + 8 * lane + 512 * j + 4 * h);
+      g[2 * j + h] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  double usq = 0.0;
+
+  const uint16_t *Lt = static_cast<const uint16_t *>(a.L);
+  auto load = [&](u4(&c)[E2], int64_t col) {
+    const uint16_t *p = Lt + col * a.ld + 8 * lane;
+#pragma unroll
+    for (int j = 0; j < E2; ++j) {
+      const int64_t row0 = 8 * lane + 512 * j;
+      c[j] = (row0 < n) ? __builtin_nontemporal_load(reinterpret_cast<const u4 *>(p + 512 * j)) : u4{0u, 0u, 0u, 0u};
+    }
+  };
+  // rows past n inside a loaded 16-byte group (n % 8 != 0 only): masked at
+  // use, so the mask never waits on a load still in flight
+  auto keep = [&](int j, int w) -> unsigned int {
+    if (!RAGGED) return 0xffffffffu;
+    const int64_t row = 8 * lane + 512 * j + 2 * w;
+    return row + 1 < n ? 0xffffffffu : (row < n ? 0x0000ffffu : 0u);
+  };
+  auto lo = [](unsigned int w) { return __uint_as_float(w << 16); };
+  auto hi = [](unsigned int w) { return __uint_as_float(w & 0xffff0000u); };
+  int64_t col_cur = 0;
+  auto process = [&](const u4(&c)[E2]) {
+    u4 m[E2];
+#pragma unroll
+    for (int j = 0; j < E2; ++j)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) m[j][w] = c[j][w] & keep(j, w);
+    float d0 = 0.f, d1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < E2; ++j) {
+      d0 = fmaf(lo(m[j][0]), xr[2 * j].x, d0);
+      d1 = fmaf(hi(m[j][0]), xr[2 * j].y, d1);
+      d0 = fmaf(lo(m[j][1]), xr[2 * j].z, d0);
+      d1 = fmaf(hi(m[j][1]), xr[2 * j].w, d1);
+      d0 = fmaf(lo(m[j][2]), xr[2 * j + 1].x, d0);
+      d1 = fmaf(hi(m[j][2]), xr[2 * j + 1].y, d1);
+      d0 = fmaf(lo(m[j][3]), xr[2 * j + 1].z, d0);
+      d1 = fmaf(hi(m[j][3]), xr[2 * j + 1].w, d1);
+    }
+    const float d = wave_sum_f32(d0 + d1);
+    const double ut = a.ua ? a.ua[col_cur] + (double)d : (double)d;
+    usq = fma(ut, ut, usq);
+#pragma unroll
+    for (int j = 0; j < E2; ++j) {
+      g[2 * j].x = fmaf(lo(m[j][0]), d, g[2 * j].x);
+      g[2 * j].y = fmaf(hi(m[j][0]), d, g[2 * j].y);
+      g[2 * j].z = fmaf(lo(m[j][1]), d, g[2 * j].z);
+      g[2 * j].w = fmaf(hi(m[j][1]), d, g[2 * j].w);
+      g[2 * j + 1].x = fmaf(lo(m[j][2]), d, g[2 * j + 1].x);
+      g[2 * j + 1].y = fmaf(hi(m[j][2]), d, g[2 * j + 1].y);
+      g[2 * j + 1].z = fmaf(lo(m[j][3]), d, g[2 * j + 1].z);
+      g[2 * j + 1].w = fmaf(hi(m[j][3]), d, g[2 * j + 1].w);
+    }
+  };
+
+  u4 c0[E2], c1[E2];
+  int64_t col = gw;
+  if (col < a.cols) load(c0, col);
+  while (col < a.cols) {
+    const int64_t col1 = col + W;
+    if (col1 < a.cols) load(c1, col1);
+    col_cur = col;
+    process(c0);
+    if (col1 >= a.cols) break;
+    const int64_t col2 = col1 + W;
+    if (col2 < a.cols) load(c0, col2);
+    col_cur = col1;
+    process(c1);
+    col = col2;
+  }
+
+#pragma unroll
+  for (int j = 0; j < E2; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) sh[wave * 64 * E + 2 * lane + h + 128 * j] = g[2 * j + h];
+  if (lane == 0) shu[wave] = usq;
+  __syncthreads();
+  float *out = a.partials + (int64_t)blockIdx.x * a.ldp;
+  for (int q = threadIdx.x; q < 64 * E; q += 256) {
+    f4 s = sh[q];
+    s += sh[64 * E + q];
+    s += sh[2 * 64 * E + q];
+    s += sh[3 * 64 * E + q];
+    *reinterpret_cast<f4 *>(out + 4 * q) = s;
+  }
+  if (threadIdx.x == 0) a.usq_part[blockIdx.x] = ((shu[0] + shu[1]) + shu[2]) + shu[3];
+}
+
 // Row blocks of 64 sum the sweep partials in a fixed order (deterministic)
 // and assemble the gradient of the current mode.  No cross-workgroup
 // signalling: the serial tail is a separate one-workgroup launch, so the
@@ -504,9 +619,31 @@ int launch_random_unit(double *u, float *xs, int64_t n, uint64_t seed, hipStream
 
 int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
   if (a.dtype == NPGA_BF16) {
-#define CALL(E) hipLaunchKernelGGL((k_sweep<E, bf16_t>), dim3(a.sweep_grid), dim3(256), 0, s, a)
-    NPGA_SLOT_SWITCH(slots, CALL)
+    const bool wide = slots >= 2 && (slots & 1) == 0 && (a.ld & 7) == 0 &&
+                      (reinterpret_cast<uintptr_t>(a.L) & 15) == 0;
+    if (wide) {
+#define CALL(E2)                                                                          \
+  do {                                                                                    \
+    if (a.n & 7) hipLaunchKernelGGL((k_sweep_b16<E2, true>), dim3(a.sweep_grid), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((k_sweep_b16<E2, false>), dim3(a.sweep_grid), dim3(256), 0, s, a);        \
+  } while (0)
+      switch (slots / 2) {
+        case 1: CALL(1); break;
+        case 2: CALL(2); break;
+        case 4: CALL(4); break;
+        case 6: CALL(6); break;
+        case 8: CALL(8); break;
+        case 11: CALL(11); break;
+        case 14: CALL(14); break;
+        case 16: CALL(16); break;
+        default: return (int)hipErrorInvalidValue;
+      }
 #undef CALL
+    } else {
+#define CALL(E) hipLaunchKernelGGL((k_sweep<E, bf16_t>), dim3(a.sweep_grid), dim3(256), 0, s, a)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+    }
   } else {
 #define CALL(E) hipLaunchKernelGGL((k_sweep<E, float>), dim3(a.sweep_grid), dim3(256), 0, s, a)
     NPGA_SLOT_SWITCH(slots, CALL)

@@ -34,19 +34,58 @@ def test_to_bf16_bit_exact(npga, n, T):
     np.testing.assert_array_equal(bits, oq.to_bf16_bits(Rt))
 
 
-@pytest.mark.parametrize("n,T", [(64, 256), (1000, 4000), (5440, 2000)])
+def _check_bf16_gradient(Rt, x, g, f):
+    n, T = Rt.shape[1], Rt.shape[0]
+    L = oq.round_to_bf16(Rt).reshape(Rt.shape).T        # n x T, the bfloat16 values
+    u = L.T @ x.astype(np.float64)
+    g_ref = 2 * (L @ u)
+    B = 2 * (np.abs(L) @ (np.abs(L).T @ np.abs(x.astype(np.float64))))
+    assert np.all(np.abs(g - g_ref) <= (n + T) * U32 * B)
+    assert abs(f - u @ u) <= 1e-5 * (u @ u)
+
+
+# 64: 8-byte loads (one 256-row slot); the rest: 16-byte loads, with n % 8
+# != 0 (rows past n masked inside a load) at 300, 1001, 2053 and 5437
+@pytest.mark.parametrize("n,T", [(64, 256), (300, 700), (1000, 4000), (1001, 3000), (2053, 1500),
+                                 (5437, 1200), (5440, 2000)])
 def test_bf16_gradient(npga, n, T):
     spec = spec_with("c2", n, T, seed=70 + n)
     Rt = gen.returns_TxN(spec)
     x = gen.random_vector(n, 5, "uniform")
     x = (x / x.sum()).astype(np.float32)
     g, f = npga.gradient(npga.to_bf16(to_dev(Rt)), to_dev(x), 0.0)
-    L = oq.round_to_bf16(Rt).reshape(Rt.shape).T        # n x T, the bfloat16 values
-    u = L.T @ x.astype(np.float64)
-    g_ref = 2 * (L @ u)
-    B = 2 * (np.abs(L) @ (np.abs(L).T @ np.abs(x.astype(np.float64))))
-    assert np.all(np.abs(g.cpu().numpy() - g_ref) <= (n + T) * U32 * B)
-    assert abs(f - u @ u) <= 1e-5 * (u @ u)
+    _check_bf16_gradient(Rt, x, g.cpu().numpy(), f)
+
+
+@pytest.mark.parametrize("n,T", [(1001, 2000), (5437, 900)])
+def test_bf16_gradient_narrow_layout(npga, n, T):
+    """ld % 8 == 4 selects the 8-byte-load sweep through the C-ABI; rows
+    n..ld-1 hold NaN, which the kernels must never use."""
+    import ctypes
+    from paper_2604_02917_amd import api
+    spec = spec_with("c2", n, T, seed=90 + n)
+    Rt = gen.returns_TxN(spec)
+    x = gen.random_vector(n, 7, "uniform")
+    x = (x / x.sum()).astype(np.float32)
+    ld = (n + 3) // 4 * 4
+    if ld % 8 == 0:
+        ld += 4
+    bits = oq.to_bf16_bits(Rt).reshape(T, n)
+    buf = np.full((T, ld), 0x7FC0, dtype=np.uint16)      # bfloat16 NaN padding
+    buf[:, :n] = bits
+    Ld = torch.from_numpy(buf.view(np.int16)).to("cuda:0")
+    xd = to_dev(x)
+    mu = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(max(int(api._lib.npga_solve_workspace_size(n, T, None)), 256), dtype=torch.uint8,
+                     device="cuda:0")
+    fac = api._Factor(n, T, ld, Ld.data_ptr(), mu.data_ptr(), 0.0, 1, 0)
+    fv = ctypes.c_double(0.0)
+    rc = api._lib.npga_gradient(ctypes.byref(fac), ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                ctypes.byref(fv), ctypes.c_void_p(ws.data_ptr()), ws.numel(), api._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    _check_bf16_gradient(Rt, x, g.cpu().numpy(), fv.value)
 
 
 @pytest.mark.parametrize("n,T,q", [(64, 256, 0.5), (300, 3000, 0.6), (1000, 6000, 0.6)])
