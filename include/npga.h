@@ -107,6 +107,9 @@ typedef struct npga_options {
                             the support, no negative reduced cost); kept for ABI
                             stability; default 1e-9                                   */
   int32_t refine_max_iter; /* iteration cap of the refinement phase; default 20000    */
+  int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
+                            (see npga_batched_tune), or -1 for the built-in choice
+                            from the shape; default -1                               */
 } npga_options;
 
 /* Result of a solve (host). */
@@ -256,19 +259,58 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
                     void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * npga_solve_batched - m independent solves sharing L_eff (an efficient
- * frontier: one target r_j per column of X).  r_targets (host, m values),
- * X device n x m float32 (leading dim n), res (host, m results, may be NULL).
- * Returns NPGA_ERR_UNSUPPORTED in builds without the batched path.
+ * npga_solve_batched - m independent solves of eq. mv on one factor, one
+ * target return r_j per solve (points of the efficient frontier, Sec. 5).
+ * Every target runs Algorithm 1 with its own iterate, momentum, projection
+ * and stopping test (Sec. 3.1), the shared step alpha = 1/(safety L_f_hat)
+ * of one power method, and the same float64 face refinement as npga_solve.
+ * The gradients of all targets come from two matrix-core GEMMs per
+ * iteration, U^T = X^T L and G = 2 L U, so L is read twice per iteration for
+ * all m targets; a target that has stopped keeps its x and is skipped by the
+ * tails.
+ *   f          factor (float32 or bfloat16), gamma >= 0
+ *   r_targets  host, m target returns, each <= max(mu) (else
+ *              NPGA_ERR_INFEASIBLE before any iteration)
+ *   m          1 <= m <= NPGA_MAX_BATCH
+ *   X          device n x m float32, column j = x_j, leading dim ldx >= n;
+ *              read as x^0 when opt->warm_start, always written
+ *   res        host, m results (may be NULL); time_to_tol_ms of target j is
+ *              the GPU time from entry to the end of the chunk of
+ *              check_every iterations in which its stopping test passed;
+ *              sweep_ms is the mean time of one U+G GEMM pair
+ *   ws         npga_batched_workspace_size(n, cols, m, opt) bytes
+ * Returns NPGA_OK when every target returned NPGA_OK, else the status of the
+ * first target that did not.  opt->path must be AUTO or GEMV.  Synchronises
+ * `stream`.
  *
+ * npga_gradient_batched - G[:, j] = 2 L (L^T X[:, j]) + 2 gamma X[:, j] and
+ * f_out[j] = ||L^T X[:, j]||^2 + gamma ||X[:, j]||^2 (float64 sums) for
+ * m columns, by the batched GEMMs.  G device n x m float64 (ldg >= n);
+ * f_out host m or NULL (then the call does not synchronise).  config as in
+ * npga_options.batch_config.  ws: npga_batched_workspace_size(n, cols, m, NULL).
+ *
+ * npga_batched_tune - times each tile configuration on this factor and m
+ * (reps U+G GEMM pairs each, HIP events on `stream`) and returns the fastest
+ * in *best; ms_out (host, NPGA_BATCH_CONFIGS entries, may be NULL) receives
+ * the mean time per pair.  Uses the workspace of npga_solve_batched.
+ * ------------------------------------------------------------------------- */
+#define NPGA_MAX_BATCH 1024
+#define NPGA_BATCH_CONFIGS 12
+size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt);
+int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
+                       const npga_options *opt, float *X, int64_t ldx, npga_result *res,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_gradient_batched(const npga_factor *f, const float *X, int64_t ldx, int32_t m,
+                          double *G, int64_t ldg, double *f_out, int32_t config, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
+int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *best,
+                      float *ms_out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * npga_backward - gradients of a loss l(x*) through the solution map
  * x*(mu, L) by implicit differentiation of the KKT system on the active set.
  * Returns NPGA_ERR_UNSUPPORTED in builds without the adjoint.
  * ------------------------------------------------------------------------- */
-size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt);
-int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
-                       const npga_options *opt, float *X, npga_result *res, void *ws,
-                       size_t ws_bytes, hipStream_t stream);
 int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,
                   double *dl_dmu, float *dl_dL, void *ws, size_t ws_bytes,
                   hipStream_t stream);

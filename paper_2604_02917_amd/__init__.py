@@ -8,6 +8,9 @@ package loads the library and raises if it is missing: there is no fallback.
 from .api import (  # noqa: F401
     NpgaError,
     Options,
+    batched_tune,
+    gradient_batched,
+    solve_batched,
     build_factor,
     gradient,
     lib_path,

@@ -42,7 +42,8 @@ class _Options(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("step_safety", ctypes.c_double),
                 ("refine", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32)]
+                ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
+                ("batch_config", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -85,7 +86,10 @@ def _load():
                                            vp, vp, sz, vp]),
         "npga_batched_workspace_size": (sz, [i64, i64, i32, ctypes.POINTER(_Options)]),
         "npga_solve_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i32, ctypes.POINTER(_Options),
-                                              vp, ctypes.POINTER(_Result), vp, sz, vp]),
+                                              vp, i64, ctypes.POINTER(_Result), vp, sz, vp]),
+        "npga_gradient_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i64, i32, vp, i64, vp, i32,
+                                                 vp, sz, vp]),
+        "npga_batched_tune": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, i32, vp, vp, vp, sz, vp]),
         "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
@@ -121,6 +125,7 @@ class Options:
     restart: bool = False
     refine_tol: float = 1e-9
     refine_max_iter: int = 20000
+    batch_config: int = -1
 
     def _c(self):
         o = _Options()
@@ -130,6 +135,7 @@ class Options:
         o.refine, o.path, o.seed = int(self.refine), PATHS[self.path], self.seed
         o.warm_start, o.restart = int(self.warm_start), int(self.restart)
         o.refine_tol, o.refine_max_iter = self.refine_tol, self.refine_max_iter
+        o.batch_config = self.batch_config
         return o
 
 
@@ -207,6 +213,75 @@ def solve(L_TxN, mu, r, gamma=0.0, x0=None, options=None, **kw):
     if code not in (NPGA_OK, 3):
         raise NpgaError(code, "npga_solve")
     return x, info
+
+
+def _info(res, code):
+    info = {k: getattr(res, k) for k, _ in _Result._fields_}
+    info["lambda"] = info.pop("lambda_")
+    info["status_name"] = STATUS_NAMES.get(code, str(code))
+    return info
+
+
+BATCH_CONFIGS = 12
+
+
+def solve_batched(L_TxN, mu, r_targets, gamma=0.0, X0=None, options=None, **kw):
+    """m solves on one factor, target r_j per solve (an efficient frontier).
+
+    r_targets: sequence of m floats.  X0: optional (m, n) warm starts.
+    Returns (X (m, n) float32 tensor, row j = x_j; list of m info dicts).
+    """
+    opts = options or Options(**kw)
+    if X0 is not None:
+        opts = dataclasses.replace(opts, warm_start=True)
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    mu = mu.to(dtype=torch.float64).contiguous()
+    r = [float(v) for v in r_targets]
+    m = len(r)
+    co = opts._c()
+    ws = _workspace(_lib.npga_batched_workspace_size(n, cols, m, ctypes.byref(co)), Lb.device)
+    X = torch.empty((m, n), dtype=torch.float32, device=Lb.device)
+    if X0 is not None:
+        X.copy_(X0.to(torch.float32))
+    res = (_Result * m)()
+    rt = (ctypes.c_double * m)(*r)
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    code = _lib.npga_solve_batched(ctypes.byref(f), rt, m, ctypes.byref(co), _ptr(X), n, res, _ptr(ws),
+                                   ws.numel(), _stream())
+    infos = [_info(res[j], res[j].status) for j in range(m)]
+    if code not in (NPGA_OK, 3):
+        raise NpgaError(code, "npga_solve_batched")
+    return X, infos
+
+
+def gradient_batched(L_TxN, X, gamma=0.0, config=-1):
+    """G[j] = 2 L (L^T x_j) + 2 gamma x_j and f_j for the rows x_j of X (m, n),
+    by the batched matrix-core GEMMs.  Returns (G (m, n) float64, f list)."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    X = X.to(torch.float32).contiguous()
+    m = X.shape[0]
+    mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
+    G = torch.empty((m, n), dtype=torch.float64, device=Lb.device)
+    ws = _workspace(_lib.npga_batched_workspace_size(n, cols, m, None), Lb.device)
+    fo = (ctypes.c_double * m)()
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    _check(_lib.npga_gradient_batched(ctypes.byref(f), _ptr(X), n, m, _ptr(G), n, fo, int(config), _ptr(ws),
+                                      ws.numel(), _stream()), "npga_gradient_batched")
+    return G, list(fo)
+
+
+def batched_tune(L_TxN, m, reps=5):
+    """Times every batched tile configuration on this factor and batch size;
+    returns (best config id, list of ms per U+G GEMM pair)."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
+    ws = _workspace(_lib.npga_batched_workspace_size(n, cols, m, None), Lb.device)
+    best = ctypes.c_int32(-1)
+    ms = (ctypes.c_float * BATCH_CONFIGS)()
+    f = _factor(Lb, n, cols, ld, mu, 0.0)
+    _check(_lib.npga_batched_tune(ctypes.byref(f), int(m), int(reps), ctypes.byref(best), ms, _ptr(ws),
+                                  ws.numel(), _stream()), "npga_batched_tune")
+    return best.value, list(ms)
 
 
 def project(v, mu, r):

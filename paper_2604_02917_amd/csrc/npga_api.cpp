@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "npga.h"
 #include "npga_internal.h"
@@ -118,7 +119,8 @@ bool options_valid(const npga_options &o) {
   return is_fin(o.tol) && o.tol > 0 && o.check_every >= 1 && o.max_iter >= 1 && is_fin(o.proj_tol) &&
          o.proj_tol > 0 && o.power_iters >= 1 && is_fin(o.step_safety) && o.step_safety >= 1.0 &&
          (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
-         is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0;
+         is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0 && o.batch_config >= -1 &&
+         o.batch_config < npga::kBatchConfigs;
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -296,6 +298,7 @@ void npga_default_options(npga_options *o) {
   o->restart = 0;
   o->refine_tol = 1e-9;
   o->refine_max_iter = 20000;
+  o->batch_config = -1;
 }
 
 const char *npga_status_string(int status) {
@@ -710,17 +713,439 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
   return NPGA_OK;
 }
 
-size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt) {
-  (void)n; (void)cols; (void)m; (void)opt;
-  return 0;
+}  // extern "C"
+
+namespace {
+
+// Workspace of a batched solve: a single-solve region (power method, float64
+// anchors), then the per-target states and vectors and the GEMM buffers.
+struct BatchLayout {
+  SolveLayout single;
+  size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, total;
+  int64_t npad, ldx, ldut, ldpm, ldq;
+};
+
+constexpr int kMaxSplits = 64;
+constexpr int kNumVec = 9;  // xbuf0, xbuf1, gbuf0, gbuf1, pvec, fvec, gvec, xa, ga
+
+BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m) {
+  BatchLayout l{};
+  l.single = npga::solve_layout(n, cols, NPGA_PATH_GEMV);
+  l.npad = (int64_t)256 * l.single.slots;
+  l.ldx = l.npad;
+  l.ldut = (m + 3) / 4 * 4;
+  l.ldpm = (m + 3) / 4 * 4;
+  l.ldq = l.ldpm;
+  size_t off = align_up(l.single.total, 256);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  l.off_states = take(sizeof(DevState) * (size_t)m);
+  l.off_X = take(sizeof(float) * (size_t)l.ldx * (size_t)m);
+  l.off_vec = take(sizeof(double) * (size_t)kNumVec * (size_t)l.npad * (size_t)m);
+  l.off_Ut = take(sizeof(float) * (size_t)l.ldut * (size_t)cols);
+  l.off_P = take(sizeof(float) * (size_t)kMaxSplits * (size_t)n * (size_t)l.ldpm);
+  const int64_t utiles_max = (cols + 63) / 64;
+  l.off_usq = take(sizeof(double) * (size_t)utiles_max * (size_t)l.ldq);
+  l.off_status = take(sizeof(int32_t) * (size_t)(2 * (m + 1)));
+  l.total = off;
+  return l;
 }
 
-int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
-                       const npga_options *opt, float *X, npga_result *res, void *ws,
-                       size_t ws_bytes, hipStream_t stream) {
-  (void)f; (void)r_targets; (void)m; (void)opt; (void)X; (void)res; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return NPGA_ERR_UNSUPPORTED;
+npga::BatchArgs carve_batch(const npga_factor *f, const BatchLayout &l, void *ws, int32_t m,
+                            const npga::BatchConfig &cfg) {
+  char *base = static_cast<char *>(ws);
+  npga::BatchArgs b{};
+  SolveArgs &a = b.base;
+  a.L = f->L;
+  a.dtype = f->dtype;
+  a.ld = f->ld;
+  a.n = f->n;
+  a.cols = f->cols;
+  a.mu = f->mu;
+  a.mode = npga::kTailNpga;
+  a.st = reinterpret_cast<DevState *>(base + l.off_states);
+  a.xs = reinterpret_cast<float *>(base + l.off_X);
+  double *v = reinterpret_cast<double *>(base + l.off_vec);
+  const int64_t blk = l.npad * (int64_t)m;
+  a.xbuf0 = v;
+  a.xbuf1 = v + blk;
+  a.gbuf0 = v + 2 * blk;
+  a.gbuf1 = v + 3 * blk;
+  b.m = m;
+  b.vstride = l.npad;
+  b.gstride = l.npad;
+  b.ldx = l.ldx;
+  b.Ut = reinterpret_cast<float *>(base + l.off_Ut);
+  b.ldut = l.ldut;
+  b.P = reinterpret_cast<float *>(base + l.off_P);
+  b.ldpm = l.ldpm;
+  b.usq_part = reinterpret_cast<double *>(base + l.off_usq);
+  b.ldq = l.ldq;
+  // per-target vectors are laid out target-major inside each block: vector
+  // k of target j at v + k * blk + j * npad
+  int64_t kc = ((f->cols + cfg.splits - 1) / cfg.splits + 31) / 32 * 32;
+  b.kchunk = kc;
+  b.splits = (int32_t)((f->cols + kc - 1) / kc);
+  b.utiles = (int32_t)((f->cols + cfg.u_bm - 1) / cfg.u_bm);
+  return b;
+}
+
+void batch_refine_vectors(npga::BatchArgs &b, const BatchLayout &l, void *ws) {
+  double *v = reinterpret_cast<double *>(static_cast<char *>(ws) + l.off_vec);
+  const int64_t blk = l.npad * (int64_t)b.m;
+  b.base.pvec = v + 4 * blk;
+  b.base.fvec = v + 5 * blk;
+  b.base.gvec = v + 6 * blk;
+  b.base.xa = v + 7 * blk;
+  b.base.ga = v + 8 * blk;
+}
+
+// Pinned host buffers of a batched call: m states and two status slots.
+struct BatchPinned {
+  DevState *states = nullptr;
+  int32_t *status = nullptr;  // 2 slots of (m + 1)
+  int32_t cap = 0;
+};
+
+BatchPinned *batch_pinned(int32_t m) {
+  thread_local BatchPinned p;
+  if (p.cap < m) {
+    if (p.states) (void)hipHostFree(p.states);
+    if (p.status) (void)hipHostFree(p.status);
+    p.states = nullptr;
+    p.status = nullptr;
+    p.cap = 0;
+    void *a = nullptr, *c = nullptr;
+    if (hipHostMalloc(&a, sizeof(DevState) * (size_t)m, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&c, sizeof(int32_t) * (size_t)(2 * (m + 1)), hipHostMallocDefault) != hipSuccess) {
+      (void)hipHostFree(a);
+      return nullptr;
+    }
+    p.states = static_cast<DevState *>(a);
+    p.status = static_cast<int32_t *>(c);
+    p.cap = m;
+  }
+  return &p;
+}
+
+const npga::BatchConfig &batch_config_of(int32_t requested, int64_t n, int64_t cols, int32_t m) {
+  const int id = (requested >= 0 && requested < npga::kBatchConfigs) ? requested
+                                                                      : npga::batch_default_config(n, cols, m);
+  return npga::kBatchConfigTable[id];
+}
+
+// Runs chunks of check_every batched iterations until no target is running.
+// t_done[j] receives the GPU time from ev0 to the end of the chunk in which
+// target j stopped (unchanged for targets that stopped before the phase).
+int run_batch_phase(const npga::BatchArgs &b, const npga::BatchConfig &cfg, int slots, int check_every,
+                    int64_t max_chunks, hipStream_t s, int32_t *dev_status, int32_t *pin_status, hipEvent_t *evs,
+                    hipEvent_t ev0, double *t_done, SweepTimer *tm) {
+  const int32_t m = b.m;
+  auto issue = [&](int slot) -> int {
+    for (int i = 0; i < check_every; ++i) {
+      if (i == 0 && tm && hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+      if (npga::launch_bgemm(b, cfg, s)) return NPGA_ERR_HIP;
+      if (i == 0 && tm && hipEventRecord(tm->b[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+      if (npga::launch_breduce_tail(b, slots, s)) return NPGA_ERR_HIP;
+    }
+    int32_t *ds = dev_status + (size_t)slot * (m + 1);
+    int32_t *hs = pin_status + (size_t)slot * (m + 1);
+    if (npga::launch_bstatus(b, ds, s)) return NPGA_ERR_HIP;
+    if (hipMemcpyAsync(hs, ds, sizeof(int32_t) * (size_t)(m + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return NPGA_ERR_HIP;
+    if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
+    return NPGA_OK;
+  };
+  std::vector<char> seen(m, 0);
+  int64_t issued = 0, consumed = 0;
+  int e = issue(0);
+  if (e) return e;
+  ++issued;
+  e = issue(1);
+  if (e) return e;
+  ++issued;
+  for (;;) {
+    const int slot = consumed & 1;
+    if (hipEventSynchronize(evs[slot]) != hipSuccess) return NPGA_ERR_HIP;
+    ++consumed;
+    const int32_t *hs = pin_status + (size_t)slot * (m + 1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, evs[slot]);
+    for (int32_t j = 0; j < m; ++j) {
+      if (!seen[j] && hs[1 + j] != npga::kRunning) {
+        seen[j] = 1;
+        if (t_done[j] < 0) t_done[j] = ms;
+      }
+    }
+    if (tm && hs[0] > 0) {
+      float g = 0.f;
+      if (hipEventElapsedTime(&g, tm->a[slot], tm->b[slot]) == hipSuccess) {
+        tm->total_ms += g;
+        tm->samples += 1;
+      }
+    }
+    if (hs[0] == 0) {
+      if (hipStreamSynchronize(s) != hipSuccess) return NPGA_ERR_HIP;
+      return NPGA_OK;
+    }
+    if (issued >= max_chunks) {
+      if (hipStreamSynchronize(s) != hipSuccess) return NPGA_ERR_HIP;
+      return NPGA_OK;
+    }
+    e = issue(slot);
+    if (e) return e;
+    ++issued;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt) {
+  (void)opt;
+  if (n < 1 || n > NPGA_MAX_N || cols < 1 || m < 1 || m > NPGA_MAX_BATCH) return 0;
+  return batch_layout(n, cols, m).total;
+}
+
+int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m, const npga_options *opt,
+                       float *X, int64_t ldx, npga_result *res, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  const auto t0 = Clock::now();
+  npga_options o;
+  npga_default_options(&o);
+  if (opt) o = *opt;
+  if (!factor_valid(f) || !r_targets || !X || m < 1 || m > NPGA_MAX_BATCH || ldx < f->n ||
+      !options_valid(o) || !aligned(X, 4))
+    return NPGA_ERR_INVALID;
+  if (o.path == NPGA_PATH_SYRK) return NPGA_ERR_UNSUPPORTED;
+  for (int32_t j = 0; j < m; ++j)
+    if (!is_fin(r_targets[j])) return NPGA_ERR_INVALID;
+  const BatchLayout lay = batch_layout(f->n, f->cols, m);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  BatchPinned *bp = batch_pinned(m);
+  if (!pin || !bp) return NPGA_ERR_HIP;
+  const npga::BatchConfig &cfg = batch_config_of(o.batch_config, f->n, f->cols, m);
+  Carved c = carve(f, lay.single, ws, NPGA_PATH_GEMV);
+  npga::BatchArgs b = carve_batch(f, lay, ws, m, cfg);
+  const int slots = lay.single.slots;
+  int32_t *dev_status = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + lay.off_status);
+
+  hipEvent_t ev0, evs[2], ev_setup;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&evs[0]));
+  HIPCHK(hipEventCreate(&evs[1]));
+  HIPCHK(hipEventCreate(&ev_setup));
+  SweepTimer tm;
+  HIPCHK(hipEventCreate(&tm.a[0]));
+  HIPCHK(hipEventCreate(&tm.a[1]));
+  HIPCHK(hipEventCreate(&tm.b[0]));
+  HIPCHK(hipEventCreate(&tm.b[1]));
+  struct EvGuard {
+    hipEvent_t e[8];
+    ~EvGuard() {
+      for (auto &x : e) (void)hipEventDestroy(x);
+    }
+  } guard{{ev0, evs[0], evs[1], ev_setup, tm.a[0], tm.a[1], tm.b[0], tm.b[1]}};
+
+  HIPCHK(hipEventRecord(ev0, stream));
+  // mu statistics and feasibility of every target (one synchronisation)
+  pin[2] = initial_state(f, r_targets[0], o);
+  HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_prepare(c.a, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pin[3].n_nonfinite > 0) return NPGA_ERR_NUMERIC;
+  const double mu_max = pin[3].mu_max, mu_absmax = pin[3].mu_absmax;
+  for (int32_t j = 0; j < m; ++j)
+    if (r_targets[j] > mu_max) return NPGA_ERR_INFEASIBLE;
+
+  // shared step size: power method on L (Sec. 3.1 Remark)
+  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, o.seed, stream));
+  {
+    Carved cp = c;
+    cp.a.mode = npga::kTailPower;
+    for (int i = 0; i < o.power_iters; ++i) LAUNCHCHK(step(cp, NPGA_PATH_GEMV, slots, stream));
+  }
+  LAUNCHCHK(npga::launch_set_alpha(c.st, o.step_safety, stream));
+
+  // per-target states, x^0 = Pi_F(x_in or 1/n)
+  for (int32_t j = 0; j < m; ++j) {
+    DevState s0 = initial_state(f, r_targets[j], o);
+    s0.mu_max = mu_max;
+    s0.mu_absmax = mu_absmax;
+    s0.tolphi = o.proj_tol * std::max(std::fabs(r_targets[j]), mu_absmax);
+    bp->states[j] = s0;
+  }
+  HIPCHK(hipMemcpyAsync(b.base.st, bp->states, sizeof(DevState) * (size_t)m, hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_bcopy_step(b, c.st, stream));
+  LAUNCHCHK(npga::launch_bset_x0(b, o.warm_start ? X : nullptr, ldx, stream));
+  LAUNCHCHK(npga::launch_bproject_init(b, slots, stream));
+  HIPCHK(hipEventRecord(ev_setup, stream));
+
+  std::vector<double> t_done(m, -1.0);
+  const int64_t main_chunks = (int64_t)o.max_iter / o.check_every + 4;
+  int e = run_batch_phase(b, cfg, slots, o.check_every, main_chunks, stream, dev_status, bp->status, evs, ev0,
+                          t_done.data(), &tm);
+  if (e) return e;
+  HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  std::vector<DevState> after_main(bp->states, bp->states + m);
+
+  std::vector<int32_t> refine_iters(m, 0), refined(m, 0), ref_done(m, npga::kConverged);
+  bool any = false;
+  for (int32_t j = 0; j < m; ++j) any = any || after_main[j].done == npga::kConverged;
+  if (any && o.refine && o.refine_max_iter > 0) {
+    batch_refine_vectors(b, lay, ws);
+    npga::BatchArgs br = b;
+    br.base.mode = npga::kTailCG;
+    std::vector<double> t_unused(m, 0.0);
+    for (int round = 0; round < 2; ++round) {
+      // float64 anchor gradients of every target still converged
+      LAUNCHCHK(npga::launch_bcopy_anchor(br, stream));
+      for (int32_t j = 0; j < m; ++j) {
+        const int32_t dj = round == 0 ? after_main[j].done : ref_done[j];
+        if (dj != npga::kConverged) continue;
+        LAUNCHCHK(npga::launch_precise_gradient(c.a, br.base.xa + (int64_t)j * br.vstride,
+                                                reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                                                           lay.single.off_ua),
+                                                const_cast<double *>(br.base.ga) + (int64_t)j * br.vstride,
+                                                reinterpret_cast<double *>(c.a.partials), slots, stream));
+      }
+      LAUNCHCHK(npga::launch_bphase_reset(br, o.refine_tol, o.refine_max_iter, stream));
+      LAUNCHCHK(npga::launch_bcg_init(br, slots, stream));
+      const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
+      e = run_batch_phase(br, cfg, slots, o.check_every, ref_chunks, stream, dev_status, bp->status, evs, ev0,
+                          t_unused.data(), nullptr);
+      if (e) return e;
+      HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost,
+                            stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      for (int32_t j = 0; j < m; ++j) {
+        const int32_t prev = round == 0 ? after_main[j].done : ref_done[j];
+        if (prev != npga::kConverged) continue;
+        refine_iters[j] += bp->states[j].cg_iter;
+        ref_done[j] = bp->states[j].done;
+        refined[j] = (bp->states[j].done == npga::kConverged && bp->states[j].cg_kkt) ? 1 : 0;
+      }
+    }
+  }
+  LAUNCHCHK(npga::launch_bfinalize(b, X, ldx, stream));
+  HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+
+  float setup_ms = 0.f;
+  (void)hipEventElapsedTime(&setup_ms, ev0, ev_setup);
+  const double wall = ms_since(t0);
+  int first_bad = NPGA_OK;
+  for (int32_t j = 0; j < m; ++j) {
+    const DevState &am = after_main[j];
+    const DevState &fin = bp->states[j];
+    int status = map_done(am.done);
+    if (am.done == npga::kConverged && ref_done[j] != npga::kConverged && ref_done[j] != npga::kMaxIter)
+      status = map_done(ref_done[j]);
+    if (status != NPGA_OK && first_bad == NPGA_OK) first_bad = status;
+    if (!res) continue;
+    npga_result &rj = res[j];
+    std::memset(&rj, 0, sizeof(rj));
+    rj.status = status;
+    rj.iters = (am.done == npga::kConverged) ? am.stop_iter : am.iter;
+    rj.refine_iters = refine_iters[j];
+    rj.support = fin.support;
+    rj.return_active = fin.nu_c > 0.0 ? 1 : 0;
+    rj.refined = refined[j];
+    rj.path_used = NPGA_PATH_GEMV;
+    rj.residual = am.stop_residual;
+    rj.final_residual = fin.residual;
+    rj.objective = fin.objective;
+    rj.nu = fin.nu_kkt;
+    rj.lambda = fin.lambda_kkt;
+    rj.alpha = fin.alpha;
+    rj.lipschitz = fin.lipschitz;
+    rj.time_ms = wall;
+    rj.time_to_tol_ms = t_done[j];
+    rj.setup_ms = setup_ms;
+    rj.sweep_ms = tm.samples ? tm.total_ms / tm.samples : 0.0;
+    rj.sweep_samples = tm.samples;
+  }
+  return first_bad;
+}
+
+int npga_gradient_batched(const npga_factor *f, const float *X, int64_t ldx, int32_t m, double *G, int64_t ldg,
+                          double *f_out, int32_t config, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!factor_valid(f) || !X || !G || m < 1 || m > NPGA_MAX_BATCH || ldx < f->n || ldg < f->n ||
+      config < -1 || config >= npga::kBatchConfigs || !aligned(X, 4) || !aligned(G, 8))
+    return NPGA_ERR_INVALID;
+  const BatchLayout lay = batch_layout(f->n, f->cols, m);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  BatchPinned *bp = batch_pinned(m);
+  if (!bp) return NPGA_ERR_HIP;
+  npga_options o;
+  npga_default_options(&o);
+  const npga::BatchConfig &cfg = batch_config_of(config, f->n, f->cols, m);
+  npga::BatchArgs b = carve_batch(f, lay, ws, m, cfg);
+  b.base.mode = npga::kTailGrad;
+  b.base.gbuf0 = G;
+  b.base.gbuf1 = nullptr;
+  b.gstride = ldg;
+  for (int32_t j = 0; j < m; ++j) bp->states[j] = initial_state(f, 0.0, o);
+  HIPCHK(hipMemcpyAsync(b.base.st, bp->states, sizeof(DevState) * (size_t)m, hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_bload_x(b, X, ldx, stream));
+  LAUNCHCHK(npga::launch_bgemm(b, cfg, stream));
+  LAUNCHCHK(npga::launch_breduce_tail(b, lay.single.slots, stream));
+  if (f_out) {
+    HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int32_t j = 0; j < m; ++j) f_out[j] = bp->states[j].objective;
+  }
+  return NPGA_OK;
+}
+
+int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *best, float *ms_out, void *ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!factor_valid(f) || !best || m < 1 || m > NPGA_MAX_BATCH || reps < 1) return NPGA_ERR_INVALID;
+  const BatchLayout lay = batch_layout(f->n, f->cols, m);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  hipEvent_t a, z;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&z));
+  struct G2 {
+    hipEvent_t a, z;
+    ~G2() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(z);
+    }
+  } guard{a, z};
+  {
+    const npga::BatchConfig &c0 = npga::kBatchConfigTable[0];
+    npga::BatchArgs b0 = carve_batch(f, lay, ws, m, c0);
+    LAUNCHCHK(npga::launch_bset_x0(b0, nullptr, 0, stream));  // zero GEMM input
+  }
+  float best_ms = 1e30f;
+  int32_t best_id = 0;
+  for (int c = 0; c < npga::kBatchConfigs; ++c) {
+    const npga::BatchConfig &cfg = npga::kBatchConfigTable[c];
+    npga::BatchArgs b = carve_batch(f, lay, ws, m, cfg);
+    LAUNCHCHK(npga::launch_bgemm(b, cfg, stream));  // warm-up
+    HIPCHK(hipEventRecord(a, stream));
+    for (int r = 0; r < reps; ++r) LAUNCHCHK(npga::launch_bgemm(b, cfg, stream));
+    HIPCHK(hipEventRecord(z, stream));
+    HIPCHK(hipEventSynchronize(z));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, z));
+    ms /= (float)reps;
+    if (ms_out) ms_out[c] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_id = c;
+    }
+  }
+  *best = best_id;
+  return NPGA_OK;
 }
 
 int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,

@@ -119,6 +119,40 @@ struct SolveArgs {
   double *gvec;        // gradient maintained by linearity
 };
 
+// m independent solves sharing L (one target return per solve).  Target j
+// uses the SolveArgs of target 0 with every per-target pointer advanced by
+// j strides; the gradient of all targets comes from two skinny GEMMs,
+//     U^T = X^T L   (Ut[j + t ldut] = sum_i X[i, j] L[i, t])
+//     G   = L U     (split over t: P[s][i][j] partial sums)
+// followed by a reduce that applies each target's epilogue.
+struct BatchArgs {
+  SolveArgs base;      // target 0; base.xs is X (n x m float32, column stride ldx)
+  int32_t m;
+  int64_t vstride;     // doubles between consecutive targets' n-vectors
+  int64_t gstride;     // doubles between targets' gradient buffers (gbuf0/gbuf1)
+  int64_t ldx;         // floats between consecutive columns of X
+  float *Ut;           // U^T, m x cols, leading dim ldut
+  int64_t ldut;
+  float *P;            // G partials: P[(s * n + i) * ldpm + j]
+  int64_t ldpm;
+  int32_t splits;      // number of t-ranges of the G GEMM
+  int64_t kchunk;      // t-range length of one split (multiple of 32)
+  double *usq_part;    // per-tile ||U_{:,j}||^2 partials: [tile * ldq + j]
+  int64_t ldq;
+  int32_t utiles;      // number of row tiles of the U GEMM
+};
+
+// Tile configuration of the two batched GEMMs.
+struct BatchConfig {
+  int32_t u_bm, u_bn;  // U GEMM tile (rows of U = periods t, columns = targets)
+  int32_t g_bm, g_bn;  // G GEMM tile (rows of G = assets i, columns = targets)
+  int32_t splits;      // t-splits of the G GEMM
+};
+
+constexpr int kBatchConfigs = 12;
+extern const BatchConfig kBatchConfigTable[kBatchConfigs];
+int batch_default_config(int64_t n, int64_t cols, int32_t m);
+
 // Workspace carving for a solve.
 struct SolveLayout {
   size_t off_state, off_status_dev, off_xs, off_x0, off_x1, off_g0, off_g1, off_part, off_usq,
@@ -161,6 +195,20 @@ int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, 
                             double *part, int slots, hipStream_t s);
 int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s);
 int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s);
+
+// Batched solves (npga_batched.hip).
+int launch_bgemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s);
+int launch_breduce_tail(const BatchArgs &b, int slots, hipStream_t s);
+int launch_bproject_init(const BatchArgs &b, int slots, hipStream_t s);
+int launch_bcg_init(const BatchArgs &b, int slots, hipStream_t s);
+int launch_bfinalize(const BatchArgs &b, float *X, int64_t ldx_out, hipStream_t s);
+int launch_bset_x0(const BatchArgs &b, const float *X0, int64_t ldx0, hipStream_t s);
+int launch_bcopy_step(const BatchArgs &b, const DevState *src, hipStream_t s);
+int launch_bload_x(const BatchArgs &b, const float *X, int64_t ldx_in, hipStream_t s);
+int launch_bphase_reset(const BatchArgs &b, double tol, int32_t max_iter, hipStream_t s);
+int launch_bcopy_anchor(const BatchArgs &b, hipStream_t s);
+int launch_bstatus(const BatchArgs &b, int32_t *out, hipStream_t s);
+int launch_zero_f32(float *p, int64_t count, hipStream_t s);
 
 // Factor build.
 int launch_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,

@@ -437,101 +437,16 @@ __global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
     tail_grad<E>(a, usq, redbuf);
 }
 
-// x0 = Pi_F(xbuf0) (Algorithm 1 requires x^0 in F); initialises the iteration.
 template <int E>
 __global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
-  DevState *st = a.st;
   __shared__ double redbuf[64];
-  BlockReducer<5> red{redbuf, 0};
-  const int tid = threadIdx.x;
-  double mu[E], v[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    mu[j] = (i < a.n) ? a.mu[i] : 0.0;
-    v[j] = (i < a.n) ? a.xbuf0[i] : -1.0e300;
-  }
-  const ProjResult pr = project_F<E>(v, mu, st->r, st->tolphi, 0.0, -1.0e300, red);
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    if (i < a.n) {
-      a.xbuf0[i] = v[j];
-      a.xbuf1[i] = v[j];
-      a.gbuf0[i] = 0.0;
-      a.gbuf1[i] = 0.0;
-      a.xs[i] = (float)v[j];
-    }
-  }
-  if (tid == 0) {
-    st->iter = 0;
-    st->t = 1.0;
-    st->beta = 0.0;
-    st->nu = pr.nu;
-    st->tau = pr.tau;
-    st->nu_c = pr.nu;
-    st->tau_c = pr.tau;
-    st->proj_flags |= pr.flags;
-    st->ticket = 0u;
-    if (pr.flags & 2) st->done = kBracket;
-  }
+  project_init_body<E>(a, redbuf);
 }
 
-// Start of the face-CG refinement: x = x_k (= the anchor), g = g_a + 2 gamma x,
-// free set = support of x, return constraint held if the last stopping-test
-// projection had nu > 0; p = projected gradient.
 template <int E>
 __global__ __launch_bounds__(256) void k_cg_init(SolveArgs a) {
-  DevState *st = a.st;
   __shared__ double redbuf[64];
-  BlockReducer<5> red{redbuf, 0};
-  const int tid = threadIdx.x;
-  const int64_t n = a.n;
-  const double *x_p = (st->iter & 1) ? a.xbuf1 : a.xbuf0;
-  double x[E], g[E], mu[E], fr[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    const bool ok = i < n;
-    x[j] = ok ? x_p[i] : 0.0;
-    g[j] = ok ? a.ga[i] + 2.0 * st->gamma * x[j] : 0.0;
-    mu[j] = ok ? a.mu[i] : 0.0;
-    fr[j] = (ok && x[j] > 0.0) ? 1.0 : 0.0;
-  }
-  const bool active = st->nu_c > 0.0;
-  double lam, nu;
-  face_multipliers<E>(g, mu, fr, active, red, lam, nu);
-  double acc[5] = {0, 0, 0, 0, 0};
-  double p[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    p[j] = (fr[j] > 0.0) ? -(g[j] - lam - nu * mu[j]) : 0.0;
-    acc[0] = fma(p[j], p[j], acc[0]);
-  }
-  red.sum(acc);
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    if (i < n) {
-      a.gvec[i] = g[j];
-      a.pvec[i] = p[j];
-      a.fvec[i] = fr[j];
-      a.xs[i] = (float)p[j];
-    }
-  }
-  if (tid == 0) {
-    st->cg_rr = acc[0];
-    st->cg_rr0 = acc[0];
-    st->cg_active = active ? 1 : 0;
-    st->cg_iter = 0;
-    st->cg_cycles = 0;
-    st->cg_released = 0;
-    st->cg_blocked = 0;
-    st->cg_best_rr = acc[0];
-    st->cg_best_it = 0;
-    st->cg_kkt = 0;
-    st->ticket = 0u;
-  }
+  cg_init_body<E>(a, redbuf);
 }
 
 // Standalone projection (npga_project entry point).
