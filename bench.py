@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-syrk-compare", action="store_true")
     ap.add_argument("--no-str", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-frontier", action="store_true")
+    ap.add_argument("--frontier-seq", type=int, default=4,
+                    help="single solves timed for the one-at-a-time comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -78,6 +81,64 @@ def cpu_baseline(Rt, r, gpu_grad_evals, budget_s):
                    f"gradient), scaled to the {gpu_grad_evals} gradient evaluations the GPU "
                    f"needed to reach residual 1e-6"),
     }
+
+
+def frontier_section(npga, gen, torch, dev, n_seq):
+    """Efficient frontier at n = 2000, T = 20000 (5 factors, seed 4): m = 128
+    targets r_j = r_mv + j (0.95 max mu - r_mv)/127, all solved by one batched
+    call; frontier solves/s = m / GPU time until the last target's stopping
+    test passed.  r_mv comes from a GPU solve with a slack return target."""
+    spec = gen.SPECS["c4"]
+    Rt = gen.returns_TxN(spec)
+    R4 = torch.from_numpy(Rt).to(dev)
+    del Rt
+    L4, mu4 = npga.build_factor(R4)
+    del R4
+    mu_h = mu4.cpu().numpy()
+    x_mv, _ = npga.solve(L4, mu4, float(mu_h.min()) - 1.0)
+    r_mv = float(mu_h @ x_mv.cpu().numpy().astype("float64"))
+    rs = gen.frontier_targets_from_mv(r_mv, float(mu_h.max()), 128)
+    n, T, m = spec.n, spec.T, len(rs)
+    flops = 4.0 * n * T * m            # U = L^T X and G = L U: 2 n T m each
+    sec = {"workload": "frontier n=2000, T=20000, m=128 targets (seed 4)", "m": m}
+    for name, Lx in (("f32", L4), ("bf16", npga.to_bf16(L4))):
+        best, cfg_ms = npga.batched_tune(Lx, m)
+        runs = []
+        for _ in range(2):
+            X, infos = npga.solve_batched(Lx, mu4, rs, batch_config=best)
+            runs.append(infos)
+        infos = runs[-1]
+        t_all = max(i["time_to_tol_ms"] for i in infos) / 1e3
+        gemm_ms = infos[0]["sweep_ms"]
+        sec[name] = {
+            "frontier_solves_per_s": m / t_all,
+            "time_to_tol_all_s": t_all,
+            "solve_ms_incl_refinement": infos[0]["time_ms"],
+            "setup_ms": infos[0]["setup_ms"],
+            "iters_max": max(i["iters"] for i in infos),
+            "iters_median": sorted(i["iters"] for i in infos)[m // 2],
+            "refine_iters_max": max(i["refine_iters"] for i in infos),
+            "all_ok": all(i["status"] == 0 for i in infos),
+            "all_refined": all(i["refined"] == 1 for i in infos),
+            "config": best,
+            "config_ms": cfg_ms,
+            "gemm_pair_ms": gemm_ms,
+            "gemm_TFLOPs": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms else None,
+            "objectives_nondecreasing": all(infos[j + 1]["objective"] >= infos[j]["objective"] * (1 - 1e-6)
+                                            for j in range(m - 1)),
+        }
+    # the same targets one solve at a time (a sample, scaled to m)
+    seq = []
+    idx = [int(round(v)) for v in (i * (m - 1) / max(n_seq - 1, 1) for i in range(n_seq))]
+    for j in idx:
+        npga.solve(L4, mu4, float(rs[j]))
+        _, inf1 = npga.solve(L4, mu4, float(rs[j]))
+        seq.append(inf1["time_to_tol_ms"] / 1e3)
+    t_seq = sum(seq) / len(seq) * m
+    sec["one_at_a_time"] = {"targets_timed": idx, "time_to_tol_s_mean": sum(seq) / len(seq),
+                            "frontier_solves_per_s": m / t_seq}
+    sec["speedup_batched_f32_vs_one_at_a_time"] = sec["f32"]["frontier_solves_per_s"] / (m / t_seq)
+    return sec
 
 
 def main():
@@ -258,6 +319,8 @@ def main():
             "full_model_gap": max(f_full_str - f_full, 0.0) / max(abs(f_full), 1e-12),
             "status": info_str["status_name"],
         }
+    if not args.no_frontier:
+        out["frontier"] = frontier_section(npga, gen, torch, dev, args.frontier_seq)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Rt, r, grad_evals, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -721,8 +721,8 @@ namespace {
 // anchors), then the per-target states and vectors and the GEMM buffers.
 struct BatchLayout {
   SolveLayout single;
-  size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, total;
-  int64_t npad, ldx, ldut, ldpm, ldq;
+  size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, off_act, off_U16, off_Lt, total;
+  int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt;
 };
 
 constexpr int kMaxSplits = 64;
@@ -750,10 +750,38 @@ BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m) {
   const int64_t utiles_max = (cols + 63) / 64;
   l.off_usq = take(sizeof(double) * (size_t)utiles_max * (size_t)l.ldq);
   l.off_status = take(sizeof(int32_t) * (size_t)(2 * (m + 1)));
+  l.off_act = take(sizeof(int32_t) * (size_t)(m + 1));
+  // bfloat16 factors: U planes and the row-major copy of L
+  l.ldu16 = (cols + 7) / 8 * 8;
+  l.ldlt = l.ldu16;
+  l.off_U16 = take(sizeof(uint16_t) * 3 * (size_t)m * (size_t)l.ldu16);
+  l.off_Lt = take(sizeof(uint16_t) * (size_t)n * (size_t)l.ldlt);
   l.total = off;
   return l;
 }
 
+// Split and tile counts of a configuration for this factor.
+npga::BatchArgs with_config(npga::BatchArgs b, const npga::BatchConfig &cfg) {
+  const int64_t cols = b.base.cols;
+  const int64_t kc = ((cols + cfg.splits - 1) / cfg.splits + 31) / 32 * 32;
+  b.kchunk = kc;
+  b.splits = (int32_t)((cols + kc - 1) / kc);
+  if (b.Lt) {
+    const int bt = cfg.g_bn == 32 ? 128 : 64;  // period tile of the bfloat16 U GEMM
+    b.utiles = (int32_t)((cols + bt - 1) / bt);
+  } else {
+    b.utiles = (int32_t)((cols + cfg.u_bm - 1) / cfg.u_bm);
+  }
+  return b;
+}
+
+// The bfloat16 matrix-core path needs 16-byte groups along each column.
+bool use_b16(const npga_factor *f) {
+  return f->dtype == NPGA_BF16 && (f->ld % 8) == 0 && aligned(f->L, 16);
+}
+
+// Per-target vectors are laid out target-major inside each block: vector k
+// of target j at v + k * (npad m) + j * npad.
 npga::BatchArgs carve_batch(const npga_factor *f, const BatchLayout &l, void *ws, int32_t m,
                             const npga::BatchConfig &cfg) {
   char *base = static_cast<char *>(ws);
@@ -784,13 +812,27 @@ npga::BatchArgs carve_batch(const npga_factor *f, const BatchLayout &l, void *ws
   b.ldpm = l.ldpm;
   b.usq_part = reinterpret_cast<double *>(base + l.off_usq);
   b.ldq = l.ldq;
-  // per-target vectors are laid out target-major inside each block: vector
-  // k of target j at v + k * blk + j * npad
-  int64_t kc = ((f->cols + cfg.splits - 1) / cfg.splits + 31) / 32 * 32;
-  b.kchunk = kc;
-  b.splits = (int32_t)((f->cols + kc - 1) / kc);
-  b.utiles = (int32_t)((f->cols + cfg.u_bm - 1) / cfg.u_bm);
-  return b;
+  int32_t *act = reinterpret_cast<int32_t *>(base + l.off_act);
+  b.act = act;
+  b.mact = act + m;
+  if (use_b16(f)) {
+    b.Lt = reinterpret_cast<const uint16_t *>(base + l.off_Lt);
+    b.ldlt = l.ldlt;
+    b.U16 = reinterpret_cast<uint16_t *>(base + l.off_U16);
+    b.ldu16 = l.ldu16;
+    b.u16plane = (int64_t)m * l.ldu16;
+  }
+  return with_config(b, cfg);
+}
+
+// Per-call preparation of the bfloat16 path: Lt = L row-major (zero past
+// T) and zeroed U planes (their padding past T must read as zero).
+int batch_prepare_b16(const npga::BatchArgs &b, const BatchLayout &l, hipStream_t s) {
+  if (!b.Lt) return 0;
+  const int64_t u16_floats = (int64_t)(3 * (size_t)b.m * (size_t)l.ldu16 * sizeof(uint16_t) / sizeof(float));
+  if (npga::launch_zero_f32(reinterpret_cast<float *>(b.U16), u16_floats, s)) return 1;
+  return npga::launch_transpose16(static_cast<const uint16_t *>(b.base.L), b.base.ld, b.base.n, b.base.cols,
+                                  const_cast<uint16_t *>(b.Lt), b.ldlt, s);
 }
 
 void batch_refine_vectors(npga::BatchArgs &b, const BatchLayout &l, void *ws) {
@@ -837,14 +879,32 @@ const npga::BatchConfig &batch_config_of(int32_t requested, int64_t n, int64_t c
   return npga::kBatchConfigTable[id];
 }
 
+// Configuration for the chunk about to run: the requested one while it is
+// not wider than the running targets need, else the built-in choice for
+// the narrower tile (the host's count lags the device's by at most a
+// chunk, and only ever over-counts, so the grid still covers every column).
+const npga::BatchConfig &config_for_running(const npga::BatchConfig &req, int64_t n, int64_t cols,
+                                            int32_t running) {
+  const int need = running <= 32 ? 32 : (running <= 64 ? 64 : 128);
+  if (req.u_bn <= need && req.g_bn <= need) return req;
+  return npga::kBatchConfigTable[npga::batch_default_config(n, cols, need)];
+}
+
 // Runs chunks of check_every batched iterations until no target is running.
 // t_done[j] receives the GPU time from ev0 to the end of the chunk in which
 // target j stopped (unchanged for targets that stopped before the phase).
-int run_batch_phase(const npga::BatchArgs &b, const npga::BatchConfig &cfg, int slots, int check_every,
+int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int slots, int check_every,
                     int64_t max_chunks, hipStream_t s, int32_t *dev_status, int32_t *pin_status, hipEvent_t *evs,
                     hipEvent_t ev0, double *t_done, SweepTimer *tm) {
-  const int32_t m = b.m;
+  const int32_t m = b0.m;
+  int32_t running = m;  // last count read back (an upper bound of the device's)
+  int32_t *act = const_cast<int32_t *>(b0.act);
+  int32_t *mact = const_cast<int32_t *>(b0.mact);
+  // GEMM columns = targets running at the start of the phase
+  if (npga::launch_bstatus(b0, dev_status, act, mact, s)) return NPGA_ERR_HIP;
   auto issue = [&](int slot) -> int {
+    const npga::BatchConfig &cfg = config_for_running(req, b0.base.n, b0.base.cols, running);
+    const npga::BatchArgs b = with_config(b0, cfg);
     for (int i = 0; i < check_every; ++i) {
       if (i == 0 && tm && hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
       if (npga::launch_bgemm(b, cfg, s)) return NPGA_ERR_HIP;
@@ -853,7 +913,7 @@ int run_batch_phase(const npga::BatchArgs &b, const npga::BatchConfig &cfg, int 
     }
     int32_t *ds = dev_status + (size_t)slot * (m + 1);
     int32_t *hs = pin_status + (size_t)slot * (m + 1);
-    if (npga::launch_bstatus(b, ds, s)) return NPGA_ERR_HIP;
+    if (npga::launch_bstatus(b, ds, act, mact, s)) return NPGA_ERR_HIP;
     if (hipMemcpyAsync(hs, ds, sizeof(int32_t) * (size_t)(m + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
       return NPGA_ERR_HIP;
     if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
@@ -880,7 +940,8 @@ int run_batch_phase(const npga::BatchArgs &b, const npga::BatchConfig &cfg, int 
         if (t_done[j] < 0) t_done[j] = ms;
       }
     }
-    if (tm && hs[0] > 0) {
+    running = hs[0];
+    if (tm && hs[0] == m) {  // pairs over the full batch only
       float g = 0.f;
       if (hipEventElapsedTime(&g, tm->a[slot], tm->b[slot]) == hipSuccess) {
         tm->total_ms += g;
@@ -983,6 +1044,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   }
   HIPCHK(hipMemcpyAsync(b.base.st, bp->states, sizeof(DevState) * (size_t)m, hipMemcpyHostToDevice, stream));
   LAUNCHCHK(npga::launch_bcopy_step(b, c.st, stream));
+  LAUNCHCHK(batch_prepare_b16(b, lay, stream));
   LAUNCHCHK(npga::launch_bset_x0(b, o.warm_start ? X : nullptr, ldx, stream));
   LAUNCHCHK(npga::launch_bproject_init(b, slots, stream));
   HIPCHK(hipEventRecord(ev_setup, stream));
@@ -1094,7 +1156,9 @@ int npga_gradient_batched(const npga_factor *f, const float *X, int64_t ldx, int
   b.gstride = ldg;
   for (int32_t j = 0; j < m; ++j) bp->states[j] = initial_state(f, 0.0, o);
   HIPCHK(hipMemcpyAsync(b.base.st, bp->states, sizeof(DevState) * (size_t)m, hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(batch_prepare_b16(b, lay, stream));
   LAUNCHCHK(npga::launch_bload_x(b, X, ldx, stream));
+  LAUNCHCHK(npga::launch_bact_all(b, const_cast<int32_t *>(b.act), const_cast<int32_t *>(b.mact), stream));
   LAUNCHCHK(npga::launch_bgemm(b, cfg, stream));
   LAUNCHCHK(npga::launch_breduce_tail(b, lay.single.slots, stream));
   if (f_out) {
@@ -1123,7 +1187,9 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
   {
     const npga::BatchConfig &c0 = npga::kBatchConfigTable[0];
     npga::BatchArgs b0 = carve_batch(f, lay, ws, m, c0);
+    LAUNCHCHK(batch_prepare_b16(b0, lay, stream));
     LAUNCHCHK(npga::launch_bset_x0(b0, nullptr, 0, stream));  // zero GEMM input
+    LAUNCHCHK(npga::launch_bact_all(b0, const_cast<int32_t *>(b0.act), const_cast<int32_t *>(b0.mact), stream));
   }
   float best_ms = 1e30f;
   int32_t best_id = 0;

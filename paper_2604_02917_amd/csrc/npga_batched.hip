@@ -127,6 +127,16 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
   const int64_t ld = b.base.ld;
   const float *X = b.base.xs;
   const int kq = 4 * (tid & 7);
+  const int ma = *b.mact;
+  if (j0 >= ma) return;
+  (void)m;
+  // targets of this thread's X columns (column c -> target act[c])
+  const float *xcol[QB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int64_t c = j0 + (tid >> 3) + 32 * q;
+    xcol[q] = (c < ma) ? X + (int64_t)b.act[c] * b.ldx : nullptr;
+  }
 
   typename R::type ra[QA];
   f4 rb[QB];
@@ -138,10 +148,8 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
       ra[q] = (t < T && k < n) ? R::load(L + t * ld + k) : R::zero();
     }
 #pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      const int64_t j = j0 + (tid >> 3) + 32 * q;
-      rb[q] = (j < m && k < n) ? *reinterpret_cast<const f4 *>(X + j * b.ldx + k) : f4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int q = 0; q < QB; ++q)
+      rb[q] = (xcol[q] && k < n) ? *reinterpret_cast<const f4 *>(xcol[q] + k) : f4{0.f, 0.f, 0.f, 0.f};
   };
   auto sstore = [&](int buf, int64_t k0) {
     const int64_t k = k0 + kq;
@@ -223,7 +231,7 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
       for (int v = 0; v < 16; ++v) {
         const int64_t t = t0 + wr * 32 * PM + 32 * p + 8 * (v >> 2) + 4 * h + (v & 3);
         const float val = acc[p][q][v];
-        if (t < T && j < m) b.Ut[j + t * b.ldut] = val;
+        if (t < T && j < ma) b.Ut[j + t * b.ldut] = val;
         cs[q] = fma((double)val, (double)val, cs[q]);  // rows t >= T are zero
       }
     }
@@ -238,8 +246,8 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < WM; ++w) sum += ush[w * BN + c];
-    const int64_t j = j0 + c;
-    if (j < m) b.usq_part[(int64_t)blockIdx.x * b.ldq + j] = sum;
+    const int64_t cc = j0 + c;
+    if (cc < ma) b.usq_part[(int64_t)blockIdx.x * b.ldq + b.act[cc]] = sum;
   }
 }
 
@@ -272,6 +280,9 @@ __global__ __launch_bounds__(256) void k_bgemm_g(BatchArgs b) {
   const TL *L = static_cast<const TL *>(b.base.L);
   const int64_t ld = b.base.ld;
   const float *Ut = b.Ut;
+  const int ma = *b.mact;
+  if (j0 >= ma) return;
+  (void)m;
 
   typename R::type ra[QA];
   f4 rb[QB];
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(256) void k_bgemm_g(BatchArgs b) {
       const int idx = tid + 256 * q;
       const int64_t t = k0 + idx / FB;
       const int64_t j = j0 + 4 * (idx % FB);
-      rb[q] = (t < te && j < m) ? *reinterpret_cast<const f4 *>(Ut + j + t * b.ldut) : f4{0.f, 0.f, 0.f, 0.f};
+      rb[q] = (t < te && j < ma) ? *reinterpret_cast<const f4 *>(Ut + j + t * b.ldut) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
   auto sstore = [&](int buf) {
@@ -348,51 +359,63 @@ __global__ __launch_bounds__(256) void k_bgemm_g(BatchArgs b) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t i = i0 + wr * 32 * PM + 32 * p + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (i < n && j < m) P[i * b.ldpm + j] = acc[p][q][v];
+        if (i < n && j < ma) P[i * b.ldpm + j] = acc[p][q][v];
       }
     }
 }
 
 // --------------------------------------------------------------------------
 // g_j = 2 sum_s P[s][:, j] (fixed order over s, float64) and the epilogue of
-// the current mode; a 64 x 32 tile transposed through LDS so that both the
-// partial reads (along j) and the per-target writes (along i) coalesce.
+// the current mode.  A 16 x 32 tile (rows i x GEMM columns c) per
+// workgroup: the partial reads run along c, eight splits in flight per
+// thread; the tile is transposed through LDS so the per-target reads and
+// writes run along i.
 // --------------------------------------------------------------------------
+constexpr int RB = 16;  // rows of a reduce tile
+
 __global__ __launch_bounds__(256) void k_breduce(BatchArgs b) {
-  __shared__ double tile[64][33];
+  __shared__ double tile[RB][33];
   const int64_t n = b.base.n;
-  const int m = b.m;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int j0 = blockIdx.y * 32;
+  const int ma = *b.mact;
+  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  const int c0 = blockIdx.y * 32;  // GEMM column block (running targets)
   const int tid = threadIdx.x;
+  if (c0 >= ma) return;
   {
-    const int jj = tid & 31, ii = tid >> 5;
+    const int cc = tid & 31, ii = tid >> 5;
     const int64_t split_stride = n * b.ldpm;
+    const int S = b.splits;
 #pragma unroll
-    for (int rr = 0; rr < 8; ++rr) {
-      const int64_t i = i0 + ii + 8 * rr;
-      const int j = j0 + jj;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = i0 + ii + 8 * h;
       double s = 0.0;
-      if (i < n && j < m) {
-        const float *p = b.P + i * b.ldpm + j;
-        for (int sp = 0; sp < b.splits; ++sp) s += (double)p[sp * split_stride];
+      if (i < n && c0 + cc < ma) {
+        const float *p = b.P + i * b.ldpm + c0 + cc;
+        int sp = 0;
+        for (; sp + 8 <= S; sp += 8) {
+          float v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = p[(int64_t)(sp + e) * split_stride];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) s += (double)v[e];
+        }
+        for (; sp < S; ++sp) s += (double)p[(int64_t)sp * split_stride];
       }
-      tile[ii + 8 * rr][jj] = s;
+      tile[ii + 8 * h][cc] = s;
     }
   }
   __syncthreads();
-  const int il = tid & 63, jq = tid >> 6;
+  const int il = tid & 15, cq = tid >> 4;
   const int64_t i = i0 + il;
   if (i >= n) return;
 #pragma unroll
-  for (int rr = 0; rr < 8; ++rr) {
-    const int jl = jq + 4 * rr;
-    const int j = j0 + jl;
-    if (j >= m) continue;
-    const SolveArgs a = target_args(b, j);
+  for (int h = 0; h < 2; ++h) {
+    const int cl = cq + 16 * h;
+    if (c0 + cl >= ma) continue;
+    const SolveArgs a = target_args(b, b.act[c0 + cl]);
     const DevState *st = a.st;
     if (st->done != kRunning) continue;
-    const double tot = tile[il][jl];
+    const double tot = tile[il][cl];
     if (a.mode == kTailNpga) {
       const int cur = st->iter & 1;
       const double *xk = cur ? a.xbuf1 : a.xbuf0;
@@ -511,22 +534,48 @@ __global__ __launch_bounds__(256) void k_bcopy_anchor(BatchArgs b) {
   if (i < a.n) const_cast<double *>(a.xa)[i] = x[i];
 }
 
-// out[0] = number of running targets, out[1 + j] = done code of target j.
-__global__ __launch_bounds__(256) void k_bstatus(BatchArgs b, int32_t *out) {
-  __shared__ int cnt[256];
+// out[0] = number of running targets, out[1 + j] = done code of target j;
+// act[0..mact) = the running targets in ascending order (GEMM columns of the
+// next iterations).  One workgroup; target j = 4 tid + e (m <= 1024).
+__global__ __launch_bounds__(256) void k_bstatus(BatchArgs b, int32_t *out, int32_t *act, int32_t *mact) {
+  __shared__ int scan[256];
+  const int tid = threadIdx.x;
+  int run[4];
   int c = 0;
-  for (int j = threadIdx.x; j < b.m; j += 256) {
-    const int32_t d = b.base.st[j].done;
-    out[1 + j] = d;
-    c += (d == kRunning) ? 1 : 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int j = 4 * tid + e;
+    run[e] = 0;
+    if (j < b.m) {
+      const int32_t d = b.base.st[j].done;
+      out[1 + j] = d;
+      run[e] = (d == kRunning) ? 1 : 0;
+      c += run[e];
+    }
   }
-  cnt[threadIdx.x] = c;
+  // inclusive scan of the per-thread counts (Hillis-Steele)
+  scan[tid] = c;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = (tid >= off) ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = cnt[0];
+  int pos = scan[tid] - c;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (run[e]) act[pos++] = 4 * tid + e;
+  if (tid == 255) {
+    out[0] = scan[255];
+    *mact = scan[255];
+  }
+}
+
+// Every target is a GEMM column (batched gradient, tuning).
+__global__ __launch_bounds__(256) void k_bact_all(int32_t m, int32_t *act, int32_t *mact) {
+  for (int j = threadIdx.x; j < m; j += 256) act[j] = j;
+  if (threadIdx.x == 0) *mact = m;
 }
 
 __global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t count) {
@@ -585,12 +634,13 @@ static int launch_bgemm_t(const BatchArgs &b, const BatchConfig &c, hipStream_t 
 }
 
 int launch_bgemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s) {
+  if (b.Lt) return launch_b16_gemm(b, c, s);
   if (b.base.dtype == NPGA_BF16) return launch_bgemm_t<bf16_t>(b, c, s);
   return launch_bgemm_t<float>(b, c, s);
 }
 
 int launch_breduce_tail(const BatchArgs &b, int slots, hipStream_t s) {
-  const dim3 gr((unsigned)((b.base.n + 63) / 64), (unsigned)((b.m + 31) / 32));
+  const dim3 gr((unsigned)((b.base.n + RB - 1) / RB), (unsigned)((b.m + 31) / 32));
   hipLaunchKernelGGL(k_breduce, gr, dim3(256), 0, s, b);
   if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
 #define CALL(E) hipLaunchKernelGGL(k_btail<E>, dim3((unsigned)b.m), dim3(256), 0, s, b)
@@ -647,8 +697,14 @@ int launch_bcopy_anchor(const BatchArgs &b, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-int launch_bstatus(const BatchArgs &b, int32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_bstatus, dim3(1), dim3(256), 0, s, b, out);
+int launch_bstatus(const BatchArgs &b, int32_t *out, int32_t *act, int32_t *mact, hipStream_t s) {
+  if (b.m > 1024) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bstatus, dim3(1), dim3(256), 0, s, b, out, act, mact);
+  return (int)hipGetLastError();
+}
+
+int launch_bact_all(const BatchArgs &b, int32_t *act, int32_t *mact, hipStream_t s) {
+  hipLaunchKernelGGL(k_bact_all, dim3(1), dim3(256), 0, s, b.m, act, mact);
   return (int)hipGetLastError();
 }
 

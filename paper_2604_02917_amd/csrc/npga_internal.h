@@ -140,6 +140,18 @@ struct BatchArgs {
   double *usq_part;    // per-tile ||U_{:,j}||^2 partials: [tile * ldq + j]
   int64_t ldq;
   int32_t utiles;      // number of row tiles of the U GEMM
+  // GEMM columns are the running targets only: column c < *mact is target
+  // act[c] (ascending); U^T and P are indexed by c, everything else by j
+  const int32_t *act;
+  const int32_t *mact;
+  // bfloat16 factors on the bfloat16 matrix cores (null otherwise): a
+  // row-major copy Lt[i * ldlt + t] of L and U as three bfloat16 planes
+  // U16[pl * u16plane + c * ldu16 + t]
+  const uint16_t *Lt;
+  int64_t ldlt;
+  uint16_t *U16;
+  int64_t ldu16;
+  int64_t u16plane;
 };
 
 // Tile configuration of the two batched GEMMs.
@@ -207,8 +219,12 @@ int launch_bcopy_step(const BatchArgs &b, const DevState *src, hipStream_t s);
 int launch_bload_x(const BatchArgs &b, const float *X, int64_t ldx_in, hipStream_t s);
 int launch_bphase_reset(const BatchArgs &b, double tol, int32_t max_iter, hipStream_t s);
 int launch_bcopy_anchor(const BatchArgs &b, hipStream_t s);
-int launch_bstatus(const BatchArgs &b, int32_t *out, hipStream_t s);
+int launch_bstatus(const BatchArgs &b, int32_t *out, int32_t *act, int32_t *mact, hipStream_t s);
+int launch_bact_all(const BatchArgs &b, int32_t *act, int32_t *mact, hipStream_t s);
 int launch_zero_f32(float *p, int64_t count, hipStream_t s);
+int launch_b16_gemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s);
+int launch_transpose16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, uint16_t *Lt, int64_t ldlt,
+                       hipStream_t s);
 
 // Factor build.
 int launch_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,

@@ -69,9 +69,48 @@ def make_c3():
     print(f"wrote {path}: f*={f_str:.6e} gap={doc['full_model_gap']:.4f} ({time.time() - t0:.1f}s)", flush=True)
 
 
+C4_SAMPLED = [0, 1, 16, 32, 48, 64, 80, 96, 112, 127]
+
+
+def make_c4():
+    """Frontier workload: n = 2000, T = 20000, 128 targets from r_mv to
+    0.95 max mu; exact objective and multipliers at every target, the
+    minimiser itself at a sample of the targets."""
+    from oracle.frontier import min_variance
+    spec = gen.SPECS["c4"]
+    t0 = time.time()
+    Rt = gen.returns_TxN(spec)
+    mu, L = ofactor.build_factor(Rt.T)
+    Q = L @ L.T
+    x_mv, r_mv = min_variance(Q, mu)
+    rs = gen.frontier_targets_from_mv(r_mv, float(mu.max()), 128)
+    print(f"c4: min-variance r_mv={r_mv:.6e} ({time.time() - t0:.1f}s)", flush=True)
+    pts = []
+    for j in range(len(rs)):
+        out = exact_mv(Q, mu, float(rs[j]), fista_tol=1e-10)
+        x = out["x"]
+        rep = qp.kkt_report(2 * Q, np.zeros(spec.n), mu, float(rs[j]), x, out["lam"], out["nu"])
+        assert qp.certificate_ok(rep, tol_stat=1e-9, tol_feas=1e-12, r_scale=np.abs(mu).max()), rep
+        p = {"j": j, "r": float(rs[j]), "objective": factor_objective(L, 0.0, x), "nu": out["nu"],
+             "lambda": out["lam"], "support": int((x > 0).sum())}
+        if j in C4_SAMPLED:  # minimisers stored at a sample of the targets only (file size)
+            p["x"] = [float(v) for v in x]
+        pts.append(p)
+        print(f"c4: target {j} f*={p['objective']:.6e} ({time.time() - t0:.1f}s)", flush=True)
+    doc = {"workload": "c4", "n": spec.n, "T": spec.T, "seed": spec.seed, "m": 128,
+           "panel_sha256": panel_digest(Rt), "r_mv": r_mv, "f_mv": factor_objective(L, 0.0, x_mv),
+           "targets": [float(v) for v in rs], "points": pts}
+    path = os.path.join(HERE, "c4_frontier.json")
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
+
+
 def make(name):
     if name == "c3":
         return make_c3()
+    if name == "c4":
+        return make_c4()
     spec = gen.SPECS[name]
     t0 = time.time()
     Rt = gen.returns_TxN(spec)

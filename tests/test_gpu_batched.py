@@ -117,3 +117,36 @@ def test_batched_infeasible_target(npga):
     with pytest.raises(npga.NpgaError) as e:
         npga.solve_batched(L, mu, bad)
     assert e.value.code == 2
+
+
+def test_gradient_batched_bf16_narrow_layout(npga):
+    """ld % 8 == 4 (bfloat16 rows not in 16-byte groups) takes the float32
+    matrix-core GEMMs on the widened entries; rows n..ld-1 hold NaN."""
+    import ctypes
+    from paper_2604_02917_amd import api
+    n, T, m = 1001, 1500, 20
+    spec = spec_with("c2", n, T, seed=400)
+    Rt = gen.returns_TxN(spec)
+    X = _rows_on_simplex(m, n, 401)
+    ld = (n + 3) // 4 * 4
+    if ld % 8 == 0:
+        ld += 4
+    buf = np.full((T, ld), 0x7FC0, dtype=np.uint16)
+    buf[:, :n] = oq.to_bf16_bits(Rt).reshape(T, n)
+    Ld = torch.from_numpy(buf.view(np.int16)).to("cuda:0")
+    Xd = to_dev(X)
+    mu = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    G = torch.empty((m, n), dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(int(api._lib.npga_batched_workspace_size(n, T, m, None)), dtype=torch.uint8, device="cuda:0")
+    fac = api._Factor(n, T, ld, Ld.data_ptr(), mu.data_ptr(), 0.0, 1, 0)
+    fo = (ctypes.c_double * m)()
+    rc = api._lib.npga_gradient_batched(ctypes.byref(fac), ctypes.c_void_p(Xd.data_ptr()), n, m,
+                                        ctypes.c_void_p(G.data_ptr()), n, fo, -1, ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), api._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    L = oq.round_to_bf16(Rt).reshape(Rt.shape).T
+    Xt = X.astype(np.float64).T
+    U = L.T @ Xt
+    B = 2 * (np.abs(L) @ (np.abs(L).T @ np.abs(Xt)))
+    assert np.all(np.abs(G.cpu().numpy().T - 2 * (L @ U)) <= (n + T + 8) * U32 * B)
