@@ -127,6 +127,17 @@ def frontier_section(npga, gen, torch, dev, n_seq):
             "objectives_nondecreasing": all(infos[j + 1]["objective"] >= infos[j]["objective"] * (1 - 1e-6)
                                             for j in range(m - 1)),
         }
+    # adaptive momentum restart (an option; Algorithm 1 itself has none)
+    best16 = sec["bf16"]["config"]
+    Lb16 = npga.to_bf16(L4)
+    npga.solve_batched(Lb16, mu4, rs, batch_config=best16, restart=True)
+    _, inf_r = npga.solve_batched(Lb16, mu4, rs, batch_config=best16, restart=True)
+    t_r = max(i["time_to_tol_ms"] for i in inf_r) / 1e3
+    sec["bf16_restart"] = {"frontier_solves_per_s": m / t_r, "time_to_tol_all_s": t_r,
+                           "iters_max": max(i["iters"] for i in inf_r),
+                           "iters_median": sorted(i["iters"] for i in inf_r)[m // 2],
+                           "all_ok": all(i["status"] == 0 for i in inf_r)}
+    del Lb16
     # the same targets one solve at a time (a sample, scaled to m)
     seq = []
     idx = [int(round(v)) for v in (i * (m - 1) / max(n_seq - 1, 1) for i in range(n_seq))]

@@ -59,3 +59,31 @@ def test_c3_golden_consistent():
     assert np.all(np.diff(sig) <= 0) and sig[-1] >= ref["sigma_513"]
     k = ref["kkt"]
     assert k["stat_support"] <= 1e-9 and k["dual_offsupport"] >= -1e-9
+
+
+GOLDEN_C4 = os.path.join(os.path.dirname(__file__), "golden", "c4_frontier.json")
+
+
+@pytest.mark.slow
+def test_c4_golden_consistent():
+    """Stored frontier: regenerated panel, stored minimisers feasible with
+    the stored objectives, f* nondecreasing and convex along the targets."""
+    with open(GOLDEN_C4) as fh:
+        ref = json.load(fh)
+    spec = gen.SPECS["c4"]
+    Rt = gen.returns_TxN(spec)
+    assert panel_digest(Rt) == ref["panel_sha256"]
+    mu, L = ofactor.build_factor(Rt.T)
+    rs = np.asarray(ref["targets"])
+    np.testing.assert_allclose(rs, gen.frontier_targets_from_mv(ref["r_mv"], float(mu.max()), 128), rtol=0,
+                               atol=0)
+    f = np.array([p["objective"] for p in ref["points"]])
+    assert np.all(np.diff(f) >= 0) and np.all(f[:-2] - 2 * f[1:-1] + f[2:] >= -1e-12 * f.max())
+    assert f[0] == pytest.approx(ref["f_mv"], rel=1e-9)
+    for p in ref["points"]:
+        if "x" not in p:
+            continue
+        x = np.asarray(p["x"])
+        assert x.min() >= 0 and abs(x.sum() - 1) <= 1e-12
+        assert mu @ x >= p["r"] - 1e-14
+        assert factor_objective(L, 0.0, x) == pytest.approx(p["objective"], rel=1e-12)
