@@ -308,12 +308,47 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
 
 /* ---------------------------------------------------------------------------
  * npga_backward - gradients of a loss l(x*) through the solution map
- * x*(mu, L) by implicit differentiation of the KKT system on the active set.
- * Returns NPGA_ERR_UNSUPPORTED in builds without the adjoint.
+ * x*(mu, L, r, gamma) of eq. mv, by implicit differentiation of the KKT
+ * conditions (Sec. 3.1 "Stopping condition") on the face of x*: the
+ * support S = {x*_i > 0} and the return row when mu^T x* - r <= 1e-6
+ * max(|r|, max|mu|) with a nonnegative multiplier.  With a the solution of
+ *     H_SS a + a_lam 1 + a_nu mu_S = dl/dx_S,  1^T a = 0,  mu_S^T a = 0
+ * (H = 2 (L L^T + gamma I); the mu row dropped when the return constraint
+ * is not in the face), the gradients are
+ *     dl/dmu_S = nu a - a_nu x*_S,  dl/dmu_{S^c} = 0,  dl/dr = a_nu,
+ *     dl/dgamma = -2 a^T x*,        dl/dL = -2 (a u^T + x* v^T),
+ * u = L^T x*, v = L^T a.  a is found by projected conjugate gradients with
+ * the fused sweep for H p (float32 products) and one float64-anchored
+ * correction round.  The formula assumes the face does not change under a
+ * small perturbation; res->degenerate = 1 flags a zero x_i with near-zero
+ * reduced cost, |S| = 1, or mu constant on S.
+ *   x_star   device n float32: a solution (e.g. from npga_solve)
+ *   dl_dx    device n float32: gradient of the loss at x_star
+ *   dl_dmu   device n float64 output
+ *   dl_dL    device n x cols float32 output (column-major, leading dim
+ *            ldg >= n), or NULL to skip it
+ *   res      host, may be NULL
+ *   ws       npga_backward_workspace_size(n, cols) bytes
+ * Synchronises `stream`.  Returns NPGA_ERR_NOT_CONVERGED if the adjoint
+ * iteration hit its cap (outputs still written).
  * ------------------------------------------------------------------------- */
+typedef struct npga_backward_result {
+  int32_t status;
+  int32_t cg_iters;       /* projected-CG iterations, both rounds            */
+  int32_t support;        /* |S|                                              */
+  int32_t return_active;  /* 1 if the return row is in the face             */
+  int32_t degenerate;     /* 1 if the face may change under perturbation     */
+  int32_t reserved;
+  double nu, lambda;      /* multipliers of f at x* (least squares on S)     */
+  double dl_dr;           /* a_nu                                             */
+  double dl_dgamma;       /* -2 a^T x*                                        */
+  double residual;        /* ||projected residual|| / ||dl/dx_S||, float64   */
+  double time_ms;         /* host wall time                                   */
+} npga_backward_result;
+size_t npga_backward_workspace_size(int64_t n, int64_t cols);
 int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,
-                  double *dl_dmu, float *dl_dL, void *ws, size_t ws_bytes,
-                  hipStream_t stream);
+                  double *dl_dmu, float *dl_dL, int64_t ldg, npga_backward_result *res,
+                  void *ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

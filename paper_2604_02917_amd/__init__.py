@@ -6,8 +6,10 @@ HIP stream into the C ABI declared in ``include/npga.h``.  Importing the
 package loads the library and raises if it is missing: there is no fallback.
 """
 from .api import (  # noqa: F401
+    NPGAFunction,
     NpgaError,
     Options,
+    backward,
     batched_tune,
     gradient_batched,
     solve_batched,

@@ -46,6 +46,13 @@ class _Options(ctypes.Structure):
                 ("batch_config", ctypes.c_int32)]
 
 
+class _BackwardResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("return_active", ctypes.c_int32), ("degenerate", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nu", ctypes.c_double), ("lambda_", ctypes.c_double), ("dl_dr", ctypes.c_double),
+                ("dl_dgamma", ctypes.c_double), ("residual", ctypes.c_double), ("time_ms", ctypes.c_double)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("support", ctypes.c_int32),
@@ -90,7 +97,9 @@ def _load():
         "npga_gradient_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i64, i32, vp, i64, vp, i32,
                                                  vp, sz, vp]),
         "npga_batched_tune": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, i32, vp, vp, vp, sz, vp]),
-        "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, vp, sz, vp]),
+        "npga_backward_workspace_size": (sz, [i64, i64]),
+        "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, i64,
+                                         ctypes.POINTER(_BackwardResult), vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +291,50 @@ def batched_tune(L_TxN, m, reps=5):
     _check(_lib.npga_batched_tune(ctypes.byref(f), int(m), int(reps), ctypes.byref(best), ms, _ptr(ws),
                                   ws.numel(), _stream()), "npga_batched_tune")
     return best.value, list(ms)
+
+
+def backward(L_TxN, mu, r, x_star, dl_dx, gamma=0.0, want_dL=True):
+    """Adjoint of the solution map (implicit differentiation of the KKT
+    system on the face of x*).  Returns (dl_dmu (n,) float64, dl_dL (T, n)
+    float32 or None, info dict with dl_dr, dl_dgamma, nu, support, ...)."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    mu = mu.to(dtype=torch.float64).contiguous()
+    xs = x_star.to(torch.float32).contiguous()
+    gx = dl_dx.to(torch.float32).contiguous()
+    dmu = torch.empty(n, dtype=torch.float64, device=Lb.device)
+    dL = torch.empty((cols, n), dtype=torch.float32, device=Lb.device) if want_dL else None
+    ws = _workspace(_lib.npga_backward_workspace_size(n, cols), Lb.device)
+    res = _BackwardResult()
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    code = _lib.npga_backward(ctypes.byref(f), float(r), _ptr(xs), _ptr(gx), _ptr(dmu), _ptr(dL), n,
+                              ctypes.byref(res), _ptr(ws), ws.numel(), _stream())
+    info = {k: getattr(res, k) for k, _ in _BackwardResult._fields_}
+    info["lambda"] = info.pop("lambda_")
+    info["status_name"] = STATUS_NAMES.get(code, str(code))
+    if code not in (NPGA_OK, 3):
+        raise NpgaError(code, "npga_backward")
+    return dmu, dL, info
+
+
+class NPGAFunction(torch.autograd.Function):
+    """x* = argmin_{x in F} ||L^T x||^2 + gamma ||x||^2 as a differentiable
+    map of (mu, L): forward by npga_solve, backward by npga_backward.
+    Usage: x = NPGAFunction.apply(mu, L_TxN, r[, gamma])."""
+
+    @staticmethod
+    def forward(ctx, mu, L_TxN, r, gamma=0.0):
+        x, info = solve(L_TxN.detach(), mu.detach(), float(r), gamma=gamma)
+        ctx.save_for_backward(mu, L_TxN, x)
+        ctx.r, ctx.gamma = float(r), float(gamma)
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        mu, L_TxN, x = ctx.saved_tensors
+        dmu, dL, _ = backward(L_TxN.detach(), mu.detach(), ctx.r, x, gx, gamma=ctx.gamma,
+                              want_dL=ctx.needs_input_grad[1])
+        return dmu.to(mu.dtype), (dL.to(L_TxN.dtype) if dL is not None else None), None, None
 
 
 def project(v, mu, r):

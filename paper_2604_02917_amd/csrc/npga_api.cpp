@@ -1214,11 +1214,120 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
   return NPGA_OK;
 }
 
-int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx,
-                  double *dl_dmu, float *dl_dL, void *ws, size_t ws_bytes, hipStream_t stream) {
-  (void)f; (void)r; (void)x_star; (void)dl_dx; (void)dl_dmu; (void)dl_dL; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return NPGA_ERR_UNSUPPORTED;
+size_t npga_backward_workspace_size(int64_t n, int64_t cols) {
+  if (n < 1 || n > NPGA_MAX_N || cols < 1) return 0;
+  const SolveLayout l = npga::solve_layout(n, cols, NPGA_PATH_GEMV);
+  const size_t npad = (size_t)256 * l.slots;
+  return align_up(l.total, 256) + align_up(sizeof(double) * (3 * npad + (size_t)cols), 256);
+}
+
+int npga_backward(const npga_factor *f, double r, const float *x_star, const float *dl_dx, double *dl_dmu,
+                  float *dl_dL, int64_t ldg, npga_backward_result *res, void *ws, size_t ws_bytes,
+                  hipStream_t stream) {
+  const auto t0 = Clock::now();
+  if (!factor_valid(f) || !x_star || !dl_dx || !dl_dmu || !is_fin(r) || !aligned(dl_dmu, 8)) return NPGA_ERR_INVALID;
+  if (dl_dL && ldg < f->n) return NPGA_ERR_INVALID;
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV);
+  if (!ws || !aligned(ws, 256) || ws_bytes < npga_backward_workspace_size(f->n, f->cols)) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  npga_options o;
+  npga_default_options(&o);
+  Carved c = carve(f, lay, ws, NPGA_PATH_GEMV);
+  const int slots = lay.slots;
+  const int64_t npad = (int64_t)256 * slots;
+  char *base = static_cast<char *>(ws);
+  double *rhs = reinterpret_cast<double *>(base + lay.off_xa);
+  double *G = reinterpret_cast<double *>(base + lay.off_ga);
+  double *u = reinterpret_cast<double *>(base + lay.off_ua);
+  double *vecs = reinterpret_cast<double *>(base + lay.off_vecs);
+  double *extra = reinterpret_cast<double *>(base + align_up(lay.total, 256));
+  double *gl = extra;
+  double *abase = extra + npad;
+  double *hab = extra + 2 * npad;
+  double *v = extra + 3 * npad;  // cols doubles
+  double *part = reinterpret_cast<double *>(c.a.partials);
+  c.a.pvec = vecs;
+  c.a.fvec = vecs + npad;
+  c.a.gvec = vecs + 2 * npad;
+  c.a.ga = G;
+
+  pin[2] = initial_state(f, r, o);
+  HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  LAUNCHCHK(npga::launch_prepare(c.a, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pin[3].n_nonfinite > 0) return NPGA_ERR_NUMERIC;
+  const double act_tol = 1e-6 * std::max(std::fabs(r), pin[3].mu_absmax);
+
+  // x* (float64) and the loss gradient; float64 gradient of f at x*
+  LAUNCHCHK(npga::launch_set_vector(c.a.xbuf1, x_star, nullptr, f->n, 0.0, nullptr, stream));
+  LAUNCHCHK(npga::launch_set_vector(gl, dl_dx, nullptr, f->n, 0.0, nullptr, stream));
+  LAUNCHCHK(npga::launch_set_vector(abase, nullptr, nullptr, f->n, 0.0, nullptr, stream));
+  LAUNCHCHK(npga::launch_precise_gradient(c.a, c.a.xbuf1, u, G, part, slots, stream));
+  LAUNCHCHK(npga::launch_adj_face(c.a, slots, act_tol, stream));
+
+  // projected CG on the face, two rounds: the second solves for the
+  // correction from the float64 residual of the first
+  Carved cg = c;
+  cg.a.mode = npga::kTailAdj;
+  cg.a.ga = nullptr;
+  hipEvent_t evs[2], ev0;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&evs[0]));
+  HIPCHK(hipEventCreate(&evs[1]));
+  struct EvGuard3 {
+    hipEvent_t e[3];
+    ~EvGuard3() {
+      for (auto &x : e) (void)hipEventDestroy(x);
+    }
+  } guard{{ev0, evs[0], evs[1]}};
+  HIPCHK(hipEventRecord(ev0, stream));
+  int cg_iters = 0, done = npga::kConverged;
+  const int max_iter = 4 * (int)std::min<int64_t>(f->n, 5000) + 100;
+  for (int round = 0; round < 2; ++round) {
+    const double *rr = gl;
+    if (round > 0) {
+      LAUNCHCHK(npga::launch_adj_rhs(f->n, f->gamma, gl, abase, hab, rhs, stream));
+      rr = rhs;
+    }
+    LAUNCHCHK(npga::launch_phase(c.st, 0, 0.0, max_iter, 0, stream));
+    LAUNCHCHK(npga::launch_adj_init(cg.a, rr, slots, stream));
+    double ms = 0.0;
+    const int64_t chunks = (int64_t)max_iter / o.check_every + 4;
+    int e = run_phase(cg, NPGA_PATH_GEMV, slots, o.check_every, chunks, stream, pin, evs, ev0, &done, &ms, nullptr);
+    if (e) return e;
+    HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    cg_iters += pin[2].cg_iter;
+    LAUNCHCHK(npga::launch_adj_accum(c.a, abase, stream));
+    // float64 product H a_total for the next right-hand side and the finish
+    LAUNCHCHK(npga::launch_precise_gradient(c.a, abase, v, hab, part, slots, stream));
+    if (done != npga::kConverged) break;
+  }
+  LAUNCHCHK(npga::launch_adj_finish(c.a, gl, abase, hab, dl_dmu, slots, stream));
+  if (dl_dL) LAUNCHCHK(npga::launch_adj_dL(abase, c.a.xbuf1, u, v, f->n, f->cols, dl_dL, ldg, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const DevState &fin = pin[3];
+  int status = NPGA_OK;
+  if (done == npga::kNumeric) status = NPGA_ERR_NUMERIC;
+  else if (done != npga::kConverged) status = NPGA_ERR_NOT_CONVERGED;
+  if (res) {
+    std::memset(res, 0, sizeof(*res));
+    res->status = status;
+    res->cg_iters = cg_iters;
+    res->support = fin.support;
+    res->return_active = fin.cg_active;
+    res->degenerate = (fin.proj_flags & 4) ? 1 : 0;
+    res->nu = fin.nu_kkt;
+    res->lambda = fin.lambda_kkt;
+    res->dl_dr = fin.adj_anu;
+    res->dl_dgamma = fin.adj_dgamma;
+    res->residual = fin.adj_res;
+    res->time_ms = ms_since(t0);
+  }
+  return status;
 }
 
 }  // extern "C"

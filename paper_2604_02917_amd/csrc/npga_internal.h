@@ -29,6 +29,7 @@ enum TailMode : int32_t {
   kTailPower = 1,  // power-method step
   kTailGrad = 2,   // gradient and objective only (no update)
   kTailCG = 3,     // refinement: conjugate gradient on the identified face
+  kTailAdj = 4,    // adjoint: projected conjugate gradient on the face's KKT system
 };
 
 // Solver state resident in the workspace.  Written only by the single
@@ -75,6 +76,10 @@ struct alignas(256) DevState {
   double cg_best_rr;    // smallest ||r||^2 seen in the current CG round
   int32_t cg_best_it;   // iteration at which it was seen
   int32_t cg_kkt;       // 1 if the round ended on the KKT test
+  // adjoint results
+  double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
+  double adj_dgamma;         // dl/dgamma
+  double adj_res;            // relative projected residual of the adjoint solve
 };
 
 // Host-visible status block copied back once per chunk of iterations.
@@ -225,6 +230,18 @@ int launch_zero_f32(float *p, int64_t count, hipStream_t s);
 int launch_b16_gemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s);
 int launch_transpose16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, uint16_t *Lt, int64_t ldlt,
                        hipStream_t s);
+
+// Adjoint (npga_adjoint.hip).  Vectors: x* in xbuf1, the face gradient
+// 2 L L^T x* in ga, the loss gradient rhs in xa, the CG iterate in xbuf0.
+int launch_adj_face(const SolveArgs &a, int slots, double act_tol, hipStream_t s);
+int launch_adj_init(const SolveArgs &a, const double *rhs, int slots, hipStream_t s);
+int launch_adj_rhs(int64_t n, double gamma, const double *gl, const double *abase, const double *hab, double *rhs,
+                   hipStream_t s);
+int launch_adj_accum(const SolveArgs &a, double *abase, hipStream_t s);
+int launch_adj_finish(const SolveArgs &a, const double *gl, const double *abase, const double *hab,
+                      double *dl_dmu, int slots, hipStream_t s);
+int launch_adj_dL(const double *ahat, const double *x, const double *u, const double *v, int64_t n, int64_t cols,
+                  float *dL, int64_t ldg, hipStream_t s);
 
 // Factor build.
 int launch_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb, int64_t ldb,

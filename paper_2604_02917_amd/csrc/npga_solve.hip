@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a) {
       gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
     } else if (a.mode == kTailGrad) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.xbuf0[i];
-    } else if (a.mode == kTailCG) {
+    } else if (a.mode == kTailCG || a.mode == kTailAdj) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.pvec[i];
     } else {
       a.gbuf0[i] = tot;
@@ -431,6 +431,8 @@ __global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
     tail_npga<E>(a, usq, redbuf);
   else if (a.mode == kTailCG)
     tail_cg<E>(a, redbuf, mbuf, ibuf);
+  else if (a.mode == kTailAdj)
+    tail_adj<E>(a, redbuf);
   else if (a.mode == kTailPower)
     tail_power<E>(a, usq, redbuf);
   else

@@ -521,4 +521,99 @@ __device__ void cg_init_body(const SolveArgs &a, double *redbuf) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint of the solution map (implicit differentiation of the KKT system on
+// the face of x*).  With H = 2 (L L^T + gamma I) restricted to the support S
+// and the constraint rows 1^T (and mu_S^T when the return constraint is in
+// the face), the adjoint a solves
+//     H_SS a + a_lam 1 + a_nu mu_S = g_S,   1^T a = 0,   mu_S^T a = 0,
+// i.e. a minimises 1/2 a^T H a - g^T a on that subspace.  Projected
+// conjugate gradients: the projector is the least-squares multiplier fit of
+// face_multipliers, the products H p come from the float32 sweep, and the
+// gradient q = H a - g is carried by linearity.  State: a in xbuf0, q in
+// gvec, p in pvec, free flags in fvec, H p in gbuf0.
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ void tail_adj(const SolveArgs &a, double *redbuf) {
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  BlockReducer<5> red{redbuf, 0};
+  double x[E], q[E], p[E], hp[E], mu[E], fr[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    const bool ok = i < n;
+    x[j] = ok ? a.xbuf0[i] : 0.0;
+    q[j] = ok ? a.gvec[i] : 0.0;
+    p[j] = ok ? a.pvec[i] : 0.0;
+    hp[j] = ok ? a.gbuf0[i] : 0.0;
+    mu[j] = ok ? a.mu[i] : 0.0;
+    fr[j] = ok ? a.fvec[i] : 0.0;
+  }
+  const bool active = st->cg_active != 0;
+  const double rr = st->cg_rr;
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) acc[0] = fma(fr[j] * p[j], hp[j], acc[0]);
+  red.sum(acc);
+  const double php = acc[0];
+  const double step = (php > 0.0 && rr > 0.0) ? rr / php : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    x[j] = fma(step, p[j], x[j]);
+    q[j] = fma(step, fr[j] * hp[j], q[j]);
+  }
+  double lam, nu;
+  face_multipliers<E>(q, mu, fr, active, red, lam, nu);
+  double rv[E];
+  double acc2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    rv[j] = (fr[j] > 0.0) ? -(q[j] - lam - nu * mu[j]) : 0.0;
+    acc2[0] = fma(rv[j], rv[j], acc2[0]);
+  }
+  red.sum(acc2);
+  const double rr_new = acc2[0];
+  const int it = st->cg_iter + 1;
+  double best = st->cg_best_rr;
+  int best_it = st->cg_best_it;
+  if (rr_new < 0.5 * best) {
+    best = rr_new;
+    best_it = it;
+  }
+  // stop: projected residual below 1e-12 of the right-hand side, or no
+  // halving for 60 iterations (the float32 products' floor; the host then
+  // re-anchors in float64)
+  const bool conv = rr_new <= 1e-24 * st->cg_rr0;
+  const bool stalled = it - best_it > 60;
+  const double beta = (rr > 0.0) ? rr_new / rr : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    p[j] = fma(beta, p[j], rv[j]);
+    if (i < n) {
+      a.xbuf0[i] = x[j];
+      a.gvec[i] = q[j];
+      a.pvec[i] = p[j];
+      a.xs[i] = (float)p[j];
+    }
+  }
+  if (tid == 0) {
+    st->cg_iter = it;
+    st->cg_rr = rr_new;
+    st->cg_best_rr = best;
+    st->cg_best_it = best_it;
+    if (!isfinite(rr_new)) {
+      st->done = kNumeric;
+    } else if (conv || stalled) {
+      st->done = kConverged;
+      st->cg_kkt = conv ? 1 : 0;
+    } else if (it >= st->max_iter) {
+      st->done = kMaxIter;
+    }
+  }
+}
+
 }  // namespace npga

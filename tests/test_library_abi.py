@@ -100,3 +100,10 @@ def test_invalid_arguments_rejected_before_launch():
     assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
                                   null, 0, null) == 6
     assert lib.npga_project(null, null, 4, 0.0, null, null, null, 0, null) == 1
+    f = api._Factor(64, 256, 64, 16, 16, 0.0, 0, 0)
+    assert lib.npga_backward(ctypes.byref(f), 0.0, null, null, null, null, 64, None, null, 0, null) == 1
+    assert lib.npga_backward(ctypes.byref(f), 0.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), 63, None, null, 0, null) == 1      # ldg < n
+    assert lib.npga_backward(ctypes.byref(f), 0.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             null, 64, None, null, 0, null) == 6                     # no workspace
+    assert lib.npga_backward_workspace_size(64, 256) > lib.npga_solve_workspace_size(64, 256, None)
