@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-str", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--frontier-seq", type=int, default=4,
                     help="single solves timed for the one-at-a-time comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -81,6 +82,32 @@ def cpu_baseline(Rt, r, gpu_grad_evals, budget_s):
                    f"gradient), scaled to the {gpu_grad_evals} gradient evaluations the GPU "
                    f"needed to reach residual 1e-6"),
     }
+
+
+def adjoint_section(npga, gen, torch, dev, spec, R, x, r):
+    """npga_backward at the C2 solution with l(w) = w^T Sigma_test w -
+    mu_test^T w: float64 face gradient, projected CG, dl/dmu and the n x T
+    dl/dL (a 1.05 GB write)."""
+    Rtest = torch.from_numpy(gen.heldout_returns_TxN(spec, 5000, gen.factor_model.HELDOUT_SEED_C5)).to(dev)
+    Lt, mut = npga.build_factor(Rtest)
+    del Rtest
+    xd = x.to(torch.float64)
+    Ltd = Lt.to(torch.float64)
+    g = (2.0 * (Ltd.T @ (Ltd @ xd)) - mut).to(torch.float32)
+    del Ltd, Lt
+    L, mu = npga.build_factor(R)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dmu, dL, info = npga.backward(L, mu, r, x, g)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    n, T = spec.n, spec.T
+    return {"workload": "dl/dmu and dl/dL at the n=5440, T=48374 solution; held-out loss (5000 periods, seed 105)",
+            "backward_ms": times[-1], "cg_iters": info["cg_iters"], "support": info["support"],
+            "return_active": info["return_active"], "residual": info["residual"],
+            "dl_dL_write_GB": 4.0 * n * T / 1e9, "status": info["status_name"]}
 
 
 def frontier_section(npga, gen, torch, dev, n_seq):
@@ -330,6 +357,10 @@ def main():
             "full_model_gap": max(f_full_str - f_full, 0.0) / max(abs(f_full), 1e-12),
             "status": info_str["status_name"],
         }
+    # adjoint of the solution map at the benchmark's solution: out-of-sample
+    # loss on a held-out block (5000 periods, seed 105), dl/dmu and dl/dL
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_section(npga, gen, torch, dev, spec, R, x, r)
     if not args.no_frontier:
         out["frontier"] = frontier_section(npga, gen, torch, dev, args.frontier_seq)
     if not args.no_cpu_baseline:

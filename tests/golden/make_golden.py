@@ -106,7 +106,48 @@ def make_c4():
     print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
 
 
+def make_c5():
+    """Adjoint at full size: the out-of-sample loss l(w) = w^T Sigma_test w -
+    mu_test^T w (held-out block: same B and drift, fresh draws, seed 105,
+    5000 periods) differentiated at the stored C2 minimiser."""
+    from oracle.adjoint import kkt_adjoint
+    spec = gen.SPECS["c2"]
+    t0 = time.time()
+    with open(os.path.join(HERE, "c2_solution.json")) as fh:
+        c2 = json.load(fh)
+    x = np.asarray(c2["x"]).astype(np.float32).astype(np.float64)  # the point the GPU is handed
+    Rtest = gen.heldout_returns_TxN(spec, 5000, gen.factor_model.HELDOUT_SEED_C5)
+    mu_t, L_t = ofactor.build_factor(Rtest.T)
+    g = (2.0 * (L_t @ (L_t.T @ x)) - mu_t).astype(np.float32).astype(np.float64)
+    Rt = gen.returns_TxN(spec)
+    mu, L = ofactor.build_factor(Rt.T)
+    del Rt
+    print(f"c5: data {time.time() - t0:.1f}s", flush=True)
+    adj = kkt_adjoint(L, 0.0, mu, c2["r"], x, c2["lambda"], c2["nu"], g)
+    print(f"c5: adjoint {time.time() - t0:.1f}s", flush=True)
+    rng = np.random.default_rng(55)
+    idx_i = rng.integers(0, spec.n, 256)
+    idx_t = rng.integers(0, spec.T, 256)
+    a, u, v = adj["a"], L.T @ x, L.T @ adj["a"]
+    samples = [[int(i), int(t), float(-2.0 * (a[i] * u[t] + x[i] * v[t]))] for i, t in zip(idx_i, idx_t)]
+    dL_max = 0.0
+    for t0_ in range(0, spec.T, 4096):
+        blk = -2.0 * (np.outer(a, u[t0_:t0_ + 4096]) + np.outer(x, v[t0_:t0_ + 4096]))
+        dL_max = max(dL_max, float(np.abs(blk).max()))
+    doc = {"workload": "c5", "n": spec.n, "T": spec.T, "test_periods": 5000,
+           "heldout_seed": gen.factor_model.HELDOUT_SEED_C5, "r": c2["r"],
+           "support": int(len(adj["support"])), "active": bool(adj["active"]),
+           "dr": adj["dr"], "dgamma": adj["dgamma"], "dmu": [float(v_) for v_ in adj["dmu"]],
+           "dL_samples": samples, "dL_max": dL_max}
+    path = os.path.join(HERE, "c5_adjoint.json")
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
+
+
 def make(name):
+    if name == "c5":
+        return make_c5()
     if name == "c3":
         return make_c3()
     if name == "c4":

@@ -87,3 +87,25 @@ def test_c4_golden_consistent():
         assert x.min() >= 0 and abs(x.sum() - 1) <= 1e-12
         assert mu @ x >= p["r"] - 1e-14
         assert factor_objective(L, 0.0, x) == pytest.approx(p["objective"], rel=1e-12)
+
+
+GOLDEN_C5 = os.path.join(os.path.dirname(__file__), "golden", "c5_adjoint.json")
+
+
+@pytest.mark.slow
+def test_c5_golden_consistent():
+    """Stored full-size adjoint: zero off the support, and the constraint
+    rows of the adjoint system (1^T a = 0, mu_S^T a = 0) give
+    sum(dl/dmu) = -dl/dr and mu^T dl/dmu = -r dl/dr."""
+    with open(GOLDEN_C5) as fh:
+        ref = json.load(fh)
+    with open(GOLDEN) as fh:
+        c2 = json.load(fh)
+    x = np.asarray(c2["x"])
+    dmu = np.asarray(ref["dmu"])
+    assert np.all(dmu[x <= 0] == 0.0) and ref["support"] == int((x > 0).sum()) and ref["active"]
+    spec = gen.SPECS["c2"]
+    Rt = gen.returns_TxN(spec)
+    mu = Rt.astype(np.float64).mean(axis=0)
+    assert dmu.sum() == pytest.approx(-ref["dr"], rel=1e-8)
+    assert mu @ dmu == pytest.approx(-ref["r"] * ref["dr"], rel=1e-6)
