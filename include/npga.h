@@ -107,6 +107,10 @@ typedef struct npga_options {
                             the support, no negative reduced cost); kept for ABI
                             stability; default 1e-9                                   */
   int32_t refine_max_iter; /* iteration cap of the refinement phase; default 20000    */
+  int32_t momentum;      /* 0: the t_k sequence of Algorithm 1 (default); 1: the constant
+                            beta = (1 - sqrt(alpha m_f))/(1 + sqrt(alpha m_f)) with
+                            m_f = 2 gamma (Sec. 3.1 "Strongly convex specialization");
+                            needs gamma > 0, else NPGA_ERR_INVALID                     */
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
                             (see npga_batched_tune), or -1 for the built-in choice
                             from the shape; default -1                               */

@@ -82,8 +82,16 @@ def power_method(L, iters, u0):
     return np.array(ray), u
 
 
+def constant_momentum(alpha, m_f):
+    """beta = (1 - sqrt(alpha m_f)) / (1 + sqrt(alpha m_f)): the constant
+    momentum of the strongly convex specialization (Sec. 3.1; Thm. npga-
+    convergence (b)), with m_f a lower curvature bound (m_f >= 2 gamma)."""
+    q = np.sqrt(alpha * m_f)
+    return float((1.0 - q) / (1.0 + q))
+
+
 def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
-         restart=False, record=False):
+         restart=False, record=False, beta_const=None):
     """Algorithm 1 with the fixed step ``alpha``.
 
     ``x0`` is projected onto F first (Algorithm 1 requires x^0 in F).
@@ -92,6 +100,8 @@ def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
     before the k-th step, using grad f(x^k).  ``restart`` applies the
     gradient-based adaptive restart of O'Donoghue and Candes (resets t to 1
     when (y^k - x^{k+1})^T (x^{k+1} - x^k) > 0); it is off by default.
+    ``beta_const`` replaces the t_k sequence by a constant momentum (used
+    from the second step on; the first step has beta = 0).
     """
     mu = np.asarray(mu, dtype=np.float64)
     x, _, _ = proj_F(np.asarray(x0, dtype=np.float64), mu, r)
@@ -117,7 +127,7 @@ def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
         if restart and (y - x_new) @ (x_new - x) > 0:
             t = 1.0
         t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
-        beta = (t - 1.0) / t_new
+        beta = (t - 1.0) / t_new if beta_const is None else beta_const
         t = t_new
         x_prev, x = x, x_new
         k += 1

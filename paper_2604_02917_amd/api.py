@@ -43,7 +43,7 @@ class _Options(ctypes.Structure):
                 ("refine", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
-                ("batch_config", ctypes.c_int32)]
+                ("momentum", ctypes.c_int32), ("batch_config", ctypes.c_int32)]
 
 
 class _BackwardResult(ctypes.Structure):
@@ -135,6 +135,7 @@ class Options:
     refine_tol: float = 1e-9
     refine_max_iter: int = 20000
     batch_config: int = -1
+    momentum: str = "fista"   # "fista" (Algorithm 1) or "constant" (strongly convex, gamma > 0)
 
     def _c(self):
         o = _Options()
@@ -145,6 +146,7 @@ class Options:
         o.warm_start, o.restart = int(self.warm_start), int(self.restart)
         o.refine_tol, o.refine_max_iter = self.refine_tol, self.refine_max_iter
         o.batch_config = self.batch_config
+        o.momentum = {"fista": 0, "constant": 1}[self.momentum]
         return o
 
 

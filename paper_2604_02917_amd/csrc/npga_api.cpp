@@ -120,7 +120,7 @@ bool options_valid(const npga_options &o) {
          o.proj_tol > 0 && o.power_iters >= 1 && is_fin(o.step_safety) && o.step_safety >= 1.0 &&
          (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
          is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0 && o.batch_config >= -1 &&
-         o.batch_config < npga::kBatchConfigs;
+         o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1);
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -182,6 +182,7 @@ DevState initial_state(const npga_factor *f, double r, const npga_options &o) {
   s.tol = o.tol;
   s.residual = INFINITY;
   s.stop_residual = INFINITY;
+  s.const_momentum = o.momentum == 1 ? 1 : 0;
   return s;
 }
 
@@ -299,6 +300,7 @@ void npga_default_options(npga_options *o) {
   o->refine_tol = 1e-9;
   o->refine_max_iter = 20000;
   o->batch_config = -1;
+  o->momentum = 0;
 }
 
 const char *npga_status_string(int status) {
@@ -332,6 +334,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   npga_default_options(&o);
   if (opt) o = *opt;
   if (!factor_valid(f) || !x || !is_fin(r) || !options_valid(o)) return NPGA_ERR_INVALID;
+  if (o.momentum == 1 && !(f->gamma > 0.0)) return NPGA_ERR_INVALID;
   const int path = resolve_path(o.path, f->n, f->cols);
   if (path == NPGA_PATH_SYRK && f->dtype != NPGA_F32) return NPGA_ERR_UNSUPPORTED;
   const SolveLayout lay = npga::solve_layout(f->n, f->cols, path);
@@ -983,6 +986,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
       !options_valid(o) || !aligned(X, 4))
     return NPGA_ERR_INVALID;
   if (o.path == NPGA_PATH_SYRK) return NPGA_ERR_UNSUPPORTED;
+  if (o.momentum == 1 && !(f->gamma > 0.0)) return NPGA_ERR_INVALID;
   for (int32_t j = 0; j < m; ++j)
     if (!is_fin(r_targets[j])) return NPGA_ERR_INVALID;
   const BatchLayout lay = batch_layout(f->n, f->cols, m);

@@ -76,6 +76,8 @@ struct alignas(256) DevState {
   double cg_best_rr;    // smallest ||r||^2 seen in the current CG round
   int32_t cg_best_it;   // iteration at which it was seen
   int32_t cg_kkt;       // 1 if the round ended on the KKT test
+  int32_t const_momentum;    // 1: beta_k = beta_const instead of the t_k sequence
+  double beta_const;
   // adjoint results
   double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
   double adj_dgamma;         // dl/dgamma
@@ -198,7 +200,7 @@ int launch_finalize(const SolveArgs &a, float *x_out, int slots, hipStream_t s);
 int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter, int32_t restart,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
-int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);
+int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);  // also beta_const
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.
 int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,

@@ -136,6 +136,9 @@ __global__ void k_set_alpha(DevState *st, double safety) {
     const double lf = 2.0 * (st->rho2 + st->gamma);
     st->lipschitz = lf;
     st->alpha = (lf > 0.0) ? 1.0 / (safety * lf) : 1.0;
+    // strongly convex specialization: m_f = 2 gamma
+    const double q = sqrt(st->alpha * 2.0 * st->gamma);
+    st->beta_const = (1.0 - q) / (1.0 + q);
   }
 }
 

@@ -107,7 +107,7 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     }
   }
   const double tn = 0.5 * (1.0 + sqrt(fma(4.0 * t, t, 1.0)));
-  const double bn = (t - 1.0) / tn;
+  const double bn = st->const_momentum ? st->beta_const : (t - 1.0) / tn;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + 256 * j;

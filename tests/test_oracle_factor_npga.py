@@ -104,3 +104,36 @@ def test_exact_mv_certificate_c1():
     rep = qp.kkt_report(H, np.zeros(spec.n), mu, r, out["x"], out["lam"], out["nu"])
     assert qp.certificate_ok(rep, tol_stat=1e-10, tol_feas=1e-13, r_scale=abs(mu).max())
     assert out["f"] == pytest.approx(factor_objective(L, 0.0, out["x"]))
+
+
+def test_constant_momentum_linear_rate():
+    """Strongly convex specialization (Sec. 3.1, Thm. npga-convergence (b)):
+    with m_f = 2 gamma and beta = (1 - sqrt(alpha m_f))/(1 + sqrt(alpha m_f)),
+    f(x^k) - f* <= (1 - sqrt(alpha m_f))^k (f(x^0) - f* + m_f/2 ||x^0 - x*||^2)
+    (the standard constant-momentum bound), and the iterates reach x*."""
+    from oracle.npga import FactorModel, constant_momentum, npga
+    from oracle.projection import proj_F
+    from oracle.reference import exact_mv
+    rng = np.random.default_rng(77)
+    n, T = 20, 12                                   # rank-deficient: the ridge gives m_f > 0
+    L = rng.standard_normal((n, T)) * 0.02
+    mu = rng.normal(5e-4, 3e-4, n)
+    r = float(np.quantile(mu, 0.6))
+    gamma = 1e-3 * float(np.sum(L * L)) / n
+    model = FactorModel(L, gamma)
+    alpha = 1.0 / model.lipschitz_exact()
+    m_f = 2.0 * gamma
+    beta = constant_momentum(alpha, m_f)
+    q = 1.0 - np.sqrt(alpha * m_f)
+    ref = exact_mv(L @ L.T + gamma * np.eye(n), mu, r, fista_tol=1e-12)
+    fstar = model.value(ref["x"])
+    x0 = np.full(n, 1.0 / n)
+    xp0, _, _ = proj_F(x0, mu, r)
+    c0 = model.value(xp0) - fstar + 0.5 * m_f * float(np.sum((xp0 - ref["x"]) ** 2))
+    for k in (10, 40, 160):
+        out = npga(model, mu, r, alpha, x0, tol=0.0, check_every=10 ** 9, max_iter=k, beta_const=beta)
+        gap = model.value(out["x"]) - fstar
+        assert gap <= q ** k * c0 * (1 + 1e-9) + 1e-18, (k, gap, q ** k * c0)
+    out = npga(model, mu, r, alpha, x0, tol=1e-12, check_every=5, max_iter=20000, beta_const=beta)
+    assert out["converged"]
+    np.testing.assert_allclose(out["x"], ref["x"], atol=1e-9)
