@@ -12,6 +12,7 @@ from .factor_model import (
     target_return,
     frontier_targets_from_mv,
     gaussian_sketch,
+    countsketch,
     random_vector,
     heldout_returns_TxN,
 )
@@ -23,6 +24,7 @@ __all__ = [
     "target_return",
     "frontier_targets_from_mv",
     "gaussian_sketch",
+    "countsketch",
     "random_vector",
     "heldout_returns_TxN",
 ]

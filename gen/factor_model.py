@@ -123,6 +123,15 @@ def gaussian_sketch(T: int, k: int, seed: int, dtype=np.float32) -> np.ndarray:
     return out
 
 
+def countsketch(T: int, k: int, seed: int):
+    """CountSketch draws (Sec. 2.3): bucket h(t) uniform on [0, k) and sign
+    s(t) = +-1 for each period t.  Returns (h int32 (T,), s float32 (T,))."""
+    rng = np.random.default_rng(seed)
+    h = rng.integers(0, k, T).astype(np.int32)
+    s = (2 * rng.integers(0, 2, T) - 1).astype(np.float32)
+    return h, s
+
+
 def random_vector(n: int, seed: int, kind: str = "normal", scale: float = 1.0) -> np.ndarray:
     """Random float64 test vectors (projection inputs, warm starts)."""
     rng = np.random.default_rng(seed)

@@ -244,8 +244,7 @@ int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, in
  *     gamma = ridge_coef * trace(Y Y^T) / n   (ridge stage; untruncated Y).
  *   L       device n x T float32 (ldl)
  *   S_opt   device T x k float32 column-major with leading dim lds >= T, or
- *           NULL to draw S on the device (NPGA_ERR_UNSUPPORTED in builds
- *           without the on-device generator)
+ *           NULL to draw S on the device from `seed` (npga_sketch_str_ex)
  *   Leff    device n x ell float32 output (ldle >= n, multiple of 4)
  *   sigma   device ell float32 output: leading singular values of Y
  *   gamma_out (host) receives gamma
@@ -257,6 +256,56 @@ int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, in
  * that eigenspace.  Synchronises `stream`.
  * ------------------------------------------------------------------------- */
 size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell);
+
+/* ---------------------------------------------------------------------------
+ * npga_sketch_str_ex - the STR build with the options of Sec. 2.3, 2.5 and
+ * App. D (npga_sketch_str is this call with a fixed ell, the trace ridge and
+ * a Gaussian S, drawn on the device when S_opt is NULL):
+ *   sketch    NPGA_SKETCH_GAUSSIAN: Phi = S given (so->S, leading dim lds)
+ *             or drawn on the device from Philox4x32-10 (Salmon et al., SC
+ *             2011; counter (t, j, 0, 0), key so->seed; Box-Muller on the
+ *             first two output words: S[t, j] = sqrt(-2 ln u1) cos(2 pi u2)
+ *             / sqrt(k), u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32);
+ *             NPGA_SKETCH_COUNT: CountSketch Phi(t, h(t)) = s(t) with the
+ *             caller's so->cs_bucket (device T int32 in [0, k), else
+ *             NPGA_ERR_INVALID) and so->cs_sign (device T float32, +-1);
+ *   ell_rule  NPGA_ELL_FIXED: ell = so->ell; NPGA_ELL_KNEE: App. D knee rule
+ *             ell = max{i : lam_i/lam_1 >= tau, lam_{i+1}/lam_i <= rho} over
+ *             the so->ell + 1 leading eigenvalues lam_i = sigma_i^2 of G
+ *             (so the cap so->ell < k); NPGA_ERR_INVALID if no i qualifies;
+ *   ridge     kappa_tar > 1: gamma = sigma_1^2/(kappa_tar - 1) (App. D, gives
+ *             kappa(Sigma_hat) <= kappa_tar); else ridge_coef tr(Y Y^T)/n.
+ * Leff (n x ell_out, ldle) and sigma (ell_out values) as npga_sketch_str;
+ * *ell_out (host, may be NULL) receives the ell used.  ws:
+ * npga_sketch_ex_workspace_size(n, T, so).  Synchronises `stream`.
+ *
+ * npga_philox_sketch - the on-device Gaussian sketch alone: S (T x k,
+ * leading dim lds >= T) as above; raw (device 2 T k uint32, or NULL)
+ * receives the two output words of entry (t, j) at 2 (t + j T).
+ * ------------------------------------------------------------------------- */
+typedef enum npga_sketch_kind { NPGA_SKETCH_GAUSSIAN = 0, NPGA_SKETCH_COUNT = 1 } npga_sketch_kind;
+typedef enum npga_ell_rule { NPGA_ELL_FIXED = 0, NPGA_ELL_KNEE = 1 } npga_ell_rule;
+typedef struct npga_str_options {
+  int32_t sketch;            /* npga_sketch_kind                               */
+  int32_t ell_rule;          /* npga_ell_rule                                  */
+  int64_t k;                 /* sketch width s; default 4096                   */
+  int64_t ell;               /* kept rank, or the knee rule's cap; default 512 */
+  double ridge_coef;         /* default 1e-4                                   */
+  double kappa_tar;          /* > 1 selects the kappa_tar ridge; default 0     */
+  double knee_tau, knee_rho; /* defaults 1e-3, 0.9                             */
+  uint64_t seed;             /* Philox key; default 3                          */
+  const float *S;            /* device Gaussian sketch or NULL                 */
+  int64_t lds;
+  const int32_t *cs_bucket;  /* device, CountSketch                            */
+  const float *cs_sign;      /* device, CountSketch                            */
+} npga_str_options;
+void npga_default_str_options(npga_str_options *so);
+size_t npga_sketch_ex_workspace_size(int64_t n, int64_t T, const npga_str_options *so);
+int npga_sketch_str_ex(const float *L, int64_t n, int64_t T, int64_t ldl, const npga_str_options *so,
+                       float *Leff, int64_t ldle, float *sigma, int64_t *ell_out, double *gamma_out,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_philox_sketch(uint64_t seed, int64_t T, int64_t k, float *S, int64_t lds, uint32_t *raw,
+                       hipStream_t stream);
 int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k,
                     int64_t ell, double ridge_coef, uint64_t seed, const float *S_opt,
                     int64_t lds, float *Leff, int64_t ldle, float *sigma, double *gamma_out,

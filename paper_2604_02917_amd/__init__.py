@@ -18,6 +18,8 @@ from .api import (  # noqa: F401
     lib_path,
     project,
     sketch_str,
+    sketch_str_ex,
+    philox_sketch,
     solve,
     spectral_norm_sq,
     syrk,

@@ -46,6 +46,14 @@ class _Options(ctypes.Structure):
                 ("momentum", ctypes.c_int32), ("batch_config", ctypes.c_int32)]
 
 
+class _StrOptions(ctypes.Structure):
+    _fields_ = [("sketch", ctypes.c_int32), ("ell_rule", ctypes.c_int32), ("k", ctypes.c_int64),
+                ("ell", ctypes.c_int64), ("ridge_coef", ctypes.c_double), ("kappa_tar", ctypes.c_double),
+                ("knee_tau", ctypes.c_double), ("knee_rho", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("S", ctypes.c_void_p), ("lds", ctypes.c_int64), ("cs_bucket", ctypes.c_void_p),
+                ("cs_sign", ctypes.c_void_p)]
+
+
 class _BackwardResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("return_active", ctypes.c_int32), ("degenerate", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -97,6 +105,11 @@ def _load():
         "npga_gradient_batched": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, i64, i32, vp, i64, vp, i32,
                                                  vp, sz, vp]),
         "npga_batched_tune": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, i32, vp, vp, vp, sz, vp]),
+        "npga_default_str_options": (None, [ctypes.POINTER(_StrOptions)]),
+        "npga_sketch_ex_workspace_size": (sz, [i64, i64, ctypes.POINTER(_StrOptions)]),
+        "npga_sketch_str_ex": (ctypes.c_int, [vp, i64, i64, i64, ctypes.POINTER(_StrOptions), vp, i64, vp,
+                                              ctypes.POINTER(i64), ctypes.POINTER(dbl), vp, sz, vp]),
+        "npga_philox_sketch": (ctypes.c_int, [u64, i64, i64, vp, i64, vp, vp]),
         "npga_backward_workspace_size": (sz, [i64, i64]),
         "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, i64,
                                          ctypes.POINTER(_BackwardResult), vp, sz, vp]),
@@ -293,6 +306,56 @@ def batched_tune(L_TxN, m, reps=5):
     _check(_lib.npga_batched_tune(ctypes.byref(f), int(m), int(reps), ctypes.byref(best), ms, _ptr(ws),
                                   ws.numel(), _stream()), "npga_batched_tune")
     return best.value, list(ms)
+
+
+def sketch_str_ex(L_TxN, k, ell, sketch="gaussian", S_kxT=None, seed=3, h=None, sgn=None, ell_rule="fixed",
+                  tau=1e-3, rho=0.9, ridge_coef=1e-4, kappa_tar=0.0):
+    """STR build with the App. D options.  sketch: "gaussian" (S_kxT given,
+    or drawn on the device from Philox with `seed`) or "count" (h: (T,)
+    int32 buckets, sgn: (T,) float32 signs, CUDA tensors).  ell_rule:
+    "fixed" or "knee" (ell is then the cap).  kappa_tar > 1 selects the
+    kappa_tar ridge.  Returns (Leff (ell_used, n), sigma (ell_used,), gamma,
+    ell_used)."""
+    Lb, n, T, ld = _as_colmajor(L_TxN)
+    if Lb.dtype != torch.float32:
+        raise ValueError("sketch_str_ex expects a float32 factor")
+    so = _StrOptions()
+    _lib.npga_default_str_options(ctypes.byref(so))
+    so.sketch = {"gaussian": 0, "count": 1}[sketch]
+    so.ell_rule = {"fixed": 0, "knee": 1}[ell_rule]
+    so.k, so.ell, so.ridge_coef, so.kappa_tar = int(k), int(ell), float(ridge_coef), float(kappa_tar)
+    so.knee_tau, so.knee_rho, so.seed = float(tau), float(rho), int(seed)
+    keep = []
+    if S_kxT is not None:
+        Sb = S_kxT.to(torch.float32).contiguous()
+        keep.append(Sb)
+        so.S, so.lds = Sb.data_ptr(), Sb.shape[1]
+    if sketch == "count":
+        hb = h.to(torch.int32).contiguous()
+        sb = sgn.to(torch.float32).contiguous()
+        keep += [hb, sb]
+        so.cs_bucket, so.cs_sign = hb.data_ptr(), sb.data_ptr()
+    ldle = ld
+    Leff = torch.zeros((ell, ldle), dtype=torch.float32, device=Lb.device)
+    sigma = torch.empty(ell, dtype=torch.float32, device=Lb.device)
+    ws = _workspace(_lib.npga_sketch_ex_workspace_size(n, T, ctypes.byref(so)), Lb.device)
+    g = ctypes.c_double(0.0)
+    eo = ctypes.c_int64(0)
+    _check(_lib.npga_sketch_str_ex(_ptr(Lb), n, T, ld, ctypes.byref(so), _ptr(Leff), ldle, _ptr(sigma),
+                                   ctypes.byref(eo), ctypes.byref(g), _ptr(ws), ws.numel(), _stream()),
+           "npga_sketch_str_ex")
+    e = int(eo.value)
+    return Leff[:e, :n], sigma[:e], g.value, e
+
+
+def philox_sketch(T, k, seed, raw=False, device="cuda:0"):
+    """The on-device Gaussian sketch: returns S as a (k, T) float32 tensor
+    (column-major T x k) and, if raw, the (k, T, 2) uint32 output words."""
+    S = torch.empty((k, T), dtype=torch.float32, device=device)
+    R = torch.empty((k, T, 2), dtype=torch.int32, device=device) if raw else None
+    _check(_lib.npga_philox_sketch(int(seed), int(T), int(k), _ptr(S), int(T), _ptr(R), _stream()),
+           "npga_philox_sketch")
+    return (S, R) if raw else S
 
 
 def backward(L_TxN, mu, r, x_star, dl_dx, gamma=0.0, want_dL=True):

@@ -138,6 +138,8 @@ struct Carved {
   DevState *st;
   float *sigma;
   int64_t lds;
+  bool precise = false;       // refinement steps with float64 products (H p by two float64 passes)
+  double *uscratch = nullptr; // cols doubles for those passes
 };
 
 Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
@@ -188,6 +190,15 @@ DevState initial_state(const npga_factor *f, double r, const npga_options &o) {
 
 // One gradient evaluation + tail, on either path.
 int step(const Carved &c, int path, int slots, hipStream_t s) {
+  if (c.precise) {
+    // H p = 2 L (L^T p) + 2 gamma p with float64 products, then the tail
+    int e = npga::launch_precise_gradient(c.a, c.a.pvec, c.uscratch, c.a.gbuf0,
+                                          reinterpret_cast<double *>(c.a.partials), slots, s);
+    if (e) return e;
+    e = npga::launch_add_ridge(c.a, s);
+    if (e) return e;
+    return npga::launch_tail(c.a, slots, 0, s);
+  }
   if (path == NPGA_PATH_SYRK) return npga::launch_symv_tail(c.a, c.sigma, c.lds, slots, s);
   int e = npga::launch_sweep(c.a, slots, s);
   if (e) return e;
@@ -428,25 +439,36 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     c.a.fvec = vecs + npad;
     c.a.gvec = vecs + 2 * npad;
     c.a.mode = npga::kTailCG;
-    // two rounds: the second re-anchors at the first round's result, which
-    // removes the drift of the gradient carried by linearity
-    for (int round = 0; round < 2; ++round) {
+    // rounds re-anchored in float64 at the previous round's result (removes
+    // the drift of the gradient carried by linearity).  A round that ends
+    // without the KKT test (stagnation of the float32 products, e.g. on a
+    // badly conditioned face) switches the following rounds to float64
+    // products.
+    bool precise = false;
+    for (int round = 0; round < 4; ++round) {
       if (round > 0) {
         HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
         LAUNCHCHK(npga::launch_precise_gradient(c.a, xa, ua, ga,
                                                 reinterpret_cast<double *>(c.a.partials), slots, stream));
       }
-      LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, stream));
+      // float32 products stagnate at their rounding floor within a few dozen
+      // iterations; with float64 products a plateau means slow progress on a
+      // badly conditioned face, so those rounds wait longer
+      LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, precise ? 1000 : 60, stream));
       LAUNCHCHK(npga::launch_cg_init(c.a, slots, stream));
       double rms = 0.0;
       const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
-      e = run_phase(c, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
+      Carved cr = c;
+      cr.precise = precise;
+      cr.uscratch = ua;
+      e = run_phase(cr, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
       if (e) return e;
       HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       refine_iters += pin[2].cg_iter;
       if (done != npga::kConverged) break;
       if (pin[2].cg_kkt && round > 0) break;
+      if (!pin[2].cg_kkt) precise = true;
     }
     refined = (done == npga::kConverged && pin[2].cg_kkt) ? 1 : 0;
   }
@@ -660,19 +682,46 @@ size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell) 
   return sketch_layout(n, T, k, ell, true).total;
 }
 
-int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k, int64_t ell,
-                    double ridge_coef, uint64_t seed, const float *S_opt, int64_t lds_opt, float *Leff,
-                    int64_t ldle, float *sigma, double *gamma_out, void *ws, size_t ws_bytes,
-                    hipStream_t stream) {
-  (void)seed;
-  if (!L || !Leff || !sigma || !gamma_out) return NPGA_ERR_INVALID;
-  if (n < 1 || n > NPGA_MAX_N || T < 1 || k < 2 || k > NPGA_MAX_N || ell < 1 || ell > k) return NPGA_ERR_INVALID;
+void npga_default_str_options(npga_str_options *so) {
+  if (!so) return;
+  std::memset(so, 0, sizeof(*so));
+  so->sketch = NPGA_SKETCH_GAUSSIAN;
+  so->ell_rule = NPGA_ELL_FIXED;
+  so->k = 4096;
+  so->ell = 512;
+  so->ridge_coef = 1e-4;
+  so->kappa_tar = 0.0;
+  so->knee_tau = 1e-3;
+  so->knee_rho = 0.9;
+  so->seed = 3;
+}
+
+size_t npga_sketch_ex_workspace_size(int64_t n, int64_t T, const npga_str_options *so) {
+  if (!so) return 0;
+  return npga_sketch_workspace_size(n, T, so->k, std::min(so->ell + 1, so->k));
+}
+
+int npga_sketch_str_ex(const float *L, int64_t n, int64_t T, int64_t ldl, const npga_str_options *so, float *Leff,
+                       int64_t ldle, float *sigma, int64_t *ell_out, double *gamma_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  if (!L || !so || !Leff || !sigma || !gamma_out) return NPGA_ERR_INVALID;
+  const int64_t k = so->k, ell_cap = so->ell;
+  if (n < 1 || n > NPGA_MAX_N || T < 1 || k < 2 || k > NPGA_MAX_N || ell_cap < 1 || ell_cap > k)
+    return NPGA_ERR_INVALID;
   if (ldl < n || (ldl % 4) != 0 || ldle < n || (ldle % 4) != 0) return NPGA_ERR_INVALID;
   if (!aligned(L, 16) || !aligned(Leff, 16)) return NPGA_ERR_INVALID;
-  if (!is_fin(ridge_coef) || ridge_coef < 0) return NPGA_ERR_INVALID;
-  if (!S_opt) return NPGA_ERR_UNSUPPORTED;  // on-device sketch generation not in this build
-  if (lds_opt < T) return NPGA_ERR_INVALID;
-  const SketchLayout lay = sketch_layout(n, T, k, ell, false);
+  if (!is_fin(so->ridge_coef) || so->ridge_coef < 0 || !is_fin(so->kappa_tar)) return NPGA_ERR_INVALID;
+  if (so->sketch != NPGA_SKETCH_GAUSSIAN && so->sketch != NPGA_SKETCH_COUNT) return NPGA_ERR_INVALID;
+  if (so->ell_rule != NPGA_ELL_FIXED && so->ell_rule != NPGA_ELL_KNEE) return NPGA_ERR_INVALID;
+  if (so->ell_rule == NPGA_ELL_KNEE &&
+      (!(so->knee_tau > 0) || !(so->knee_rho > 0) || !(so->knee_rho < 1) || ell_cap >= k))
+    return NPGA_ERR_INVALID;
+  if (so->sketch == NPGA_SKETCH_GAUSSIAN && so->S && so->lds < T) return NPGA_ERR_INVALID;
+  if (so->sketch == NPGA_SKETCH_COUNT && (!so->cs_bucket || !so->cs_sign)) return NPGA_ERR_INVALID;
+  // eigenpairs computed: ell (fixed), or ell_cap + 1 eigenvalues for the knee rule
+  const int64_t m_eig = so->ell_rule == NPGA_ELL_KNEE ? ell_cap + 1 : ell_cap;
+  const bool draw_S = so->sketch == NPGA_SKETCH_GAUSSIAN && !so->S;
+  const SketchLayout lay = sketch_layout(n, T, k, m_eig, draw_S);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   char *base = static_cast<char *>(ws);
   float *Y = reinterpret_cast<float *>(base + lay.off_Y);
@@ -693,26 +742,78 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
   float *V32 = reinterpret_cast<float *>(base + lay.off_V32);
   double *frob = reinterpret_cast<double *>(base + lay.off_frob);
   double *gdev = reinterpret_cast<double *>(base + lay.off_gamma);
+  int64_t *ell_dev = reinterpret_cast<int64_t *>(gdev + 2);
+  int32_t *bad_dev = reinterpret_cast<int32_t *>(gdev + 3);
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
-  // sketch stage: Y = L S
-  LAUNCHCHK(npga::launch_gemm_f32(L, ldl, S_opt, lds_opt, Y, lay.ldy, n, k, T, stream));
-  // truncation stage: top-ell eigenspace of G = Y^T Y
+  // sketch stage: Y = L Phi
+  if (so->sketch == NPGA_SKETCH_COUNT) {
+    LAUNCHCHK(npga::launch_zero_f32(reinterpret_cast<float *>(bad_dev), 1, stream));
+    LAUNCHCHK(npga::launch_countsketch(L, ldl, n, T, so->cs_bucket, so->cs_sign, k, Y, lay.ldy, bad_dev, stream));
+  } else {
+    const float *S = so->S;
+    int64_t lds = so->lds;
+    if (draw_S) {
+      float *Sw = reinterpret_cast<float *>(base + lay.off_S);
+      LAUNCHCHK(npga::launch_philox_sketch(so->seed, T, k, Sw, lay.ldS, nullptr, stream));
+      S = Sw;
+      lds = lay.ldS;
+    }
+    LAUNCHCHK(npga::launch_gemm_f32(L, ldl, S, lds, Y, lay.ldy, n, k, T, stream));
+  }
+  // truncation stage: eigenpairs of G = Y^T Y
   LAUNCHCHK(npga::launch_gram_f64(Y, lay.ldy, n, k, s.A, stream));
   LAUNCHCHK(npga::launch_frob(Y, lay.ldy, n, k, frob, kFrobParts, stream));
   LAUNCHCHK(npga::launch_tridiag(s, stream));
-  LAUNCHCHK(npga::launch_bisect(s, ell, stream));
+  LAUNCHCHK(npga::launch_bisect(s, m_eig, stream));
+  int64_t ell = ell_cap;
+  if (so->ell_rule == NPGA_ELL_KNEE || so->sketch == NPGA_SKETCH_COUNT) {
+    if (so->ell_rule == NPGA_ELL_KNEE) LAUNCHCHK(npga::launch_knee(s.lam, m_eig, so->knee_tau, so->knee_rho, ell_dev, stream));
+    double *h = reinterpret_cast<double *>(&pin[3]);
+    HIPCHK(hipMemcpyAsync(h, gdev + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (so->sketch == NPGA_SKETCH_COUNT && *reinterpret_cast<int32_t *>(h + 1) != 0) return NPGA_ERR_INVALID;
+    if (so->ell_rule == NPGA_ELL_KNEE) {
+      ell = *reinterpret_cast<int64_t *>(h);
+      if (ell_out) *ell_out = ell;
+      if (ell < 1) return NPGA_ERR_INVALID;  // no index passes the knee rule
+    }
+  }
+  if (ell_out) *ell_out = ell;
   LAUNCHCHK(npga::launch_inverse_iter(s, ell, lay.stride, stream));
   LAUNCHCHK(npga::launch_backtransform(s, ell, V32, stream));
   // L_eff = Y V_ell (n x ell)
   LAUNCHCHK(npga::launch_gemm_f32(Y, lay.ldy, V32, k, Leff, ldle, n, ell, k, stream));
   // ridge stage and singular values
-  LAUNCHCHK(npga::launch_finish_str(s, ell, n, ridge_coef, frob, kFrobParts, sigma, gdev, stream));
+  LAUNCHCHK(npga::launch_finish_str(s, ell, n, so->ridge_coef, frob, kFrobParts, sigma, gdev, so->kappa_tar,
+                                    stream));
   double *h = reinterpret_cast<double *>(&pin[3]);
   HIPCHK(hipMemcpyAsync(h, gdev, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   *gamma_out = h[0];
   if (!is_fin(h[0])) return NPGA_ERR_NUMERIC;
+  return NPGA_OK;
+}
+
+int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k, int64_t ell,
+                    double ridge_coef, uint64_t seed, const float *S_opt, int64_t lds_opt, float *Leff,
+                    int64_t ldle, float *sigma, double *gamma_out, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  npga_str_options so;
+  npga_default_str_options(&so);
+  so.k = k;
+  so.ell = ell;
+  so.ridge_coef = ridge_coef;
+  so.seed = seed;
+  so.S = S_opt;
+  so.lds = lds_opt;
+  return npga_sketch_str_ex(L, n, T, ldl, &so, Leff, ldle, sigma, nullptr, gamma_out, ws, ws_bytes, stream);
+}
+
+int npga_philox_sketch(uint64_t seed, int64_t T, int64_t k, float *S, int64_t lds, uint32_t *raw,
+                       hipStream_t stream) {
+  if (!S || T < 1 || k < 1 || lds < T || T > 0xffffffffLL || k > 0xffffffffLL) return NPGA_ERR_INVALID;
+  LAUNCHCHK(npga::launch_philox_sketch(seed, T, k, S, lds, raw, stream));
   return NPGA_OK;
 }
 

@@ -518,6 +518,7 @@ __global__ void k_bphase_reset(BatchArgs b, double tol, int32_t max_iter) {
     DevState *st = b.base.st + j;
     if (st->done != kConverged) continue;
     st->done = kRunning;
+    st->cg_window = 60;
     st->tol = tol;
     st->max_iter = max_iter;
     st->restart = 1;

@@ -76,6 +76,9 @@ struct alignas(256) DevState {
   double cg_best_rr;    // smallest ||r||^2 seen in the current CG round
   int32_t cg_best_it;   // iteration at which it was seen
   int32_t cg_kkt;       // 1 if the round ended on the KKT test
+  int32_t cg_window;         // iterations without halving ||r||^2 that end a refinement round
+  int32_t cg_pg;             // 1: a projected-gradient step w is pending (its H (w - x) is being swept)
+  double cg_pg_nu;           // return multiplier of that step's projection
   int32_t const_momentum;    // 1: beta_k = beta_const instead of the t_k sequence
   double beta_const;
   // adjoint results
@@ -212,8 +215,9 @@ int launch_symv(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
                             double *part, int slots, hipStream_t s);
-int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s);
+int launch_phase_reset(DevState *st, double tol, int32_t max_iter, int32_t window, hipStream_t s);
 int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s);
+int launch_add_ridge(const SolveArgs &a, hipStream_t s);  // gbuf0 += 2 gamma pvec
 
 // Batched solves (npga_batched.hip).
 int launch_bgemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s);

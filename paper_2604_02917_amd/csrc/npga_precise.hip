@@ -115,6 +115,20 @@ __global__ __launch_bounds__(256) void k_precise_reduce(const double *part, int 
   if (q == 0 && i < n) g[i] = 2.0 * (((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]);
 }
 
+// H p = (2 L L^T p) + 2 gamma p for the float64 refinement steps.
+__global__ __launch_bounds__(256) void k_add_ridge(SolveArgs a) {
+  const DevState *st = a.st;
+  if (st->done != kRunning) return;
+  const double g2 = 2.0 * st->gamma;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256)
+    a.gbuf0[i] = fma(g2, a.pvec[i], a.gbuf0[i]);
+}
+
+int launch_add_ridge(const SolveArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_ridge, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  return (int)hipGetLastError();
+}
+
 #define PRECISE_SLOT_SWITCH(slots, CALL)         \
   switch (slots) {                               \
     case 1: CALL(1); break;                      \

@@ -33,6 +33,11 @@ int launch_bisect(const SketchState &s, int64_t ell, hipStream_t st);
 int launch_inverse_iter(const SketchState &s, int64_t ell, int64_t stride, hipStream_t st);
 int launch_backtransform(const SketchState &s, int64_t ell, float *V32, hipStream_t st);
 int launch_finish_str(const SketchState &s, int64_t ell, int64_t n, double coef, const double *frob_part,
-                      int nparts, float *sigma, double *gamma_dev, hipStream_t st);
+                      int nparts, float *sigma, double *gamma_dev, double kappa_tar, hipStream_t st);
+int launch_philox_sketch(uint64_t seed, int64_t T, int64_t k, float *S, int64_t lds, uint32_t *raw,
+                         hipStream_t s);
+int launch_countsketch(const float *L, int64_t ld, int64_t n, int64_t T, const int32_t *h, const float *sgn,
+                       int64_t k, float *Y, int64_t ldy, int32_t *bad, hipStream_t s);
+int launch_knee(const double *lam, int64_t m, double tau, double rho, int64_t *ell, hipStream_t s);
 
 }  // namespace npga

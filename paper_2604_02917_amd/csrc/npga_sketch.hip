@@ -582,8 +582,10 @@ __global__ __launch_bounds__(256) void k_backtransform(SketchState s, int64_t el
   }
 }
 
+// gamma: coef tr(Y Y^T)/n (kappa_tar <= 0), or sigma_1^2/(kappa_tar - 1)
+// (App. D, target condition number).
 __global__ void k_finish_str(SketchState s, int64_t ell, int64_t n, double coef, const double *frob_part,
-                             int nparts, float *sigma, double *gamma_dev) {
+                             int nparts, float *sigma, double *gamma_dev, double kappa_tar) {
   __shared__ double buf[64];
   BlockReducer<5> red{buf, 0};
   double acc[5] = {0, 0, 0, 0, 0};
@@ -591,7 +593,7 @@ __global__ void k_finish_str(SketchState s, int64_t ell, int64_t n, double coef,
   red.sum(acc);
   for (int64_t j = threadIdx.x; j < ell; j += blockDim.x) sigma[j] = (float)sqrt(fmax(s.lam[j], 0.0));
   if (threadIdx.x == 0) {
-    gamma_dev[0] = coef * acc[0] / (double)n;
+    gamma_dev[0] = (kappa_tar > 1.0) ? fmax(s.lam[0], 0.0) / (kappa_tar - 1.0) : coef * acc[0] / (double)n;
     gamma_dev[1] = acc[0];
   }
 }
@@ -653,9 +655,9 @@ int launch_backtransform(const SketchState &s, int64_t ell, float *V32, hipStrea
 }
 
 int launch_finish_str(const SketchState &s, int64_t ell, int64_t n, double coef, const double *frob_part,
-                      int nparts, float *sigma, double *gamma_dev, hipStream_t st) {
+                      int nparts, float *sigma, double *gamma_dev, double kappa_tar, hipStream_t st) {
   hipLaunchKernelGGL(k_finish_str, dim3(1), dim3(256), 0, st, s, ell, n, coef, frob_part, nparts, sigma,
-                     gamma_dev);
+                     gamma_dev, kappa_tar);
   return (int)hipGetLastError();
 }
 

@@ -143,8 +143,9 @@ __global__ void k_set_alpha(DevState *st, double safety) {
 }
 
 // Start of the refinement phase: momentum restarts from x_k (t = 1, beta = 0).
-__global__ void k_phase_reset(DevState *st, double tol, int32_t max_iter) {
+__global__ void k_phase_reset(DevState *st, double tol, int32_t max_iter, int32_t window) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->cg_window = window;
     st->done = kRunning;
     st->tol = tol;
     st->max_iter = max_iter;
@@ -614,8 +615,8 @@ int launch_finalize(const SolveArgs &a, float *x_out, int /*slots*/, hipStream_t
   return (int)hipGetLastError();
 }
 
-int launch_phase_reset(DevState *st, double tol, int32_t max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_phase_reset, dim3(1), dim3(64), 0, s, st, tol, max_iter);
+int launch_phase_reset(DevState *st, double tol, int32_t max_iter, int32_t window, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_reset, dim3(1), dim3(64), 0, s, st, tol, max_iter, window);
   return (int)hipGetLastError();
 }
 

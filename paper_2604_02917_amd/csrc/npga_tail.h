@@ -254,6 +254,53 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   bool active = st->cg_active != 0;
   const double r = st->r;
   const double rr = st->cg_rr;
+  double *xo_p = cur ? a.xbuf0 : a.xbuf1;  // the other iterate buffer (free in this phase)
+
+  // (0) a pending projected-gradient step: x <- w, g <- g + H (w - x), and CG
+  // restarts on the face of w
+  if (st->cg_pg) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + 256 * j;
+      const bool ok = i < n;
+      x[j] = ok ? xo_p[i] : 0.0;
+      g[j] += hp[j];
+      fr[j] = (ok && x[j] > 0.0) ? 1.0 : 0.0;
+    }
+    const bool act = st->cg_pg_nu > 0.0;
+    double lam0, nu0;
+    face_multipliers<E>(g, mu, fr, act, red, lam0, nu0);
+    double acc0[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      p[j] = (fr[j] > 0.0) ? -(g[j] - lam0 - nu0 * mu[j]) : 0.0;
+      acc0[0] = fma(p[j], p[j], acc0[0]);
+    }
+    red.sum(acc0);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + 256 * j;
+      if (i < n) {
+        x_p[i] = x[j];
+        a.gvec[i] = g[j];
+        a.pvec[i] = p[j];
+        a.fvec[i] = fr[j];
+        a.xs[i] = (float)p[j];
+      }
+    }
+    if (tid == 0) {
+      st->cg_pg = 0;
+      st->cg_active = act ? 1 : 0;
+      st->cg_rr = acc0[0];
+      st->cg_rr0 = acc0[0];
+      st->cg_cycles += 1;
+      st->cg_iter += 1;
+      st->cg_best_rr = acc0[0];  // a new face: restart the stagnation window
+      st->cg_best_it = st->cg_iter;
+      if (st->cg_iter >= st->max_iter) st->done = kMaxIter;
+    }
+    return;
+  }
 
   // (1) step length along p, limited by x_i >= 0 and mu^T x >= r
   double acc[5] = {0, 0, 0, 0, 0};
@@ -320,17 +367,43 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   const double gscale = sqrt(acc2[1] / (double)n) + 1e-300;
   const double gs2 = acc2[2];  // ||g_S||^2 on the free entries
 
-  // (3) face changes once the face problem is nearly solved
+  // (3) face changes once the face problem is nearly solved (or the
+  // violation dwarfs the face residual): a projected-gradient step
+  // w = Pi_F(x - alpha g), which can free and fix many indices and the
+  // return constraint at once (the gradient-projection phase of GPCG, More
+  // and Toraldo 1991); the next sweep supplies H (w - x)
   const bool nearly = rr_new <= 1e-12 * st->cg_rr0;
-  if (dm.v < -1e-13 * gscale && (nearly || sqrt(rr_new) <= 1e-2 * (-dm.v))) {
+  const bool want_pg = (dm.v < -1e-13 * gscale && (nearly || sqrt(rr_new) <= 1e-2 * (-dm.v))) ||
+                       (active && nu < 0.0 && (nearly || sqrt(rr_new) <= 1e-2 * (-nu) * st->mu_absmax));
+  if (want_pg) {
+    const double alpha = st->alpha;
+    double w[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j)
-      if ((int64_t)(tid + 256 * j) == dm.i) fr[j] = 1.0;
-    restart = true;
-    if (tid == 0) st->cg_released += 1;
-  } else if (active && nu < 0.0 && (nearly || sqrt(rr_new) <= 1e-2 * (-nu) * st->mu_absmax)) {
-    active = false;
-    restart = true;
+    for (int j = 0; j < E; ++j) w[j] = (tid + 256 * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
+    const ProjResult pr = project_F<E>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + 256 * j;
+      if (i < n) {
+        xo_p[i] = w[j];
+        x_p[i] = x[j];
+        a.gvec[i] = g[j];
+        a.pvec[i] = w[j] - x[j];
+        a.fvec[i] = fr[j];
+        a.xs[i] = (float)(w[j] - x[j]);
+      }
+    }
+    if (tid == 0) {
+      st->cg_pg = 1;
+      st->cg_pg_nu = pr.nu;
+      st->cg_iter = st->cg_iter + 1;
+      st->cg_released += 1;
+      st->proj_flags |= pr.flags;
+      if (block == 1) st->cg_blocked += 1;
+      if (pr.flags & 2) st->done = kBracket;
+      else if (st->cg_iter >= st->max_iter) st->done = kMaxIter;
+    }
+    return;
   }
   if (restart) {
     face_multipliers<E>(g, mu, fr, active, red, lam, nu);
@@ -352,15 +425,16 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   const int it = st->cg_iter + 1;
   const bool kkt = !restart && rr_new <= 1e-20 * gs2 && dm.v >= -1e-12 * gscale &&
                    !(active && nu < 0.0);
-  // stagnation: no halving of ||r||^2 for 60 iterations ends the round (the
-  // host re-anchors the gradient in float64 and starts the next round)
+  // stagnation: no halving of ||r||^2 for cg_window iterations ends the
+  // round (the host re-anchors the gradient in float64 and starts the next
+  // round)
   double best = st->cg_best_rr;
   int best_it = st->cg_best_it;
   if (restart || rr_new < 0.5 * best) {
     best = rr_new;
     best_it = st->cg_iter + 1;
   }
-  const bool stalled = (st->cg_iter + 1) - best_it > 60;
+  const bool stalled = (st->cg_iter + 1) - best_it > st->cg_window;
   bool stop = false;
   if (it % st->check_every == 0 || kkt || stalled) {
     double w[E];
@@ -517,6 +591,7 @@ __device__ void cg_init_body(const SolveArgs &a, double *redbuf) {
     st->cg_best_rr = acc[0];
     st->cg_best_it = 0;
     st->cg_kkt = 0;
+    st->cg_pg = 0;
     st->ticket = 0u;
   }
 }

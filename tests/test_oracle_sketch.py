@@ -120,3 +120,18 @@ def test_knee_rule_and_kappa_target():
     assert sketch.ell_knee(lam, 1e-1, 0.9) == 2     # tau = 0.1 leaves i <= 3; 10 -> 9.5 is no knee
     g = sketch.gamma_kappa_target(3.0, 101.0)
     assert (9.0 + g) / g == pytest.approx(101.0)
+
+
+def test_countsketch_apply_matches_dense():
+    """L Phi by the bucket scatter equals the product with the dense
+    CountSketch matrix Phi(t, h(t)) = s(t), and E[Phi Phi^T] = I."""
+    import gen
+    from oracle.sketch import countsketch_apply
+    rng = np.random.default_rng(8)
+    L = rng.standard_normal((7, 50))
+    h, s = gen.countsketch(50, 9, 4)
+    Phi = np.zeros((50, 9))
+    Phi[np.arange(50), h] = s
+    np.testing.assert_allclose(countsketch_apply(L, h, s, 9), L @ Phi, rtol=1e-14, atol=1e-14)
+    # each row of Phi has one +-1: diag(Phi Phi^T) = 1 exactly
+    assert np.all(np.diag(Phi @ Phi.T) == 1.0)
