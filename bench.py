@@ -39,10 +39,33 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe-gb", type=float, default=0.0,
+                    help="run one plain device copy of this size first (calibrates HBM byte counters)")
     ap.add_argument("--frontier-seq", type=int, default=4,
                     help="single solves timed for the one-at-a-time comparison")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
+
+
+def sweep_traffic(path_used):
+    """HBM bytes per sweep launch from the committed counter passes
+    (profiles/k_sweep_c2_traffic.json), or None when the fused sweep's
+    source has changed since they were taken (or another path ran)."""
+    import hashlib
+    import re
+    if path_used != 1:
+        return None
+    try:
+        with open(os.path.join(ROOT, "profiles", "k_sweep_c2_traffic.json")) as fh:
+            doc = json.load(fh)
+        src = open(os.path.join(ROOT, doc["source_file"])).read()
+    except (OSError, ValueError, KeyError):
+        return None
+    m = re.search(r"template <int E, typename TL>\n__global__ __launch_bounds__\(256\) void k_sweep\(SolveArgs a\) "
+                  r"\{.*?\n\}\n", src, re.S)
+    if not m or hashlib.sha256(m.group(0).encode()).hexdigest() != doc["source_sha256"]:
+        return None
+    return doc["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(Rt, r, gpu_grad_evals, budget_s):
@@ -201,6 +224,14 @@ def main():
     torch.cuda.synchronize()
     n, T = spec.n, spec.T
 
+    if args.copy_probe_gb > 0:
+        nel = int(args.copy_probe_gb * 1e9) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     def step():
         L, mu = npga.build_factor(R)
         x, info = npga.solve(L, mu, r, path=args.path)
@@ -257,7 +288,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": sweep_traffic(last["path_used"]),
             "kernel": "k_sweep (fused L^T x and L u, one read of L)" if last["path_used"] == 1
                       else "k_symv_tail",
             "bytes_per_launch": bytes_per_launch,
@@ -342,7 +373,29 @@ def main():
         xs_, info_str = npga.solve(Leff, mu, r, gamma=gamma)
         _, f_full_str = npga.gradient(L, xs_, 0.0)
         f_full = last["objective"]
+        # the same build with S drawn on the device (Philox), and with a
+        # CountSketch (k = 4096 buckets, draws seed 3)
+        variants = {}
+        hc, sc = gen.countsketch(T, 4096, 3)
+        hcd, scd = torch.from_numpy(hc).to(dev), torch.from_numpy(sc).to(dev)
+        for name, kw in (("philox_gaussian", dict(sketch="gaussian", seed=3)),
+                         ("countsketch", dict(sketch="count", h=hcd, sgn=scd))):
+            tv = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                Le_v, sig_v, g_v, _ = npga.sketch_str_ex(L, 4096, 512, ridge_coef=1e-4, **kw)
+                torch.cuda.synchronize()
+                tv.append((time.perf_counter() - tb) * 1e3)
+            xv, inf_v = npga.solve(Le_v, mu, r, gamma=g_v)
+            _, f_full_v = npga.gradient(L, xv, 0.0)
+            variants[name] = {"build_ms": tv[-1], "time_to_tol_s": inf_v["time_to_tol_ms"] / 1e3,
+                              "sigma_1": float(sig_v[0].item()),
+                              "full_model_gap": max(f_full_v - last["objective"], 0.0) / max(abs(last["objective"]), 1e-12),
+                              "status": inf_v["status_name"]}
+            del Le_v
         out["str"] = {
+            "variants": variants,
             "workload": "c2 factor, Gaussian sketch k=4096 (seed 3), ell=512, gamma=1e-4 tr(YY^T)/n",
             "build_ms": builds[-1],
             "time_to_tol_s": info_str["time_to_tol_ms"] / 1e3,
