@@ -256,8 +256,8 @@ def main():
     bytes_per_launch = 4.0 * n * (T if last["path_used"] == 1 else n)
     achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None
     iters = last["iters"]
-    # gradient evaluations to the stopping point: power method + iterations 0..iters
-    grad_evals = 30 + iters + 1
+    # gradient evaluations to the stopping point: step-size estimate + iterations 0..iters
+    grad_evals = last["step_sweeps"] + iters + 1
 
     xh = x.cpu().numpy().astype(np.float64)
     feas = {
@@ -304,6 +304,7 @@ def main():
             "return_active": last["return_active"],
             "solve_ms_incl_refinement": solve_ms,
             "setup_ms": last["setup_ms"],
+            "step_estimate_sweeps": last["step_sweeps"],
             "ms_per_iteration": (tol_s * 1e3 - last["setup_ms"]) / max(iters, 1),
             "status": last["status_name"],
             "feasibility": feas,

@@ -94,8 +94,9 @@ typedef struct npga_options {
   int32_t max_iter;      /* default 200000                                            */
   double proj_tol;       /* dual search stops at |mu^T x - r| <= proj_tol * max(|r|, max|mu|);
                             default 1e-12 (the search normally finishes exactly)      */
-  int32_t power_iters;   /* power-method iterations for ||L_eff||_2 (Sec. 3.1 Remark);
-                            default 30                                                 */
+  int32_t power_iters;   /* sweeps for ||L_eff||_2 (Sec. 3.1 Remark): the cap of the
+                            Lanczos estimate (at most 64), or the power-method count;
+                            default 20                                                 */
   double step_safety;    /* alpha = 1 / (step_safety * L_f_estimate), >= 1; default 1.05 */
   int32_t refine;        /* 1 = FP64 KKT refinement after the stop; default 1         */
   int32_t path;          /* npga_path; default NPGA_PATH_AUTO                          */
@@ -111,6 +112,10 @@ typedef struct npga_options {
                             beta = (1 - sqrt(alpha m_f))/(1 + sqrt(alpha m_f)) with
                             m_f = 2 gamma (Sec. 3.1 "Strongly convex specialization");
                             needs gamma > 0, else NPGA_ERR_INVALID                     */
+  int32_t step_estimator; /* 0: Lanczos on L_eff L_eff^T, stopped when the largest Ritz
+                            value changes by < 1e-10 (default); 1: the power method of
+                            the paper's Remark.  Both approach ||L_eff||^2 from below;
+                            step_safety covers the remainder                           */
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
                             (see npga_batched_tune), or -1 for the built-in choice
                             from the shape; default -1                               */
@@ -125,7 +130,7 @@ typedef struct npga_result {
   int32_t return_active;  /* 1 if the return constraint binds (nu > 0)              */
   int32_t refined;        /* 1 if the refinement ended on its KKT test               */
   int32_t path_used;      /* npga_path actually run                                  */
-  int32_t reserved;
+  int32_t step_sweeps;    /* gradient sweeps spent on the step-size estimate        */
   double residual;        /* stopping residual when the test first passed           */
   double final_residual;  /* residual of the returned x                             */
   double objective;       /* f(x) of the returned x, accumulated in float64         */
@@ -219,9 +224,12 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  *   fused single-pass sweep.  x device float32 (n), g device float64 (n),
  *   f_out (host, may be NULL).  ws as for npga_solve.
  *
- * npga_spectral_norm_sq - ||L_eff||_2^2 estimated by `iters` power-method
- *   steps from a seeded Gaussian start (Sec. 3.1 Remark); the returned value
- *   is the last Rayleigh value ||L_eff^T u||^2, a lower bound.
+ * npga_spectral_norm_sq - ||L_eff||_2^2 estimated from a seeded Gaussian
+ *   start (Sec. 3.1 Remark): method 1 = `iters` power-method steps (the last
+ *   Rayleigh value ||L_eff^T u||^2); method 0 = Lanczos on L_eff L_eff^T, at
+ *   most min(iters, 64) steps, stopped when the largest Ritz value changes
+ *   by less than 1e-10 relative.  Both are lower bounds.  steps_out (host,
+ *   may be NULL) receives the sweeps used.
  *
  * npga_syrk - Sigma = L L^T (n x n float32, column-major, leading dim lds,
  *   both triangles written) by float32 MFMA with float64 accumulation
@@ -231,8 +239,9 @@ int npga_project(const double *v, const double *mu, int64_t n, double r, double 
                  double *nu_tau, void *ws, size_t ws_bytes, hipStream_t stream);
 int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out,
                   void *ws, size_t ws_bytes, hipStream_t stream);
-int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed,
-                          double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, int32_t method,
+                          double *out, int32_t *steps_out, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
 int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
               hipStream_t stream);
 

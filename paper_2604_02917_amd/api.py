@@ -43,7 +43,8 @@ class _Options(ctypes.Structure):
                 ("refine", ctypes.c_int32), ("path", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
-                ("momentum", ctypes.c_int32), ("batch_config", ctypes.c_int32)]
+                ("momentum", ctypes.c_int32), ("step_estimator", ctypes.c_int32),
+                ("batch_config", ctypes.c_int32)]
 
 
 class _StrOptions(ctypes.Structure):
@@ -65,7 +66,7 @@ class _Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("support", ctypes.c_int32),
                 ("return_active", ctypes.c_int32), ("refined", ctypes.c_int32),
-                ("path_used", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("path_used", ctypes.c_int32), ("step_sweeps", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("final_residual", ctypes.c_double),
                 ("objective", ctypes.c_double), ("nu", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("alpha", ctypes.c_double),
@@ -91,7 +92,7 @@ def _load():
                                       ctypes.POINTER(_Result), vp, sz, vp]),
         "npga_project": (ctypes.c_int, [vp, vp, i64, dbl, vp, vp, vp, sz, vp]),
         "npga_gradient": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp, sz, vp]),
-        "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, vp, vp, sz, vp]),
+        "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, i32, vp, vp, vp, sz, vp]),
         "npga_syrk": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
         "npga_to_bf16": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
         "npga_build_factor_workspace_size": (sz, [i64, i64]),
@@ -138,7 +139,7 @@ class Options:
     check_every: int = 5
     max_iter: int = 200000
     proj_tol: float = 1e-12
-    power_iters: int = 30
+    power_iters: int = 20
     step_safety: float = 1.05
     refine: bool = True
     path: str = "auto"
@@ -149,6 +150,7 @@ class Options:
     refine_max_iter: int = 20000
     batch_config: int = -1
     momentum: str = "fista"   # "fista" (Algorithm 1) or "constant" (strongly convex, gamma > 0)
+    step_estimator: str = "lanczos"   # or "power" (the paper's Remark)
 
     def _c(self):
         o = _Options()
@@ -160,6 +162,7 @@ class Options:
         o.refine_tol, o.refine_max_iter = self.refine_tol, self.refine_max_iter
         o.batch_config = self.batch_config
         o.momentum = {"fista": 0, "constant": 1}[self.momentum]
+        o.step_estimator = {"lanczos": 0, "power": 1}[self.step_estimator]
         return o
 
 
@@ -429,15 +432,19 @@ def gradient(L_TxN, x, gamma=0.0):
     return g, fv.value
 
 
-def spectral_norm_sq(L_TxN, iters=30, seed=1):
+def spectral_norm_sq(L_TxN, iters=30, seed=1, method="power", return_steps=False):
+    """||L||_2^2 estimate (Sec. 3.1 Remark): method "power" (iters steps) or
+    "lanczos" (at most min(iters, 64) steps, stopped on convergence)."""
     Lb, n, cols, ld = _as_colmajor(L_TxN)
     mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
     ws = _workspace(_lib.npga_solve_workspace_size(n, cols, None), Lb.device)
     out = ctypes.c_double(0.0)
+    st = ctypes.c_int32(0)
     f = _factor(Lb, n, cols, ld, mu, 0.0)
-    _check(_lib.npga_spectral_norm_sq(ctypes.byref(f), int(iters), int(seed), ctypes.byref(out),
-                                      _ptr(ws), ws.numel(), _stream()), "npga_spectral_norm_sq")
-    return out.value
+    _check(_lib.npga_spectral_norm_sq(ctypes.byref(f), int(iters), int(seed), {"lanczos": 0, "power": 1}[method],
+                                      ctypes.byref(out), ctypes.byref(st), _ptr(ws), ws.numel(), _stream()),
+           "npga_spectral_norm_sq")
+    return (out.value, st.value) if return_steps else out.value
 
 
 def sketch_str(L_TxN, S_kxT, ell, ridge_coef=1e-4, seed=0):

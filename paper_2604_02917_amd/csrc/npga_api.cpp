@@ -120,7 +120,8 @@ bool options_valid(const npga_options &o) {
          o.proj_tol > 0 && o.power_iters >= 1 && is_fin(o.step_safety) && o.step_safety >= 1.0 &&
          (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
          is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0 && o.batch_config >= -1 &&
-         o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1);
+         o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1) &&
+         (o.step_estimator == 0 || o.step_estimator == 1);
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -203,6 +204,25 @@ int step(const Carved &c, int path, int slots, hipStream_t s) {
   int e = npga::launch_sweep(c.a, slots, s);
   if (e) return e;
   return npga::launch_reduce_tail(c.a, slots, s);
+}
+
+// ||L_eff||_2^2 by Lanczos on L_eff L_eff^T (default: the largest Ritz value
+// stops changing after about a dozen sweeps on a factor spectrum) or by the
+// power method of the paper's Remark (power_iters sweeps); then alpha.
+int estimate_step(const Carved &c, int path, int slots, const npga_options &o, hipStream_t s) {
+  if (npga::launch_random_unit(c.a.xbuf0, c.a.xs, c.a.n, o.seed, s)) return 1;
+  Carved cp = c;
+  int steps = o.power_iters;
+  if (o.step_estimator == 0) {
+    cp.a.mode = npga::kTailLanczos;
+    if (npga::launch_lanczos_init(cp.a, s)) return 1;
+    steps = std::min(o.power_iters, npga::kLanczosMax);
+  } else {
+    cp.a.mode = npga::kTailPower;
+  }
+  for (int i = 0; i < steps; ++i)
+    if (step(cp, path, slots, s)) return 1;
+  return npga::launch_set_alpha(c.st, o.step_safety, s);
 }
 
 int map_done(int done) {
@@ -301,7 +321,7 @@ void npga_default_options(npga_options *o) {
   o->check_every = 5;
   o->max_iter = 200000;
   o->proj_tol = 1e-12;
-  o->power_iters = 30;
+  o->power_iters = 20;
   o->step_safety = 1.05;
   o->refine = 1;
   o->path = NPGA_PATH_AUTO;
@@ -312,6 +332,7 @@ void npga_default_options(npga_options *o) {
   o->refine_max_iter = 20000;
   o->batch_config = -1;
   o->momentum = 0;
+  o->step_estimator = 0;
 }
 
 const char *npga_status_string(int status) {
@@ -391,14 +412,8 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   if (path == NPGA_PATH_SYRK)
     LAUNCHCHK(npga::launch_syrk(static_cast<const float *>(f->L), f->n, f->cols, f->ld, c.sigma, c.lds, stream));
 
-  // step size: power method on L_eff (Sec. 3.1 Remark), alpha = 1/(safety L_f_hat)
-  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, o.seed, stream));
-  {
-    Carved cp = c;
-    cp.a.mode = npga::kTailPower;
-    for (int i = 0; i < o.power_iters; ++i) LAUNCHCHK(step(cp, path, slots, stream));
-  }
-  LAUNCHCHK(npga::launch_set_alpha(c.st, o.step_safety, stream));
+  // step size alpha = 1/(safety L_f_hat) from ||L_eff||_2^2 (Sec. 3.1 Remark)
+  LAUNCHCHK(estimate_step(c, path, slots, o, stream));
 
   // x^0 = Pi_F(x_in or 1/n)
   LAUNCHCHK(npga::launch_set_vector(c.a.xbuf0, o.warm_start ? x : nullptr, nullptr, f->n,
@@ -491,6 +506,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     res->return_active = fin.nu_c > 0.0 ? 1 : 0;
     res->refined = refined;
     res->path_used = path;
+    res->step_sweeps = o.step_estimator == 0 ? after_main.lz_m : o.power_iters;
     res->residual = after_main.stop_residual;
     res->final_residual = fin.residual;
     res->objective = fin.objective;
@@ -567,27 +583,26 @@ int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out
   return NPGA_OK;
 }
 
-int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, double *out, void *ws,
-                          size_t ws_bytes, hipStream_t stream) {
-  if (!factor_valid(f) || !out || iters < 1) return NPGA_ERR_INVALID;
+int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, int32_t method, double *out,
+                          int32_t *steps_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!factor_valid(f) || !out || iters < 1 || (method != 0 && method != 1)) return NPGA_ERR_INVALID;
   const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
   npga_options o;
   npga_default_options(&o);
+  o.power_iters = iters;
+  o.seed = seed;
+  o.step_estimator = method;
   Carved c = carve(f, lay, ws, NPGA_PATH_GEMV);
-  c.a.mode = npga::kTailPower;
   pin[2] = initial_state(f, 0.0, o);
   HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
-  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, seed, stream));
-  for (int i = 0; i < iters; ++i) {
-    LAUNCHCHK(npga::launch_sweep(c.a, lay.slots, stream));
-    LAUNCHCHK(npga::launch_reduce_tail(c.a, lay.slots, stream));
-  }
+  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, lay.slots, o, stream));
   HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   *out = pin[3].rho2;
+  if (steps_out) *steps_out = method == 0 ? pin[3].lz_m : iters;
   return NPGA_OK;
 }
 
@@ -1130,14 +1145,8 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   for (int32_t j = 0; j < m; ++j)
     if (r_targets[j] > mu_max) return NPGA_ERR_INFEASIBLE;
 
-  // shared step size: power method on L (Sec. 3.1 Remark)
-  LAUNCHCHK(npga::launch_random_unit(c.a.xbuf0, c.a.xs, f->n, o.seed, stream));
-  {
-    Carved cp = c;
-    cp.a.mode = npga::kTailPower;
-    for (int i = 0; i < o.power_iters; ++i) LAUNCHCHK(step(cp, NPGA_PATH_GEMV, slots, stream));
-  }
-  LAUNCHCHK(npga::launch_set_alpha(c.st, o.step_safety, stream));
+  // shared step size from ||L||_2^2 (Sec. 3.1 Remark)
+  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, slots, o, stream));
 
   // per-target states, x^0 = Pi_F(x_in or 1/n)
   for (int32_t j = 0; j < m; ++j) {
@@ -1226,6 +1235,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
     rj.return_active = fin.nu_c > 0.0 ? 1 : 0;
     rj.refined = refined[j];
     rj.path_used = NPGA_PATH_GEMV;
+    rj.step_sweeps = o.step_estimator == 0 ? after_main[j].lz_m : o.power_iters;
     rj.residual = am.stop_residual;
     rj.final_residual = fin.residual;
     rj.objective = fin.objective;

@@ -509,6 +509,7 @@ __global__ void k_bcopy_step(BatchArgs b, const DevState *src) {
     b.base.st[j].lipschitz = src->lipschitz;
     b.base.st[j].rho2 = src->rho2;
     b.base.st[j].beta_const = src->beta_const;
+    b.base.st[j].lz_m = src->lz_m;
   }
 }
 

@@ -30,7 +30,10 @@ enum TailMode : int32_t {
   kTailGrad = 2,   // gradient and objective only (no update)
   kTailCG = 3,     // refinement: conjugate gradient on the identified face
   kTailAdj = 4,    // adjoint: projected conjugate gradient on the face's KKT system
+  kTailLanczos = 5,  // Lanczos step for ||L_eff||_2^2 (step-size estimate)
 };
+
+constexpr int kLanczosMax = 64;  // Lanczos steps kept in DevState
 
 // Solver state resident in the workspace.  Written only by the single
 // "tail" workgroup of a launch and read by every workgroup of later
@@ -81,6 +84,11 @@ struct alignas(256) DevState {
   double cg_pg_nu;           // return multiplier of that step's projection
   int32_t const_momentum;    // 1: beta_k = beta_const instead of the t_k sequence
   double beta_const;
+  // Lanczos tridiagonal T_m of L_eff L_eff^T (step-size estimate)
+  int32_t lz_m;
+  double lz_theta;                 // largest Ritz value of T_m
+  double lz_alpha[kLanczosMax];
+  double lz_beta[kLanczosMax];
   // adjoint results
   double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
   double adj_dgamma;         // dl/dgamma
@@ -204,6 +212,7 @@ int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
 int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);  // also beta_const
+int launch_lanczos_init(const SolveArgs &a, hipStream_t s);
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.
 int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,

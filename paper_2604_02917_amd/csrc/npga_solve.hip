@@ -133,6 +133,7 @@ __global__ void k_set_tolphi(DevState *st, double proj_tol) {
 // alpha = 1 / (safety * L_f_hat), L_f_hat = 2 (rho^2 + gamma) (Sec. 3.1 "Fixed step").
 __global__ void k_set_alpha(DevState *st, double safety) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (st->done == kConverged) st->done = kRunning;  // end of a Lanczos estimate
     const double lf = 2.0 * (st->rho2 + st->gamma);
     st->lipschitz = lf;
     st->alpha = (lf > 0.0) ? 1.0 / (safety * lf) : 1.0;
@@ -439,6 +440,8 @@ __global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
     tail_adj<E>(a, redbuf);
   else if (a.mode == kTailPower)
     tail_power<E>(a, usq, redbuf);
+  else if (a.mode == kTailLanczos)
+    tail_lanczos<E>(a, redbuf);
   else
     tail_grad<E>(a, usq, redbuf);
 }
@@ -622,6 +625,20 @@ int launch_phase_reset(DevState *st, double tol, int32_t max_iter, int32_t windo
 
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s) {
   hipLaunchKernelGGL(k_set_tolphi, dim3(1), dim3(64), 0, s, st, proj_tol);
+  return (int)hipGetLastError();
+}
+
+// Lanczos start: v_0 = xbuf0 (the random unit vector), v_{-1} = 0.
+__global__ __launch_bounds__(256) void k_lanczos_init(SolveArgs a) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) a.xbuf1[i] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.st->lz_m = 0;
+    a.st->lz_theta = 0.0;
+  }
+}
+
+int launch_lanczos_init(const SolveArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_init, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return (int)hipGetLastError();
 }
 

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restri
     }
     d = wave_sum_f32(d);
     if (lane == 0) {
-      if (a.mode == kTailPower)
+      if (a.mode == kTailPower || a.mode == kTailLanczos)
         gk[col] = (double)d;
       else if (a.mode == kTailCG || a.mode == kTailAdj)
         gk[col] = 2.0 * (double)d + 2.0 * st->gamma * pv[col];

@@ -180,6 +180,97 @@ __device__ void tail_power(const SolveArgs &a, double usq_total, double *redbuf)
 }
 
 
+// Largest eigenvalue of the m x m symmetric tridiagonal T (diagonal al,
+// off-diagonal be) by bisection on Sturm counts (one thread).
+__device__ inline double tridiag_max_eig(const double *al, const double *be, int m) {
+  double lo = 1e308, hi = -1e308;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < m ? fabs(be[i]) : 0.0);
+    lo = fmin(lo, al[i] - r);
+    hi = fmax(hi, al[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    int cnt = 0;  // eigenvalues < mid
+    double q = al[0] - mid;
+    cnt += q < 0.0;
+    for (int i = 1; i < m; ++i) {
+      const double qq = (fabs(q) < 1e-300) ? -1e-300 : q;
+      q = al[i] - mid - be[i - 1] * be[i - 1] / qq;
+      cnt += q < 0.0;
+    }
+    if (cnt == m) hi = mid;  // all below mid: the largest is below
+    else lo = mid;
+  }
+  return hi;
+}
+
+// One Lanczos step on A = L_eff L_eff^T (gbuf0 = A v from the sweep, v in
+// xbuf0, the previous basis vector in xbuf1).  The largest Ritz value of
+// T_m is a lower bound of ||L_eff||_2^2 that converges far faster than the
+// power method's Rayleigh quotient on a clustered top spectrum; the phase
+// ends when it stops changing (relative 1e-10) or the recurrence breaks
+// down, and rho2 receives it.
+template <int E>
+__device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  BlockReducer<5> red{redbuf, 0};
+  const int j = st->lz_m;
+  const double bprev = (j > 0) ? st->lz_beta[j - 1] : 0.0;
+  double w[E], v[E], vp[E];
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int64_t i = tid + 256 * q;
+    const bool ok = i < a.n;
+    w[q] = ok ? a.gbuf0[i] : 0.0;
+    v[q] = ok ? a.xbuf0[i] : 0.0;
+    vp[q] = ok ? a.xbuf1[i] : 0.0;
+    acc[0] = fma(v[q], w[q], acc[0]);
+  }
+  red.sum(acc);
+  const double al = acc[0];
+  double acc2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    w[q] = w[q] - al * v[q] - bprev * vp[q];
+    acc2[0] = fma(w[q], w[q], acc2[0]);
+  }
+  red.sum(acc2);
+  const double be = sqrt(acc2[0]);
+  __shared__ double theta_sh;
+  if (tid == 0) {
+    st->lz_alpha[j] = al;
+    st->lz_beta[j] = be;
+    theta_sh = tridiag_max_eig(st->lz_alpha, st->lz_beta, j + 1);
+  }
+  __syncthreads();
+  const double theta = theta_sh;
+  const bool conv = (j > 0 && fabs(theta - st->lz_theta) <= 1e-10 * theta) || !(be > 1e-13 * theta) ||
+                    j + 1 >= kLanczosMax;
+  if (!conv) {
+    const double inv = 1.0 / be;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int64_t i = tid + 256 * q;
+      if (i < a.n) {
+        a.xbuf1[i] = v[q];
+        a.xbuf0[i] = w[q] * inv;
+        a.xs[i] = (float)(w[q] * inv);
+      }
+    }
+  }
+  if (tid == 0) {
+    st->lz_m = j + 1;
+    st->lz_theta = theta;
+    st->rho2 = theta;
+    if (!isfinite(theta)) st->done = kNumeric;
+    else if (conv) st->done = kConverged;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Float64 KKT refinement by conjugate gradients on the identified face.
 //

@@ -88,6 +88,25 @@ def test_spectral_norm_estimate(npga):
     assert est >= 0.98 * lmax
 
 
+@pytest.mark.parametrize("n,T,K", [(300, 2000, 10), (2000, 6000, 5), (517, 3001, 3)])
+def test_lanczos_estimate(npga, n, T, K):
+    """Lanczos on L L^T: the largest Ritz value is a lower bound of
+    lambda_max that reaches it to float32-product accuracy within the step
+    cap, while the power method with as many steps is still short of it on
+    the clustered top spectrum of a factor model."""
+    spec = spec_with("c2", n, T, seed=20 + n)
+    spec = spec.__class__(**{**spec.__dict__, "K": K})
+    Rt = gen.returns_TxN(spec)
+    L = Rt.T.astype(np.float64)
+    lmax = np.linalg.eigvalsh(L @ L.T)[-1]
+    est, steps = npga.spectral_norm_sq(to_dev(Rt), iters=40, seed=5, method="lanczos", return_steps=True)
+    pw = npga.spectral_norm_sq(to_dev(Rt), iters=steps, seed=5, method="power")
+    banner(f"lanczos n={n} K={K}: {steps} steps, rel err {(lmax - est) / lmax:.1e}; power {(lmax - pw) / lmax:.1e}")
+    assert est <= lmax * (1 + 1e-6)
+    assert est >= lmax * (1 - 1e-6)
+    assert steps < 40
+
+
 @pytest.mark.parametrize("n,T", [(64, 256), (1000, 3001), (5440, 2000), (37, 100)])
 def test_build_factor_matches_oracle(npga, n, T):
     banner(f"build_factor n={n} T={T}")

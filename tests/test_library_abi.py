@@ -44,7 +44,7 @@ def test_default_options_and_status_strings():
     from paper_2604_02917_amd import api
     o = api._Options()
     api._lib.npga_default_options(ctypes.byref(o))
-    assert o.tol == 1e-6 and o.check_every == 5 and o.power_iters == 30
+    assert o.tol == 1e-6 and o.check_every == 5 and o.power_iters == 20 and o.step_estimator == 0
     assert o.step_safety == 1.05 and o.refine == 1 and o.batch_config == -1 and o.momentum == 0
     for code in range(9):
         assert api.status_string(code) and api.status_string(code) != "unknown status"
