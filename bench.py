@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--no-syrk-compare", action="store_true")
     ap.add_argument("--no-str", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-restart-compare", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe-gb", type=float, default=0.0,
@@ -311,6 +312,14 @@ def main():
         },
         "generator_s": t_gen,
     }
+    # Algorithm 1 with the adaptive momentum restart option (not the paper's
+    # default; reported beside the timed path)
+    if not args.no_restart_compare:
+        L, mu = npga.build_factor(R)
+        npga.solve(L, mu, r, restart=True)
+        _, info_r = npga.solve(L, mu, r, restart=True)
+        out["restart_variant"] = {"time_to_tol_s": info_r["time_to_tol_ms"] / 1e3, "iters_to_tol": info_r["iters"],
+                                  "objective": info_r["objective"], "status": info_r["status_name"]}
     # the covariance path (Sigma = L L^T by MFMA, then a SYMV per iteration),
     # reported beside the timed path; not part of the timed steps
     if args.path == "gemv" and not args.no_syrk_compare:

@@ -113,7 +113,7 @@ typedef struct npga_options {
                             m_f = 2 gamma (Sec. 3.1 "Strongly convex specialization");
                             needs gamma > 0, else NPGA_ERR_INVALID                     */
   int32_t step_estimator; /* 0: Lanczos on L_eff L_eff^T, stopped when the largest Ritz
-                            value changes by < 1e-10 (default); 1: the power method of
+                            value changes by < 1e-8 (default); 1: the power method of
                             the paper's Remark.  Both approach ||L_eff||^2 from below;
                             step_safety covers the remainder                           */
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
@@ -228,7 +228,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  *   start (Sec. 3.1 Remark): method 1 = `iters` power-method steps (the last
  *   Rayleigh value ||L_eff^T u||^2); method 0 = Lanczos on L_eff L_eff^T, at
  *   most min(iters, 64) steps, stopped when the largest Ritz value changes
- *   by less than 1e-10 relative.  Both are lower bounds.  steps_out (host,
+ *   by less than 1e-8 relative.  Both are lower bounds.  steps_out (host,
  *   may be NULL) receives the sweeps used.
  *
  * npga_syrk - Sigma = L L^T (n x n float32, column-major, leading dim lds,

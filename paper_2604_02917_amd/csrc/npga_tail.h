@@ -180,38 +180,64 @@ __device__ void tail_power(const SolveArgs &a, double usq_total, double *redbuf)
 }
 
 
-// Largest eigenvalue of the m x m symmetric tridiagonal T (diagonal al,
-// off-diagonal be) by bisection on Sturm counts (one thread).
-__device__ inline double tridiag_max_eig(const double *al, const double *be, int m) {
-  double lo = 1e308, hi = -1e308;
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < m ? fabs(be[i]) : 0.0);
-    lo = fmin(lo, al[i] - r);
-    hi = fmax(hi, al[i] + r);
-  }
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    int cnt = 0;  // eigenvalues < mid
-    double q = al[0] - mid;
+// Number of eigenvalues below x of the m x m symmetric tridiagonal T
+// (diagonal al, off-diagonal be): negative pivots of T - x I = L D L^T.
+__device__ inline int sturm_count(const double *al, const double *be, int m, double x) {
+  int cnt = 0;
+  double q = al[0] - x;
+  cnt += q < 0.0;
+  for (int i = 1; i < m; ++i) {
+    const double qq = (fabs(q) < 1e-300) ? -1e-300 : q;
+    q = al[i] - x - be[i - 1] * be[i - 1] / qq;
     cnt += q < 0.0;
-    for (int i = 1; i < m; ++i) {
-      const double qq = (fabs(q) < 1e-300) ? -1e-300 : q;
-      q = al[i] - mid - be[i - 1] * be[i - 1] / qq;
-      cnt += q < 0.0;
-    }
-    if (cnt == m) hi = mid;  // all below mid: the largest is below
-    else lo = mid;
   }
-  return hi;
+  return cnt;
+}
+
+// Largest eigenvalue of T by multisection with the whole workgroup: each
+// round evaluates 256 Sturm counts across the bracket and keeps the cell
+// where the count reaches m (8 rounds shrink the Gershgorin bracket by
+// 257^8).  al, be in LDS; every thread returns the same value.
+__device__ inline double tridiag_max_eig_block(const double *al, const double *be, int m, double *sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    double lo = 1e308, hi = -1e308;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < m ? fabs(be[i]) : 0.0);
+      lo = fmin(lo, al[i] - r);
+      hi = fmax(hi, al[i] + r);
+    }
+    sh[0] = lo;
+    sh[1] = hi;
+  }
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const double lo = sh[0], hi = sh[1];
+    const double w = (hi - lo) / 257.0;
+    const double x = lo + w * (double)(tid + 1);
+    const bool above = sturm_count(al, be, m, x) == m;  // x exceeds the largest eigenvalue
+    const unsigned long long mask = __ballot(above);
+    if (lane == 0) sh[2 + wave] = mask ? (double)(wave * 64 + __ffsll((long long)mask) - 1) : 256.0;
+    __syncthreads();
+    if (tid == 0) {
+      const int t = (int)fmin(fmin(sh[2], sh[3]), fmin(sh[4], sh[5]));
+      const double nlo = (t == 0) ? lo : lo + w * (double)t;
+      const double nhi = (t == 256) ? hi : lo + w * (double)(t + 1);
+      sh[0] = nlo;
+      sh[1] = nhi;
+    }
+    __syncthreads();
+  }
+  return sh[1];
 }
 
 // One Lanczos step on A = L_eff L_eff^T (gbuf0 = A v from the sweep, v in
 // xbuf0, the previous basis vector in xbuf1).  The largest Ritz value of
 // T_m is a lower bound of ||L_eff||_2^2 that converges far faster than the
 // power method's Rayleigh quotient on a clustered top spectrum; the phase
-// ends when it stops changing (relative 1e-10) or the recurrence breaks
-// down, and rho2 receives it.
+// ends when it stops changing (relative 1e-8; the Ritz value converges
+// superlinearly, so its error is then far below the step safety margin) or
+// the recurrence breaks down, and rho2 receives it.
 template <int E>
 __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   DevState *st = a.st;
@@ -240,15 +266,20 @@ __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   }
   red.sum(acc2);
   const double be = sqrt(acc2[0]);
-  __shared__ double theta_sh;
+  __shared__ double tal[kLanczosMax], tbe[kLanczosMax], msh[8];
+  if (tid < j) {
+    tal[tid] = st->lz_alpha[tid];
+    tbe[tid] = st->lz_beta[tid];
+  }
   if (tid == 0) {
+    tal[j] = al;
+    tbe[j] = be;
     st->lz_alpha[j] = al;
     st->lz_beta[j] = be;
-    theta_sh = tridiag_max_eig(st->lz_alpha, st->lz_beta, j + 1);
   }
   __syncthreads();
-  const double theta = theta_sh;
-  const bool conv = (j > 0 && fabs(theta - st->lz_theta) <= 1e-10 * theta) || !(be > 1e-13 * theta) ||
+  const double theta = tridiag_max_eig_block(tal, tbe, j + 1, msh);
+  const bool conv = (j > 0 && fabs(theta - st->lz_theta) <= 1e-8 * theta) || !(be > 1e-13 * theta) ||
                     j + 1 >= kLanczosMax;
   if (!conv) {
     const double inv = 1.0 / be;
