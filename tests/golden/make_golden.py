@@ -145,7 +145,35 @@ def make_c5():
     print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
 
 
+def make_n8192():
+    """Largest supported n: n = 8192, T = 600, K = 5 (C2 distributions,
+    seed 712), ridge 1e-3 tr(L L^T)/n, r = 60th percentile of mu."""
+    from tests.gpu_util import spec_with
+    t0 = time.time()
+    spec = spec_with("c2", 8192, 600, seed=712)
+    spec = spec.__class__(**{**spec.__dict__, "K": 5})
+    Rt = gen.returns_TxN(spec)
+    mu, L = ofactor.build_factor(Rt.T)
+    gamma = 1e-3 * float(np.sum(L * L)) / spec.n
+    r = float(np.quantile(mu, 0.6))
+    Q = L @ L.T + gamma * np.eye(spec.n)
+    out = exact_mv(Q, mu, r, fista_tol=1e-10)
+    x = out["x"]
+    rep = qp.kkt_report(2 * Q, np.zeros(spec.n), mu, r, x, out["lam"], out["nu"])
+    assert qp.certificate_ok(rep, tol_stat=1e-9, tol_feas=1e-12, r_scale=np.abs(mu).max()), rep
+    doc = {"workload": "n8192", "n": spec.n, "T": spec.T, "K": 5, "seed": 712, "gamma": gamma, "r": r,
+           "panel_sha256": panel_digest(Rt), "objective": factor_objective(L, gamma, x),
+           "lambda": out["lam"], "nu": out["nu"], "support": int((x > 0).sum()), "kkt": rep,
+           "x": [float(v) for v in x]}
+    path = os.path.join(HERE, "n8192_solution.json")
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    print(f"wrote {path}: f*={doc['objective']:.6e} support={doc['support']} ({time.time() - t0:.1f}s)", flush=True)
+
+
 def make(name):
+    if name == "n8192":
+        return make_n8192()
     if name == "c5":
         return make_c5()
     if name == "c3":
