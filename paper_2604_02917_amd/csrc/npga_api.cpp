@@ -225,6 +225,10 @@ int estimate_step(const Carved &c, int path, int slots, const npga_options &o, h
   return npga::launch_set_alpha(c.st, o.step_safety, s);
 }
 
+// Events that only take timestamps skip the system-scope fence (a cache
+// writeback and invalidate) that a default event performs when recorded.
+hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
 int map_done(int done) {
   switch (done) {
     case npga::kConverged: return NPGA_OK;
@@ -377,10 +381,10 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   const int slots = lay.slots;
 
   hipEvent_t ev0, evs[2], ev_setup;
-  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(timing_event(&ev0));
   HIPCHK(hipEventCreate(&evs[0]));
   HIPCHK(hipEventCreate(&evs[1]));
-  HIPCHK(hipEventCreate(&ev_setup));
+  HIPCHK(timing_event(&ev_setup));
   struct EvGuard {
     hipEvent_t *e;
     int k;
@@ -389,10 +393,10 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     }
   };
   SweepTimer tm;
-  HIPCHK(hipEventCreate(&tm.a[0]));
-  HIPCHK(hipEventCreate(&tm.a[1]));
-  HIPCHK(hipEventCreate(&tm.b[0]));
-  HIPCHK(hipEventCreate(&tm.b[1]));
+  HIPCHK(timing_event(&tm.a[0]));
+  HIPCHK(timing_event(&tm.a[1]));
+  HIPCHK(timing_event(&tm.b[0]));
+  HIPCHK(timing_event(&tm.b[1]));
   hipEvent_t all[8] = {ev0, evs[0], evs[1], ev_setup, tm.a[0], tm.a[1], tm.b[0], tm.b[1]};
   EvGuard guard{all, 8};
 
@@ -1117,15 +1121,15 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   int32_t *dev_status = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + lay.off_status);
 
   hipEvent_t ev0, evs[2], ev_setup;
-  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(timing_event(&ev0));
   HIPCHK(hipEventCreate(&evs[0]));
   HIPCHK(hipEventCreate(&evs[1]));
-  HIPCHK(hipEventCreate(&ev_setup));
+  HIPCHK(timing_event(&ev_setup));
   SweepTimer tm;
-  HIPCHK(hipEventCreate(&tm.a[0]));
-  HIPCHK(hipEventCreate(&tm.a[1]));
-  HIPCHK(hipEventCreate(&tm.b[0]));
-  HIPCHK(hipEventCreate(&tm.b[1]));
+  HIPCHK(timing_event(&tm.a[0]));
+  HIPCHK(timing_event(&tm.a[1]));
+  HIPCHK(timing_event(&tm.b[0]));
+  HIPCHK(timing_event(&tm.b[1]));
   struct EvGuard {
     hipEvent_t e[8];
     ~EvGuard() {
@@ -1388,7 +1392,7 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
   cg.a.mode = npga::kTailAdj;
   cg.a.ga = nullptr;
   hipEvent_t evs[2], ev0;
-  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(timing_event(&ev0));
   HIPCHK(hipEventCreate(&evs[0]));
   HIPCHK(hipEventCreate(&evs[1]));
   struct EvGuard3 {

@@ -59,6 +59,7 @@ struct alignas(256) DevState {
   double residual;      // last stopping residual
   double stop_residual; // residual when the main test passed
   double usq;           // ||L_eff^T x^k||^2 from the last sweep (float64 sum)
+  double usq_sweep;     // the sweep's per-workgroup ||L^T x||^2 partials summed in a fixed order
   double objective;     // f(x^k) at the last test
   double rho2;          // power method: ||L_eff^T u||^2 (Rayleigh value)
   double mu_max, mu_absmax;

@@ -386,6 +386,14 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a) {
   if (st->done != kRunning) return;
   __shared__ double red[4][64];
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+  if (blockIdx.x == 0) {
+    // ||L^T x||^2 from the per-workgroup partials (one per sweep workgroup)
+    __shared__ double ubuf[8];
+    BlockReducer<1> red1{ubuf, 0};
+    double u[1] = {threadIdx.x < a.sweep_grid ? a.usq_part[threadIdx.x] : 0.0};
+    red1.sum(u);
+    if (threadIdx.x == 0) st->usq_sweep = u[0];
+  }
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
   const int G = a.sweep_grid;
   double s = 0.0;
@@ -423,15 +431,9 @@ __global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
   __shared__ double redbuf[64];
   __shared__ double mbuf[8];
   __shared__ int64_t ibuf[8];
-  double usq = -1.0;
-  if (!covariance && (a.mode == kTailNpga || a.mode == kTailPower || a.mode == kTailGrad)) {
-    BlockReducer<5> red5{redbuf, 0};
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int w = threadIdx.x; w < a.sweep_grid; w += 256) acc[0] += a.usq_part[w];
-    red5.sum(acc);
-    usq = acc[0];
-    __syncthreads();
-  }
+  // the factor path's ||L^T x||^2 was summed by the reduce launch
+  const double usq =
+      (!covariance && (a.mode == kTailNpga || a.mode == kTailPower || a.mode == kTailGrad)) ? st->usq_sweep : -1.0;
   if (a.mode == kTailNpga)
     tail_npga<E>(a, usq, redbuf);
   else if (a.mode == kTailCG)

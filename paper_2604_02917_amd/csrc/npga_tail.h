@@ -26,7 +26,9 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   const double alpha = st->alpha, r = st->r, tolphi = st->tolphi;
   BlockReducer<5> red{redbuf, 0};
 
-  double mu[E], xk[E], gk[E], v[E];
+  // every vector the iteration reads is loaded up front, so the loads of
+  // all five overlap
+  double mu[E], xk[E], gk[E], v[E], xp[E], gp[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + 256 * j;
@@ -34,6 +36,8 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     mu[j] = ok ? a.mu[i] : 0.0;
     xk[j] = ok ? xk_p[i] : 0.0;
     gk[j] = ok ? gk_p[i] : 0.0;
+    xp[j] = ok ? xn_p[i] : 0.0;
+    gp[j] = ok ? gp_p[i] : 0.0;
   }
 
   if (k % st->check_every == 0) {
@@ -79,15 +83,11 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     return;
   }
   const double beta = st->beta;
-  double xp[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    const bool ok = i < n;
-    xp[j] = ok ? xn_p[i] : 0.0;
-    const double gp = ok ? gp_p[i] : 0.0;
+    const bool ok = tid + 256 * j < n;
     const double y = fma(beta, xk[j] - xp[j], xk[j]);
-    const double gy = fma(beta, gk[j] - gp, gk[j]);
+    const double gy = fma(beta, gk[j] - gp[j], gk[j]);
     v[j] = ok ? fma(-alpha, gy, y) : -1.0e300;
   }
   const ProjResult pr = project_F<E>(v, mu, r, tolphi, st->nu, st->tau, red);
@@ -231,13 +231,45 @@ __device__ inline double tridiag_max_eig_block(const double *al, const double *b
   return sh[1];
 }
 
+// Last component of the unit eigenvector of the m x m tridiagonal T for its
+// largest eigenvalue theta (an upper bound from the multisection), by two
+// steps of inverse iteration with the shift theta (1 + 1e-12): T - shift I is
+// negative definite, so its LDL^T recurrence needs no pivoting.  beta_m times
+// this component is the residual norm ||A z - theta z|| of the Ritz pair.
+__device__ inline double ritz_last_component(const double *al, const double *be, int m, double theta,
+                                             double *w, double *y /* m scratch entries each */) {
+  if (m == 1) return 1.0;
+  const double shift = theta + 1e-12 * fabs(theta);
+  for (int i = 0; i < m; ++i) y[i] = 1.0;
+  double last = 1.0;
+  for (int it = 0; it < 2; ++it) {
+    // forward elimination (w: pivots), then back substitution, in place in y
+    w[0] = al[0] - shift;
+    for (int i = 1; i < m; ++i) {
+      const double l = be[i - 1] / w[i - 1];
+      w[i] = (al[i] - shift) - l * be[i - 1];
+      y[i] -= l * y[i - 1];
+    }
+    y[m - 1] /= w[m - 1];
+    for (int i = m - 2; i >= 0; --i) y[i] = (y[i] - be[i] * y[i + 1]) / w[i];
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm = fma(y[i], y[i], nrm);
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) return 1.0;  // no estimate: not converged
+    for (int i = 0; i < m; ++i) y[i] /= nrm;
+    last = y[m - 1];
+  }
+  return last;
+}
+
 // One Lanczos step on A = L_eff L_eff^T (gbuf0 = A v from the sweep, v in
 // xbuf0, the previous basis vector in xbuf1).  The largest Ritz value of
 // T_m is a lower bound of ||L_eff||_2^2 that converges far faster than the
-// power method's Rayleigh quotient on a clustered top spectrum; the phase
-// ends when it stops changing (relative 1e-8; the Ritz value converges
-// superlinearly, so its error is then far below the step safety margin) or
-// the recurrence breaks down, and rho2 receives it.
+// power method's Rayleigh quotient on a clustered top spectrum.  The phase
+// ends when the Ritz pair's residual beta_m |s_m| falls to 1e-4 theta (an
+// eigenvalue of A then lies within 1e-4 theta of theta, far inside the step
+// safety margin, and the Ritz value's own error is of the order of the
+// squared residual) or the recurrence breaks down; rho2 receives theta.
 template <int E>
 __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   DevState *st = a.st;
@@ -266,7 +298,7 @@ __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   }
   red.sum(acc2);
   const double be = sqrt(acc2[0]);
-  __shared__ double tal[kLanczosMax], tbe[kLanczosMax], msh[8];
+  __shared__ double tal[kLanczosMax], tbe[kLanczosMax], msh[8], lzw[kLanczosMax], lzy[kLanczosMax];
   if (tid < j) {
     tal[tid] = st->lz_alpha[tid];
     tbe[tid] = st->lz_beta[tid];
@@ -279,8 +311,10 @@ __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   }
   __syncthreads();
   const double theta = tridiag_max_eig_block(tal, tbe, j + 1, msh);
-  const bool conv = (j > 0 && fabs(theta - st->lz_theta) <= 1e-8 * theta) || !(be > 1e-13 * theta) ||
-                    j + 1 >= kLanczosMax;
+  if (tid == 0) msh[6] = (j > 0) ? be * fabs(ritz_last_component(tal, tbe, j + 1, theta, lzw, lzy)) : INFINITY;
+  __syncthreads();
+  const double ritz_res = msh[6];
+  const bool conv = ritz_res <= 1e-4 * theta || !(be > 1e-13 * theta) || j + 1 >= kLanczosMax;
   if (!conv) {
     const double inv = 1.0 / be;
 #pragma unroll
