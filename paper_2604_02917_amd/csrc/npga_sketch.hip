@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_frob_partial(const float *Y, int64_t ld
 // State (SketchState): A = G (k x k, lda k) is overwritten: the reflector
 // of step i is kept in A[i+1:, i] (leading 1 explicit), d and e receive T.
 //
-// Step i, one workgroup (k_tri_small):
+// Step i, one workgroup of 1024 threads (k_tri_small):
 //   w_{i-1} = p - (tau_{i-1}/2)(p^T v_{i-1}) v_{i-1}    (p = tau A v from the
 //            previous grid kernel), then column i of the trailing block gets
 //            the rank-2 update A <- A - v w^T - w v^T, d_i = A[i, i], and the
@@ -297,52 +297,100 @@ __global__ __launch_bounds__(256) void k_frob_partial(const float *Y, int64_t ld
 //   the pending update from step i-1 (rows > i), is written back, and
 //   p_c = tau_i (A[i+1:, c] . v_i).
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tri_small(SketchState s, int64_t i) {
-  __shared__ double buf[64];
-  BlockReducer<5> red{buf, 0};
+constexpr int kTriThreads = 1024;  // one-workgroup step: 16 wavefronts
+constexpr int kTriRows = 8;        // rows per thread (k <= 8192)
+
+// Sum over the 1024-thread workgroup; every thread gets the same bits (the
+// sixteen wave totals are added in wave order).  buf: 2 x 16 doubles.
+__device__ __forceinline__ double tri_block_sum(double v, double *buf, int &parity) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_f64(v);
+  double *b = buf + 16 * parity;
+  if (lane == 0) b[wave] = v;
+  __syncthreads();
+  double t = b[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) t += b[w];
+  parity ^= 1;
+  return t;
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tri_small(SketchState s, int64_t i) {
+  __shared__ double buf[32];
+  __shared__ double x0s, wis, vis;
+  int parity = 0;
   const int64_t k = s.k;
   double *A = s.A;
+  double *coli = A + i * k;
   const int tid = threadIdx.x;
-  // w_{i-1} over rows >= i
+  // thread t owns rows r_q = i + t + 1024 q of column i, held in registers
+  // through every phase of the step
+  double c[kTriRows], vp[kTriRows], wp[kTriRows];
+#pragma unroll
+  for (int q = 0; q < kTriRows; ++q) {
+    const int64_t r = i + tid + (int64_t)kTriThreads * q;
+    c[q] = (r < k) ? coli[r] : 0.0;
+  }
   if (i > 0) {
-    const double taup = s.tau[i - 1];
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int64_t r = i + tid; r < k; r += 256) acc[0] = fma(s.p[r], s.vcur[r], acc[0]);
-    red.sum(acc);
-    const double half = 0.5 * taup * acc[0];
-    for (int64_t r = i + tid; r < k; r += 256) {
-      const double w = s.p[r] - half * s.vcur[r];
-      s.wprev[r] = w;
-      s.vprev[r] = s.vcur[r];
+    // w_{i-1} = p - (tau_{i-1}/2)(p^T v_{i-1}) v_{i-1} over rows >= i
+    double pr[kTriRows], dot = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) {
+      const int64_t r = i + tid + (int64_t)kTriThreads * q;
+      pr[q] = (r < k) ? s.p[r] : 0.0;
+      vp[q] = (r < k) ? s.vcur[r] : 0.0;
+      dot = fma(pr[q], vp[q], dot);
+    }
+    const double half = 0.5 * s.tau[i - 1] * tri_block_sum(dot, buf, parity);
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) {
+      const int64_t r = i + tid + (int64_t)kTriThreads * q;
+      wp[q] = pr[q] - half * vp[q];
+      if (r < k) {
+        s.wprev[r] = wp[q];
+        s.vprev[r] = vp[q];
+      }
+    }
+    // rank-2 update of column i with the entries at row i (thread 0, q = 0)
+    if (tid == 0) {
+      wis = wp[0];
+      vis = vp[0];
     }
     __syncthreads();
-    // update column i (rows >= i) with the rank-2 term of step i-1
-    const double wi = s.wprev[i], vi = s.vprev[i];
-    for (int64_t r = i + tid; r < k; r += 256)
-      A[r + i * k] -= s.vprev[r] * wi + s.wprev[r] * vi;
-    __syncthreads();
+    const double wi = wis, vi = vis;
+#pragma unroll
+    for (int q = 0; q < kTriRows; ++q) {
+      const int64_t r = i + tid + (int64_t)kTriThreads * q;
+      c[q] -= vp[q] * wi + wp[q] * vi;
+      if (r < k) coli[r] = c[q];
+    }
   }
-  if (tid == 0) s.d[i] = A[i + i * k];
+  if (tid == 0) s.d[i] = c[0];
   if (i >= k - 1) return;
-  // reflector for x = A[i+1:, i]
-  const double x0 = A[(i + 1) + i * k];
-  double acc[5] = {0, 0, 0, 0, 0};
-  for (int64_t r = i + 2 + tid; r < k; r += 256) {
-    const double x = A[r + i * k];
-    acc[0] = fma(x, x, acc[0]);
+  // reflector of x = A[i+1:, i] (x_0 is row i+1: thread 1, q = 0)
+  if (tid == 1) x0s = c[0];
+  double xn = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTriRows; ++q) {
+    const int64_t r = i + tid + (int64_t)kTriThreads * q;
+    if (r >= i + 2 && r < k) xn = fma(c[q], c[q], xn);
   }
-  red.sum(acc);
-  const double xn2 = acc[0];
+  const double xn2 = tri_block_sum(xn, buf, parity);  // its barrier also publishes x0s
+  const double x0 = x0s;
   double tau = 0.0, beta = x0, scale = 0.0;
   if (xn2 > 0.0) {
     beta = -copysign(sqrt(x0 * x0 + xn2), x0);
     tau = (beta - x0) / beta;
     scale = 1.0 / (x0 - beta);
   }
-  for (int64_t r = i + 1 + tid; r < k; r += 256) {
-    const double v = (r == i + 1) ? 1.0 : ((tau != 0.0) ? A[r + i * k] * scale : 0.0);
-    s.vcur[r] = v;
-    A[r + i * k] = v;
+#pragma unroll
+  for (int q = 0; q < kTriRows; ++q) {
+    const int64_t r = i + tid + (int64_t)kTriThreads * q;
+    if (r >= i + 1 && r < k) {
+      const double v = (r == i + 1) ? 1.0 : ((tau != 0.0) ? c[q] * scale : 0.0);
+      s.vcur[r] = v;
+      coli[r] = v;
+    }
   }
   if (tid == 0) {
     s.e[i] = beta;
@@ -350,6 +398,9 @@ __global__ __launch_bounds__(256) void k_tri_small(SketchState s, int64_t i) {
   }
 }
 
+// One wavefront per trailing column; eight rows (512 entries) of the column
+// and of the three step vectors are loaded before they are used, so each
+// wavefront keeps eight loads in flight.
 __global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
   const int64_t k = s.k;
   double *A = s.A;
@@ -357,18 +408,43 @@ __global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
   const int64_t W = (int64_t)gridDim.x * 4;
   const double tau = s.tau[i];
   const bool upd = i > 0;
+  const double *vcur = s.vcur, *vprev = s.vprev, *wprev = s.wprev;
   for (int64_t c = i + 1 + (int64_t)blockIdx.x * 4 + wave; c < k; c += W) {
-    const double wc = upd ? s.wprev[c] : 0.0;
-    const double vc = upd ? s.vprev[c] : 0.0;
+    const double wc = upd ? wprev[c] : 0.0;
+    const double vc = upd ? vprev[c] : 0.0;
     double *col = A + c * k;
     double dot = 0.0;
-    for (int64_t r = i + 1 + lane; r < k; r += 64) {
+    int64_t r = i + 1 + lane;
+    for (; r + 7 * 64 < k; r += 8 * 64) {
+      double a[8], v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] = col[r + 64 * u];
+        v[u] = vcur[r + 64 * u];
+      }
+      if (upd) {
+        double pv[8], pw[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          pv[u] = vprev[r + 64 * u];
+          pw[u] = wprev[r + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] -= pv[u] * wc + pw[u] * vc;
+          col[r + 64 * u] = a[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dot = fma(a[u], v[u], dot);
+    }
+    for (; r < k; r += 64) {
       double a = col[r];
       if (upd) {
-        a -= s.vprev[r] * wc + s.wprev[r] * vc;
+        a -= vprev[r] * wc + wprev[r] * vc;
         col[r] = a;
       }
-      dot = fma(a, s.vcur[r], dot);
+      dot = fma(a, vcur[r], dot);
     }
     dot = wave_sum_f64(dot);
     if (lane == 0) s.p[c] = tau * dot;
@@ -624,7 +700,7 @@ int launch_frob(const float *Y, int64_t ldy, int64_t n, int64_t k, double *part,
 int launch_tridiag(const SketchState &s, hipStream_t st) {
   const int64_t k = s.k;
   for (int64_t i = 0; i < k; ++i) {
-    hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(256), 0, st, s, i);
+    hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(kTriThreads), 0, st, s, i);
     if (i + 1 < k) {
       const int64_t cols = k - i - 1;
       const int grid = (int)std::min<int64_t>(512, (cols + 3) / 4);
