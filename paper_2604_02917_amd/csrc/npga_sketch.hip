@@ -398,9 +398,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_small(SketchState s, int64_
   }
 }
 
-// One wavefront per trailing column; eight rows (512 entries) of the column
-// and of the three step vectors are loaded before they are used, so each
-// wavefront keeps eight loads in flight.
+// One wavefront per pair of trailing columns (c, c + W): eight rows (512
+// entries) of both columns and of the three step vectors are loaded before
+// they are used, so each wavefront keeps many loads in flight and reads the
+// step vectors once for two columns.
 __global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
   const int64_t k = s.k;
   double *A = s.A;
@@ -409,17 +410,21 @@ __global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
   const double tau = s.tau[i];
   const bool upd = i > 0;
   const double *vcur = s.vcur, *vprev = s.vprev, *wprev = s.wprev;
-  for (int64_t c = i + 1 + (int64_t)blockIdx.x * 4 + wave; c < k; c += W) {
-    const double wc = upd ? wprev[c] : 0.0;
-    const double vc = upd ? vprev[c] : 0.0;
+  for (int64_t c = i + 1 + (int64_t)blockIdx.x * 4 + wave; c < k; c += 2 * W) {
+    const int64_t c2 = c + W;
+    const bool two = c2 < k;  // uniform over the wavefront
+    const double wc = upd ? wprev[c] : 0.0, vc = upd ? vprev[c] : 0.0;
+    const double wc2 = (upd && two) ? wprev[c2] : 0.0, vc2 = (upd && two) ? vprev[c2] : 0.0;
     double *col = A + c * k;
-    double dot = 0.0;
+    double *col2 = A + (two ? c2 : c) * k;
+    double dot = 0.0, dot2 = 0.0;
     int64_t r = i + 1 + lane;
     for (; r + 7 * 64 < k; r += 8 * 64) {
-      double a[8], v[8];
+      double a[8], a2[8], v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         a[u] = col[r + 64 * u];
+        a2[u] = two ? col2[r + 64 * u] : 0.0;
         v[u] = vcur[r + 64 * u];
       }
       if (upd) {
@@ -433,28 +438,50 @@ __global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
         for (int u = 0; u < 8; ++u) {
           a[u] -= pv[u] * wc + pw[u] * vc;
           col[r + 64 * u] = a[u];
+          if (two) {
+            a2[u] -= pv[u] * wc2 + pw[u] * vc2;
+            col2[r + 64 * u] = a2[u];
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) dot = fma(a[u], v[u], dot);
+      for (int u = 0; u < 8; ++u) {
+        dot = fma(a[u], v[u], dot);
+        dot2 = fma(a2[u], v[u], dot2);
+      }
     }
     for (; r < k; r += 64) {
-      double a = col[r];
+      double a = col[r], a2 = two ? col2[r] : 0.0;
       if (upd) {
-        a -= vprev[r] * wc + wprev[r] * vc;
+        const double pv = vprev[r], pw = wprev[r];
+        a -= pv * wc + pw * vc;
         col[r] = a;
+        if (two) {
+          a2 -= pv * wc2 + pw * vc2;
+          col2[r] = a2;
+        }
       }
-      dot = fma(a, vcur[r], dot);
+      const double v = vcur[r];
+      dot = fma(a, v, dot);
+      dot2 = fma(a2, v, dot2);
     }
     dot = wave_sum_f64(dot);
-    if (lane == 0) s.p[c] = tau * dot;
+    dot2 = wave_sum_f64(dot2);
+    if (lane == 0) {
+      s.p[c] = tau * dot;
+      if (two) s.p[c2] = tau * dot2;
+    }
   }
 }
 
 // --------------------------------------------------------------------------
 // The ell largest eigenvalues of the symmetric tridiagonal T (d, e) by
-// bisection on Sturm counts (number of eigenvalues below x from the signs
-// of the LDL^T pivots).  One thread per eigenvalue.
+// multisection on Sturm counts (number of eigenvalues below x from the
+// signs of the LDL^T pivots).  One wavefront per eigenvalue: each round its
+// 64 lanes count at 64 interior points of the current interval and the cell
+// where the count passes the eigenvalue's index is kept, so a round shrinks
+// the interval 65-fold where bisection halves it.  Four eigenvalues per
+// workgroup share d and e^2 in LDS.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bisect(SketchState s, int64_t ell) {
   extern __shared__ double sm[];
@@ -488,30 +515,33 @@ __global__ __launch_bounds__(256) void k_bisect(SketchState s, int64_t ell) {
   const double pivmin = 1e-300 + 4.0 * 2.2250738585072014e-308 * tnorm;
   lo -= 2.2e-16 * tnorm + 1e-300;
   hi += 2.2e-16 * tnorm + 1e-300;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= ell) return;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wave;
+  if (j >= ell) return;  // whole wavefronts leave, after the last barrier
   const int64_t m = k - 1 - j;  // ascending index of the j-th largest
-  double a = lo, b = hi;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
-    // Sturm count: eigenvalues < mid
-    int64_t cnt = 0;
-    double q = dd[0] - mid;
+  double a = lo, b = hi;         // count(a) <= m < count(b)
+  for (int round = 0; round < 64; ++round) {
+    const double w = (b - a) / 65.0;
+    const double x = a + w * (double)(lane + 1);
+    int64_t cnt = 0;  // eigenvalues below x
+    double q = dd[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
     for (int64_t i = 1; i < k; ++i) {
-      q = dd[i] - mid - ee[i - 1] / q;
+      q = dd[i] - x - ee[i - 1] / q;
       if (fabs(q) < pivmin) q = -pivmin;
       if (q < 0.0) ++cnt;
     }
-    if (cnt > m)
-      b = mid;
-    else
-      a = mid;
+    // first lane whose point lies above the eigenvalue (64: none)
+    const unsigned long long above = __ballot(cnt > m);
+    const int l = above ? __ffsll((long long)above) - 1 : 64;
+    const double na = a + w * (double)l;
+    const double nb = (l == 64) ? b : a + w * (double)(l + 1);
+    if (!(na > a || nb < b)) break;  // the cells no longer split at this precision
+    a = na;
+    b = nb;
     if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
   }
-  s.lam[j] = 0.5 * (a + b);
+  if (lane == 0) s.lam[j] = 0.5 * (a + b);
 }
 
 // --------------------------------------------------------------------------
@@ -519,7 +549,10 @@ __global__ __launch_bounds__(256) void k_bisect(SketchState s, int64_t ell) {
 // of T - lambda I with partial pivoting (the LAPACK dgttrf/dgttrs scheme),
 // three solves from a hashed start vector, normalisation.  One thread per
 // eigenvalue; the factor arrays are interleaved across threads so each
-// step is a coalesced access.
+// step is a coalesced access.  The recurrences carry the entries they pass
+// from row to row in registers (the arrays are only written, or read ahead
+// of the chain), so a step costs its arithmetic rather than a memory round
+// trip; the U solve multiplies by reciprocal pivots kept by the factorisation.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t mixh(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -528,131 +561,276 @@ __device__ __forceinline__ uint64_t mixh(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+constexpr int kIB = 16;  // rows whose inputs are loaded ahead of the recurrence
+
 __global__ __launch_bounds__(64) void k_inverse_iter(SketchState s, int64_t ell, int64_t stride) {
+  const int64_t k = s.k;
+  const double *__restrict__ d = s.d;
+  const double *__restrict__ e = s.e;
+  // ||T||_inf bound (the same for every eigenvalue): the wavefront's lanes
+  // split the rows, then a wave maximum
+  double tnorm = 0.0;
+  for (int64_t i = threadIdx.x; i < k; i += 64)
+    tnorm = fmax(tnorm, fabs(d[i]) + ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < k) ? fabs(e[i]) : 0.0));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) tnorm = fmax(tnorm, __shfl_xor(tnorm, off, 64));
   const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (j >= ell) return;
-  const int64_t k = s.k;
   const double lam = s.lam[j];
-  double *fd = s.work;                 // diagonal of U
-  double *fu = s.work + stride * k;    // first superdiagonal
-  double *fu2 = s.work + 2 * stride * k;
-  double *fl = s.work + 3 * stride * k;  // multipliers
-  double *bv = s.work + 4 * stride * k;  // right-hand side / solution
-  uint8_t *piv = reinterpret_cast<uint8_t *>(s.work + 5 * stride * k);
+  double *__restrict__ frd = s.work;               // reciprocal of the U diagonal
+  double *__restrict__ fu = s.work + stride * k;   // first superdiagonal of U
+  double *__restrict__ fu2 = s.work + 2 * stride * k;
+  double *__restrict__ fl = s.work + 3 * stride * k;  // multipliers
+  double *__restrict__ bv = s.work + 4 * stride * k;  // right-hand side / solution
+  uint8_t *__restrict__ piv = reinterpret_cast<uint8_t *>(s.work + 5 * stride * k);
 #define IX(i) ((i) * stride + j)
-  double tnorm = 0.0;
-  for (int64_t i = 0; i < k; ++i) tnorm = fmax(tnorm, fabs(s.d[i]) + ((i > 0) ? fabs(s.e[i - 1]) : 0.0) +
-                                                          ((i + 1 < k) ? fabs(s.e[i]) : 0.0));
   const double tiny = 2.2e-16 * tnorm + 1e-300;
-  // factor
-  for (int64_t i = 0; i < k; ++i) {
-    fd[IX(i)] = s.d[i] - lam;
-    if (i + 1 < k) {
-      fu[IX(i)] = s.e[i];
-      fl[IX(i)] = s.e[i];
+  auto recip = [&](double u) {
+    if (fabs(u) < tiny) u = (u < 0.0) ? -tiny : tiny;
+    return 1.0 / u;
+  };
+  // factor T - lam I = P L U; dcur, ucur: row i of the partly eliminated
+  // matrix.  One step, without branches: the row interchange (when the
+  // subdiagonal entry is the larger pivot) is a selection.
+  double dcur = d[0] - lam;
+  double ucur = (k > 1) ? e[0] : 0.0;
+  auto fstep = [&](int64_t i, double dnext, double li, double unext) {
+    const bool np = fabs(dcur) >= fabs(li);
+    const double dv = (dcur != 0.0) ? dcur : tiny;
+    const double den = np ? dv : li;
+    const double f = (np ? li : dcur) / den;
+    frd[IX(i)] = recip(den);
+    fl[IX(i)] = f;
+    fu[IX(i)] = np ? ucur : dnext;
+    fu2[IX(i)] = np ? 0.0 : unext;
+    piv[IX(i)] = np ? 0 : 1;
+    const double dn = np ? fma(-f, ucur, dnext) : fma(-f, dnext, ucur);
+    ucur = np ? unext : -f * unext;
+    dcur = dn;
+  };
+  int64_t i0 = 0;
+  for (; i0 + kIB <= k - 1; i0 += kIB) {  // whole blocks: every row index below k - 1
+    double dn[kIB], li[kIB], un[kIB];
+#pragma unroll
+    for (int u = 0; u < kIB; ++u) {
+      const int64_t i = i0 + u;
+      dn[u] = d[i + 1] - lam;
+      li[u] = e[i];
+      un[u] = (i + 2 < k) ? e[min(i + 1, k - 2)] : 0.0;
     }
-    fu2[IX(i)] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kIB; ++u) fstep(i0 + u, dn[u], li[u], un[u]);
   }
-  for (int64_t i = 0; i + 1 < k; ++i) {
-    const double di = fd[IX(i)], li = fl[IX(i)];
-    if (fabs(di) >= fabs(li)) {
-      const double dd = (di != 0.0) ? di : tiny;
-      fd[IX(i)] = dd;
-      const double f = li / dd;
-      fl[IX(i)] = f;
-      fd[IX(i + 1)] -= f * fu[IX(i)];
-      piv[IX(i)] = 0;
-    } else {
-      const double f = di / li;
-      fd[IX(i)] = li;
-      fl[IX(i)] = f;
-      const double t = fu[IX(i)];
-      fu[IX(i)] = fd[IX(i + 1)];
-      fd[IX(i + 1)] = t - f * fd[IX(i + 1)];
-      if (i + 2 < k) {
-        fu2[IX(i)] = fu[IX(i + 1)];
-        fu[IX(i + 1)] = -f * fu[IX(i + 1)];
-      }
-      piv[IX(i)] = 1;
-    }
-  }
-  if (fd[IX(k - 1)] == 0.0) fd[IX(k - 1)] = tiny;
+  for (int64_t i = i0; i + 1 < k; ++i) fstep(i, d[i + 1] - lam, e[i], (i + 2 < k) ? e[i + 1] : 0.0);
+  frd[IX(k - 1)] = recip((dcur != 0.0) ? dcur : tiny);
   // start vector
+#pragma unroll 8
   for (int64_t i = 0; i < k; ++i) {
     const uint64_t h = mixh(0x5bd1e995ull * (uint64_t)(j + 1) + (uint64_t)i);
     bv[IX(i)] = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
   }
+  double scale = 1.0;  // the previous solve's normalisation, applied as rows are read
   for (int iter = 0; iter < 3; ++iter) {
-    // L solve with the row interchanges
-    for (int64_t i = 0; i + 1 < k; ++i) {
-      const double f = fl[IX(i)];
-      if (piv[IX(i)] == 0) {
-        bv[IX(i + 1)] -= f * bv[IX(i)];
-      } else {
-        const double t = bv[IX(i)];
-        bv[IX(i)] = bv[IX(i + 1)];
-        bv[IX(i + 1)] = t - f * bv[IX(i + 1)];
+    // L solve with the row interchanges; bcur is row i of the running vector
+    double bcur = bv[IX(0)] * scale;
+    auto lstep = [&](int64_t i, double f, double bn, uint8_t pv) {
+      const bool np = pv == 0;
+      bv[IX(i)] = np ? bcur : bn;
+      bcur = np ? fma(-f, bcur, bn) : fma(-f, bn, bcur);
+    };
+    int64_t i1 = 0;
+    for (; i1 + kIB <= k - 1; i1 += kIB) {
+      double f[kIB], bn[kIB];
+      uint8_t pv[kIB];
+#pragma unroll
+      for (int u = 0; u < kIB; ++u) {
+        const int64_t i = i1 + u;
+        f[u] = fl[IX(i)];
+        bn[u] = bv[IX(i + 1)] * scale;
+        pv[u] = piv[IX(i)];
       }
+#pragma unroll
+      for (int u = 0; u < kIB; ++u) lstep(i1 + u, f[u], bn[u], pv[u]);
     }
-    // U solve
-    double nrm = 0.0;
-    for (int64_t i = k - 1; i >= 0; --i) {
-      double v = bv[IX(i)];
-      if (i + 1 < k) v -= fu[IX(i)] * bv[IX(i + 1)];
-      if (i + 2 < k) v -= fu2[IX(i)] * bv[IX(i + 2)];
-      double dd = fd[IX(i)];
-      if (fabs(dd) < tiny) dd = (dd < 0.0) ? -tiny : tiny;
-      v /= dd;
+    for (int64_t i = i1; i + 1 < k; ++i) lstep(i, fl[IX(i)], bv[IX(i + 1)] * scale, piv[IX(i)]);
+    bv[IX(k - 1)] = bcur;
+    // U solve from the last row, carrying the two rows below
+    double b1 = 0.0, b2 = 0.0, nrm = 0.0;
+    auto ustep = [&](int64_t i, double bb, double u1, double u2, double rd) {
+      const double v = (bb - u1 * b1 - u2 * b2) * rd;
       bv[IX(i)] = v;
       nrm = fmax(nrm, fabs(v));
+      b2 = b1;
+      b1 = v;
+    };
+    // rows k-1 and k-2 have no second (and k-1 no first) superdiagonal entry
+    int64_t i2 = k - 1;
+    for (; i2 >= 0 && i2 + 2 >= k; --i2)
+      ustep(i2, bv[IX(i2)], (i2 + 1 < k) ? fu[IX(i2)] : 0.0, 0.0, frd[IX(i2)]);
+    for (; i2 + 1 >= kIB; i2 -= kIB) {  // whole blocks of rows i2, i2-1, ..., i2-kIB+1 >= 0
+      double bb[kIB], u1[kIB], u2[kIB], rd[kIB];
+#pragma unroll
+      for (int u = 0; u < kIB; ++u) {
+        const int64_t i = i2 - u;
+        bb[u] = bv[IX(i)];
+        u1[u] = fu[IX(i)];
+        u2[u] = fu2[IX(i)];
+        rd[u] = frd[IX(i)];
+      }
+#pragma unroll
+      for (int u = 0; u < kIB; ++u) ustep(i2 - u, bb[u], u1[u], u2[u], rd[u]);
     }
-    const double inv = (nrm > 0.0) ? 1.0 / nrm : 1.0;
-    for (int64_t i = 0; i < k; ++i) bv[IX(i)] *= inv;
+    for (; i2 >= 0; --i2) ustep(i2, bv[IX(i2)], fu[IX(i2)], fu2[IX(i2)], frd[IX(i2)]);
+    scale = (nrm > 0.0) ? 1.0 / nrm : 1.0;
   }
   double n2 = 0.0;
-  for (int64_t i = 0; i < k; ++i) n2 = fma(bv[IX(i)], bv[IX(i)], n2);
-  const double inv = 1.0 / sqrt(n2);
+#pragma unroll 8
+  for (int64_t i = 0; i < k; ++i) {
+    const double v = bv[IX(i)] * scale;
+    n2 = fma(v, v, n2);
+  }
+  const double inv = scale / sqrt(n2);
+#pragma unroll 8
   for (int64_t i = 0; i < k; ++i) s.Z[i + j * k] = bv[IX(i)] * inv;
 #undef IX
 }
 
 // --------------------------------------------------------------------------
-// V = Q Z with Q = H_0 H_1 ... H_{k-2}: every workgroup owns two columns
-// of Z (in LDS) and applies the reflectors from the last to the first.
-// Writes V in float32 (k x ell, leading dim k) for the final product.
+// V = Q Z with Q = H_0 H_1 ... H_{k-2}, the reflectors taken kWY at a time
+// in compact WY form (Schreiber-Van Loan; LAPACK dlarft, forward and
+// columnwise): H_{i0} ... H_{i0+nb-1} = I - V_b T_b V_b^T with T_b upper
+// triangular, T_b[j][j] = tau_j and T_b[0:j, j] = -tau_j T_b[0:j, 0:j]
+// (V_b[:, 0:j]^T v_j).  The blocks are applied from the last to the first,
+// Z <- Z - V_b (T_b (V_b^T Z)), which needs one workgroup reduction per
+// block instead of one per reflector.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_backtransform(SketchState s, int64_t ell, float *V32) {
-  extern __shared__ double zc[];  // 2 k doubles
-  __shared__ double buf[64];
-  BlockReducer<5> red{buf, 0};
+constexpr int kWY = 32;
+
+// Entry r of reflector i (stored below the diagonal of A with its leading 1).
+__device__ __forceinline__ double refl(const SketchState &s, int64_t i, int64_t r) {
+  return (r > i) ? s.A[r + i * s.k] : 0.0;
+}
+
+// T_b of every block (one workgroup per block): the Gram matrix of the
+// block's reflectors, accumulated over 32-row slices staged in LDS, then the
+// triangular recurrence.  Tall: kWY x kWY per block, column-major.
+__global__ __launch_bounds__(256) void k_wy_t(SketchState s, double *Tall) {
+  __shared__ double Vs[32][kWY + 1];
+  __shared__ double G[kWY][kWY + 1];
+  __shared__ double Ts[kWY][kWY + 1];
   const int64_t k = s.k;
-  const int64_t j0 = (int64_t)blockIdx.x * 2;
-  const int ncol = (j0 + 1 < ell) ? 2 : 1;
-  for (int64_t r = threadIdx.x; r < k; r += 256) {
-    zc[r] = s.Z[r + j0 * k];
-    zc[k + r] = (ncol == 2) ? s.Z[r + (j0 + 1) * k] : 0.0;
-  }
-  __syncthreads();
-  for (int64_t i = k - 2; i >= 0; --i) {
-    const double tau = s.tau[i];
-    if (tau == 0.0) continue;
-    const double *v = s.A + i * k;  // v[r], r > i
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int64_t r = i + 1 + threadIdx.x; r < k; r += 256) {
-      const double vr = v[r];
-      acc[0] = fma(vr, zc[r], acc[0]);
-      acc[1] = fma(vr, zc[k + r], acc[1]);
+  const int64_t i0 = (int64_t)blockIdx.x * kWY;
+  const int nb = (int)min((int64_t)kWY, k - 1 - i0);
+  const int tid = threadIdx.x;
+  double g[4] = {0.0, 0.0, 0.0, 0.0};  // entries e = tid + 256 m: (e % 32, e / 32)
+  for (int64_t r0 = i0 + 1; r0 < k; r0 += 32) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int rr = tid & 31, jj = (tid >> 5) + 8 * m;
+      const int64_t r = r0 + rr;
+      Vs[rr][jj] = (jj < nb && r < k) ? refl(s, i0 + jj, r) : 0.0;
     }
-    red.sum(acc);
-    const double s0 = tau * acc[0], s1 = tau * acc[1];
-    for (int64_t r = i + 1 + threadIdx.x; r < k; r += 256) {
-      const double vr = v[r];
-      zc[r] -= s0 * vr;
-      zc[k + r] -= s1 * vr;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = tid + 256 * m, p = e & 31, q = e >> 5;
+      double acc = g[m];
+#pragma unroll 8
+      for (int rr = 0; rr < 32; ++rr) acc = fma(Vs[rr][p], Vs[rr][q], acc);
+      g[m] = acc;
     }
     __syncthreads();
   }
-  for (int64_t r = threadIdx.x; r < k; r += 256) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int e = tid + 256 * m;
+    G[e & 31][e >> 5] = g[m];
+    Ts[e & 31][e >> 5] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double tj = s.tau[i0 + j];
+    if (tid < j) {
+      double acc = 0.0;
+      for (int m = tid; m < j; ++m) acc = fma(Ts[tid][m], G[m][j], acc);
+      Ts[tid][j] = -tj * acc;
+    }
+    if (tid == 0) Ts[j][j] = tj;
+    __syncthreads();
+  }
+  double *T = Tall + (int64_t)blockIdx.x * kWY * kWY;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int e = tid + 256 * m;
+    T[e] = Ts[e & 31][e >> 5];
+  }
+}
+
+// Every workgroup owns two columns of Z (in LDS) and applies the blocks.
+// Writes V in float32 (k x ell, leading dim k) for the final product.
+__global__ __launch_bounds__(256) void k_backtransform(SketchState s, int64_t ell, const double *Tall,
+                                                       float *V32) {
+  extern __shared__ double zc[];  // 2 k doubles
+  __shared__ double buf[2 * 4 * 2 * kWY];
+  __shared__ double Tb[kWY * kWY];
+  __shared__ double xs[2 * kWY], ys[2 * kWY];
+  BlockReducer<2 * kWY> red{buf, 0};
+  const int64_t k = s.k;
+  const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * 2;
+  const int ncol = (j0 + 1 < ell) ? 2 : 1;
+  for (int64_t r = tid; r < k; r += 256) {
+    zc[r] = s.Z[r + j0 * k];
+    zc[k + r] = (ncol == 2) ? s.Z[r + (j0 + 1) * k] : 0.0;
+  }
+  const int64_t nblk = (k - 1 + kWY - 1) / kWY;
+  for (int64_t b = nblk - 1; b >= 0; --b) {
+    const int64_t i0 = b * kWY;
+    const int nb = (int)min((int64_t)kWY, k - 1 - i0);
+    for (int e = tid; e < kWY * kWY; e += 256) Tb[e] = Tall[b * kWY * kWY + e];
+    __syncthreads();  // also orders the previous block's updates of zc
+    // x = V_b^T z for both columns
+    double x[2 * kWY];
+#pragma unroll
+    for (int q = 0; q < 2 * kWY; ++q) x[q] = 0.0;
+    for (int64_t r = i0 + 1 + tid; r < k; r += 256) {
+      const double z0 = zc[r], z1 = zc[k + r];
+#pragma unroll
+      for (int jj = 0; jj < kWY; ++jj) {
+        const double v = (jj < nb) ? refl(s, i0 + jj, r) : 0.0;
+        x[jj] = fma(v, z0, x[jj]);
+        x[kWY + jj] = fma(v, z1, x[kWY + jj]);
+      }
+    }
+    red.sum(x);
+    if (tid == 0) {
+#pragma unroll
+      for (int q = 0; q < 2 * kWY; ++q) xs[q] = x[q];
+    }
+    __syncthreads();
+    // y = T_b x (T_b upper triangular), one entry per thread
+    if (tid < 2 * kWY) {
+      const int c = tid / kWY, jrow = tid % kWY;
+      double acc = 0.0;
+      for (int l = jrow; l < kWY; ++l) acc = fma(Tb[jrow + l * kWY], xs[c * kWY + l], acc);
+      ys[tid] = acc;
+    }
+    __syncthreads();
+    // z <- z - V_b y
+    for (int64_t r = i0 + 1 + tid; r < k; r += 256) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < kWY; ++jj) {
+        const double v = (jj < nb) ? refl(s, i0 + jj, r) : 0.0;
+        d0 = fma(v, ys[jj], d0);
+        d1 = fma(v, ys[kWY + jj], d1);
+      }
+      zc[r] -= d0;
+      zc[k + r] -= d1;
+    }
+  }
+  __syncthreads();
+  for (int64_t r = tid; r < k; r += 256) {
     V32[r + j0 * k] = (float)zc[r];
     if (ncol == 2) V32[r + (j0 + 1) * k] = (float)zc[k + r];
   }
@@ -711,7 +889,7 @@ int launch_tridiag(const SketchState &s, hipStream_t st) {
 }
 
 int launch_bisect(const SketchState &s, int64_t ell, hipStream_t st) {
-  const int grid = (int)((ell + 255) / 256);
+  const int grid = (int)((ell + 3) / 4);
   const size_t lds = sizeof(double) * 2 * (size_t)s.k;
   hipLaunchKernelGGL(k_bisect, dim3(grid), dim3(256), lds, st, s, ell);
   return (int)hipGetLastError();
@@ -724,9 +902,13 @@ int launch_inverse_iter(const SketchState &s, int64_t ell, int64_t stride, hipSt
 }
 
 int launch_backtransform(const SketchState &s, int64_t ell, float *V32, hipStream_t st) {
+  // the T factors go to the inverse-iteration work area, free by now
+  double *Tall = s.work;
+  const int nblk = (int)((s.k - 1 + kWY - 1) / kWY);
+  if (nblk > 0) hipLaunchKernelGGL(k_wy_t, dim3(nblk), dim3(256), 0, st, s, Tall);
   const int grid = (int)((ell + 1) / 2);
   const size_t lds = sizeof(double) * 2 * (size_t)s.k;
-  hipLaunchKernelGGL(k_backtransform, dim3(grid), dim3(256), lds, st, s, ell, V32);
+  hipLaunchKernelGGL(k_backtransform, dim3(grid), dim3(256), lds, st, s, ell, (const double *)Tall, V32);
   return (int)hipGetLastError();
 }
 
