@@ -64,7 +64,16 @@ def sweep_traffic(path_used):
         return None
     m = re.search(r"template <int E, typename TL>\n__global__ __launch_bounds__\(256\) void k_sweep\(SolveArgs a\) "
                   r"\{.*?\n\}\n", src, re.S)
-    if not m or hashlib.sha256(m.group(0).encode()).hexdigest() != doc["source_sha256"]:
+    if not m:
+        return None
+    # the kernel's text and the device helpers it calls (wave sums, loads)
+    h = hashlib.sha256(m.group(0).encode())
+    for extra in doc.get("helper_files", []):
+        try:
+            h.update(open(os.path.join(ROOT, extra)).read().encode())
+        except OSError:
+            return None
+    if h.hexdigest() != doc["source_sha256"]:
         return None
     return doc["traffic_bytes_per_launch"]
 

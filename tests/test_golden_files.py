@@ -109,3 +109,33 @@ def test_c5_golden_consistent():
     mu = Rt.astype(np.float64).mean(axis=0)
     assert dmu.sum() == pytest.approx(-ref["dr"], rel=1e-8)
     assert mu @ dmu == pytest.approx(-ref["r"] * ref["dr"], rel=1e-6)
+
+
+GOLDEN_N8192 = os.path.join(os.path.dirname(__file__), "golden", "n8192_solution.json")
+
+
+def test_n8192_golden_consistent():
+    """Stored solution at the largest n (8192 assets, 600 periods, ridge):
+    it belongs to the regenerated panel, is feasible, and its KKT conditions
+    hold when recomputed here in factor form (gradient 2 L (L^T x) + 2 gamma x)."""
+    from tests.gpu_util import spec_with
+    with open(GOLDEN_N8192) as fh:
+        ref = json.load(fh)
+    spec = spec_with("c2", 8192, 600, seed=712)
+    spec = spec.__class__(**{**spec.__dict__, "K": 5})
+    Rt = gen.returns_TxN(spec)
+    assert panel_digest(Rt) == ref["panel_sha256"]
+    mu, L = ofactor.build_factor(Rt.T)
+    gamma, r = ref["gamma"], ref["r"]
+    assert gamma == pytest.approx(1e-3 * float(np.sum(L * L)) / 8192, rel=1e-12)
+    x = np.asarray(ref["x"])
+    assert x.min() >= 0 and abs(x.sum() - 1) <= 1e-12
+    assert mu @ x >= r - 1e-14
+    assert factor_objective(L, gamma, x) == pytest.approx(ref["objective"], rel=1e-12)
+    g = 2.0 * (L @ (L.T @ x)) + 2.0 * gamma * x
+    d = g - ref["lambda"] - ref["nu"] * mu  # reduced costs
+    S = x > 0
+    scale = np.abs(g).max()
+    assert np.abs(d[S]).max() <= 1e-9 * scale
+    assert d[~S].min() >= -1e-8 * scale
+    assert ref["nu"] >= 0 and ref["nu"] * (mu @ x - r) <= 1e-12 * scale
