@@ -34,17 +34,18 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
 // float32 MFMA GEMM  C (M x N, column-major, ldc) = A B
-//   A element (m, k): kAK == 0 -> A[m + k lda] (rows contiguous, e.g. L or Y)
-//                     kAK == 1 -> A[k + m lda] (k contiguous)
+//   A element (m, k): A[m + k lda] (rows contiguous, e.g. L or Y)
 //   B element (k, n): B[k + n ldb] (k contiguous, e.g. S or V)
-// 128 x 128 tiles, four wavefronts of 64 x 64 (2 x 2 v_mfma_f32_32x32x2_f32),
-// 32-deep k slices double buffered in LDS, float64 flush every 64 k.
+// 128 x 128 tiles, eight wavefronts of 32 x 64 (1 x 2 v_mfma_f32_32x32x2_f32
+// blocks; the small per-wavefront accumulator set leaves room for two
+// wavefronts per SIMD), 32-deep k slices double buffered in LDS, float64
+// flush every 64 k.
 // --------------------------------------------------------------------------
 constexpr int GT = 128;
 constexpr int GK = 32;
 constexpr int GPAD = 129;
 
-__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(512) void k_gemm_f32(const float *__restrict__ A, int64_t lda,
                                                   const float *__restrict__ B, int64_t ldb,
                                                   float *__restrict__ C, int64_t ldc, int64_t M,
                                                   int64_t N, int64_t K) {
@@ -55,26 +56,24 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, i
   const int64_t bn = blockIdx.x / nbm;
   const int64_t m0 = bm * GT, n0 = bn * GT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  v16f acc[2][2];
-  double acc64[2][2][16];
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32.., columns wc*64..
+  v16f acc[2];
+  double acc64[2][16];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[p][q][v] = 0.f;
-        acc64[p][q][v] = 0.0;
-      }
-  // A loader (rows contiguous): float4 index (tid % 32) of k-columns tid/32 + 8 q
-  // B loader (k contiguous): column tid/8 + 32 q, float4 index (tid % 8) along k
-  f4 ra[4], rb[4];
+    for (int v = 0; v < 16; ++v) {
+      acc[q][v] = 0.f;
+      acc64[q][v] = 0.0;
+    }
+  // A loader (rows contiguous): float4 index (tid % 32) of k-columns tid/32 + 16 q
+  // B loader (k contiguous): column tid/8 + 64 q, float4 index (tid % 8) along k
+  f4 ra[2], rb[2];
   const bool bvec = (ldb % 4) == 0 && (reinterpret_cast<uintptr_t>(B) % 16) == 0;
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t kk = k0 + (tid >> 5) + 8 * q;
+    for (int q = 0; q < 2; ++q) {
+      const int64_t kk = k0 + (tid >> 5) + 16 * q;
       const int64_t mm = m0 + 4 * (tid & 31);
       f4 z = f4{0.f, 0.f, 0.f, 0.f};
       if (kk < K && mm < M) {
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, i
         if (mm + 3 >= M) z.w = 0.f;
       }
       ra[q] = z;
-      const int64_t nn = n0 + (tid >> 3) + 32 * q;
+      const int64_t nn = n0 + (tid >> 3) + 64 * q;
       const int64_t kb = k0 + 4 * (tid & 7);
       f4 zb = f4{0.f, 0.f, 0.f, 0.f};
       if (nn < N) {
@@ -103,9 +102,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, i
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<f4 *>(&As[buf][(tid >> 5) + 8 * q][4 * (tid & 31)]) = ra[q];
-      const int c = (tid >> 3) + 32 * q;
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<f4 *>(&As[buf][(tid >> 5) + 16 * q][4 * (tid & 31)]) = ra[q];
+      const int c = (tid >> 3) + 64 * q;
       const int kb = 4 * (tid & 7);
       Bs[buf][kb + 0][c] = rb[q].x;
       Bs[buf][kb + 1][c] = rb[q].y;
@@ -123,41 +122,34 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, i
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 2) {
       const int kr = kk + (lane >> 5);
-      float av[2], bv[2];
-#pragma unroll
-      for (int p = 0; p < 2; ++p) av[p] = As[buf][kr][wr * 64 + p * 32 + (lane & 31)];
+      const float av = As[buf][kr][wr * 32 + (lane & 31)];
+      float bv[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) bv[q] = Bs[buf][kr][wc * 64 + q * 32 + (lane & 31)];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[p], bv[q], acc[p][q], 0, 0, 0);
+      for (int q = 0; q < 2; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[q], acc[q], 0, 0, 0);
     }
     if ((s & 1) == 1 || s + 1 == nst) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            acc64[p][q][v] += (double)acc[p][q][v];
-            acc[p][q][v] = 0.f;
-          }
+        for (int v = 0; v < 16; ++v) {
+          acc64[q][v] += (double)acc[q][v];
+          acc[q][v] = 0.f;
+        }
     }
     if (s + 1 < nst) sstore(buf ^ 1);
     __syncthreads();
   }
+  // MFMA 32x32 output layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + (v%4), column l%32
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = m0 + wr * 64 + p * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t c = n0 + wc * 64 + q * 32 + (lane & 31);
-        if (r < M && c < N) C[r + c * ldc] = (float)acc64[p][q][v];
-      }
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = m0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int64_t c = n0 + wc * 64 + q * 32 + (lane & 31);
+      if (r < M && c < N) C[r + c * ldc] = (float)acc64[q][v];
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -858,7 +850,7 @@ __global__ void k_finish_str(SketchState s, int64_t ell, int64_t n, double coef,
 int launch_gemm_f32(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
                     int64_t M, int64_t N, int64_t K, hipStream_t st) {
   const int64_t tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)tiles), dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
+  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)tiles), dim3(512), 0, st, A, lda, B, ldb, C, ldc, M, N, K);
   return (int)hipGetLastError();
 }
 

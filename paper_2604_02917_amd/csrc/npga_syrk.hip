@@ -2,8 +2,8 @@
 // per iteration).
 //
 // k_syrk: Sigma = L L^T with float32 MFMA (v_mfma_f32_32x32x2_f32).  One
-// workgroup computes a 128 x 128 tile of the lower triangle (four
-// wavefronts, 64 x 64 each as 2 x 2 MFMA blocks) and also writes the
+// workgroup computes a 128 x 128 tile of the lower triangle (eight
+// wavefronts, 32 x 64 each as 1 x 2 MFMA blocks) and also writes the
 // mirrored tile, so Sigma is stored full.  Columns of L (periods) are the
 // reduction dimension; 32-period slices of both row panels are staged in
 // LDS (double buffered).  The float32 MFMA accumulators are flushed into
@@ -29,7 +29,7 @@ constexpr int kTile = 128;
 constexpr int kKB = 32;          // periods per LDS stage
 constexpr int kFlushStages = 8;  // float32 -> float64 flush every 256 periods
 
-__global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64_t n, int64_t T, int64_t ld,
+__global__ __launch_bounds__(512) void k_syrk(const float *__restrict__ L, int64_t n, int64_t T, int64_t ld,
                                               float *__restrict__ S, int64_t lds, int nb) {
   __shared__ float As[2][kKB][kTile];
   __shared__ float Bs[2][kKB][kTile];
@@ -50,30 +50,27 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32.., columns wc*64..
 
-  v16f acc[2][2];
-  double acc64[2][2][16];
+  v16f acc[2];
+  double acc64[2][16];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[p][q][v] = 0.f;
-        acc64[p][q][v] = 0.0;
-      }
+    for (int v = 0; v < 16; ++v) {
+      acc[q][v] = 0.f;
+      acc64[q][v] = 0.0;
     }
 
   // global -> register staging: thread loads float4 index (tid % 32) of
-  // columns (tid / 32) + 8 q, q = 0..3, for both panels
+  // columns (tid / 32) + 16 q, q = 0..1, for both panels
   const int f4i = tid & 31;
   const int colq = tid >> 5;
-  f4 ra[4], rb[4];
+  f4 ra[2], rb[2];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t t = k0 + colq + 8 * q;
+    for (int q = 0; q < 2; ++q) {
+      const int64_t t = k0 + colq + 16 * q;
       const int64_t ra0 = row_a + 4 * f4i;
       const int64_t rb0 = row_b + 4 * f4i;
       f4 za = f4{0.f, 0.f, 0.f, 0.f}, zb = za;
@@ -97,9 +94,9 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<f4 *>(&As[buf][colq + 8 * q][4 * f4i]) = ra[q];
-      *reinterpret_cast<f4 *>(&Bs[buf][colq + 8 * q][4 * f4i]) = rb[q];
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<f4 *>(&As[buf][colq + 16 * q][4 * f4i]) = ra[q];
+      *reinterpret_cast<f4 *>(&Bs[buf][colq + 16 * q][4 * f4i]) = rb[q];
     }
   };
 
@@ -113,27 +110,21 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64
 #pragma unroll
     for (int kk = 0; kk < kKB; kk += 2) {
       const int kr = kk + (lane >> 5);
-      float av[2], bv[2];
-#pragma unroll
-      for (int p = 0; p < 2; ++p) av[p] = As[buf][kr][wr * 64 + p * 32 + (lane & 31)];
+      const float av = As[buf][kr][wr * 32 + (lane & 31)];
+      float bv[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) bv[q] = Bs[buf][kr][wc * 64 + q * 32 + (lane & 31)];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[p], bv[q], acc[p][q], 0, 0, 0);
+      for (int q = 0; q < 2; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[q], acc[q], 0, 0, 0);
     }
     if (((s + 1) % kFlushStages) == 0 || s + 1 == nstages) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            acc64[p][q][v] += (double)acc[p][q][v];
-            acc[p][q][v] = 0.f;
-          }
+        for (int v = 0; v < 16; ++v) {
+          acc64[q][v] += (double)acc[q][v];
+          acc[q][v] = 0.f;
+        }
     }
     if (s + 1 < nstages) {
       sstore(buf ^ 1);
@@ -144,19 +135,17 @@ __global__ __launch_bounds__(256) void k_syrk(const float *__restrict__ L, int64
   // write the tile and its mirror.  MFMA 32x32 output layout: lane l,
   // register v -> row 8 (v/4) + 4 (l/32) + (v%4), column l%32.
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = row_a + wr * 64 + p * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t c = row_b + wc * 64 + q * 32 + (lane & 31);
-        if (r < n && c < n) {
-          const float val = (float)acc64[p][q][v];
-          S[r + c * lds] = val;
-          if (bi != bj) S[c + r * lds] = val;
-        }
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = row_a + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int64_t c = row_b + wc * 64 + q * 32 + (lane & 31);
+      if (r < n && c < n) {
+        const float val = (float)acc64[q][v];
+        S[r + c * lds] = val;
+        if (bi != bj) S[c + r * lds] = val;
       }
+    }
 }
 
 // g = 2 Sigma x (+ 2 gamma x); the serial tail runs as a separate launch.
@@ -212,7 +201,7 @@ int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, 
   const int nb = (int)((n + kTile - 1) / kTile);
   const int ntiles = nb * (nb + 1) / 2;
   const int grid = ((ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_syrk, dim3(grid), dim3(256), 0, s, L, n, T, ld, Sigma, lds, nb);
+  hipLaunchKernelGGL(k_syrk, dim3(grid), dim3(512), 0, s, L, n, T, ld, Sigma, lds, nb);
   return (int)hipGetLastError();
 }
 
