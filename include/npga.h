@@ -112,10 +112,11 @@ typedef struct npga_options {
                             beta = (1 - sqrt(alpha m_f))/(1 + sqrt(alpha m_f)) with
                             m_f = 2 gamma (Sec. 3.1 "Strongly convex specialization");
                             needs gamma > 0, else NPGA_ERR_INVALID                     */
-  int32_t step_estimator; /* 0: Lanczos on L_eff L_eff^T, stopped when the largest Ritz
-                            value changes by < 1e-8 (default); 1: the power method of
-                            the paper's Remark.  Both approach ||L_eff||^2 from below;
-                            step_safety covers the remainder                           */
+  int32_t step_estimator; /* 0: Lanczos on L_eff L_eff^T (default), stopped when the
+                            Ritz residual beta_m |s_m| is below tol theta, tol =
+                            min(1e-2, max((step_safety - 1)/4, 1e-4)); 1: the power
+                            method of the paper's Remark.  Both approach ||L_eff||^2
+                            from below; step_safety covers the remainder              */
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
                             (see npga_batched_tune), or -1 for the built-in choice
                             from the shape; default -1                               */
@@ -184,8 +185,8 @@ int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb,
 
 /* ---------------------------------------------------------------------------
  * npga_solve - Algorithm 1 (NPGA, Sec. 3.1) with the fixed step
- * alpha = 1 / (step_safety * L_f_hat), L_f_hat from the power method on
- * L_eff (Sec. 3.1 Remark), FISTA momentum t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+ * alpha = 1 / (step_safety * L_f_hat), L_f_hat from Lanczos (or the power
+ * method) on L_eff (Sec. 3.1 Remark), FISTA momentum t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
  * beta_k = (t_k - 1)/t_{k+1}, and x^{k+1} = Pi_F(y^k - alpha grad f(y^k)).
  * Pi_F is computed exactly by the scalar dual search of eq. projF-dualpath
  * (Sec. 3.1).  The stopping rule is checked every check_every iterations.
@@ -227,8 +228,9 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  * npga_spectral_norm_sq - ||L_eff||_2^2 estimated from a seeded Gaussian
  *   start (Sec. 3.1 Remark): method 1 = `iters` power-method steps (the last
  *   Rayleigh value ||L_eff^T u||^2); method 0 = Lanczos on L_eff L_eff^T, at
- *   most min(iters, 64) steps, stopped when the largest Ritz value changes
- *   by less than 1e-8 relative.  Both are lower bounds.  steps_out (host,
+ *   most min(iters, 64) steps, stopped when the residual of the largest Ritz
+ *   pair is below 1e-4 of the Ritz value (an eigenvalue of L_eff L_eff^T
+ *   lies that close).  Both are lower bounds.  steps_out (host,
  *   may be NULL) receives the sweeps used.
  *
  * npga_syrk - Sigma = L L^T (n x n float32, column-major, leading dim lds,

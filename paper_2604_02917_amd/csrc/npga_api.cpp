@@ -206,16 +206,24 @@ int step(const Carved &c, int path, int slots, hipStream_t s) {
   return npga::launch_reduce_tail(c.a, slots, s);
 }
 
-// ||L_eff||_2^2 by Lanczos on L_eff L_eff^T (default: the largest Ritz value
-// stops changing after about a dozen sweeps on a factor spectrum) or by the
-// power method of the paper's Remark (power_iters sweeps); then alpha.
-int estimate_step(const Carved &c, int path, int slots, const npga_options &o, hipStream_t s) {
+// ||L_eff||_2^2 by Lanczos on L_eff L_eff^T (default) or by the power method
+// of the paper's Remark (power_iters sweeps); then alpha.  Lanczos stops at a
+// Ritz residual of lz_tol theta.  For the step size that need only be a
+// fraction of the safety margin: with alpha = 1/(step_safety 2 (theta +
+// gamma)), lambda_max <= (1 + lz_tol) theta keeps alpha <= 1/L_f whenever
+// lz_tol < step_safety - 1; a quarter of the margin, capped at 1e-2 (about
+// eight sweeps on a factor spectrum), leaves room for rounding.
+double step_lanczos_tol(const npga_options &o) {
+  return std::min(1e-2, std::max(0.25 * (o.step_safety - 1.0), 1e-4));
+}
+
+int estimate_step(const Carved &c, int path, int slots, const npga_options &o, hipStream_t s, double lz_tol) {
   if (npga::launch_random_unit(c.a.xbuf0, c.a.xs, c.a.n, o.seed, s)) return 1;
   Carved cp = c;
   int steps = o.power_iters;
   if (o.step_estimator == 0) {
     cp.a.mode = npga::kTailLanczos;
-    if (npga::launch_lanczos_init(cp.a, s)) return 1;
+    if (npga::launch_lanczos_init(cp.a, lz_tol, s)) return 1;
     steps = std::min(o.power_iters, npga::kLanczosMax);
   } else {
     cp.a.mode = npga::kTailPower;
@@ -417,7 +425,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     LAUNCHCHK(npga::launch_syrk(static_cast<const float *>(f->L), f->n, f->cols, f->ld, c.sigma, c.lds, stream));
 
   // step size alpha = 1/(safety L_f_hat) from ||L_eff||_2^2 (Sec. 3.1 Remark)
-  LAUNCHCHK(estimate_step(c, path, slots, o, stream));
+  LAUNCHCHK(estimate_step(c, path, slots, o, stream, step_lanczos_tol(o)));
 
   // x^0 = Pi_F(x_in or 1/n)
   LAUNCHCHK(npga::launch_set_vector(c.a.xbuf0, o.warm_start ? x : nullptr, nullptr, f->n,
@@ -602,7 +610,7 @@ int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, in
   Carved c = carve(f, lay, ws, NPGA_PATH_GEMV);
   pin[2] = initial_state(f, 0.0, o);
   HIPCHK(hipMemcpyAsync(c.st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
-  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, lay.slots, o, stream));
+  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, lay.slots, o, stream, 1e-4));
   HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   *out = pin[3].rho2;
@@ -1150,7 +1158,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
     if (r_targets[j] > mu_max) return NPGA_ERR_INFEASIBLE;
 
   // shared step size from ||L||_2^2 (Sec. 3.1 Remark)
-  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, slots, o, stream));
+  LAUNCHCHK(estimate_step(c, NPGA_PATH_GEMV, slots, o, stream, step_lanczos_tol(o)));
 
   // per-target states, x^0 = Pi_F(x_in or 1/n)
   for (int32_t j = 0; j < m; ++j) {

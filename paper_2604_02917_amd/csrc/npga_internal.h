@@ -88,6 +88,7 @@ struct alignas(256) DevState {
   // Lanczos tridiagonal T_m of L_eff L_eff^T (step-size estimate)
   int32_t lz_m;
   double lz_theta;                 // largest Ritz value of T_m
+  double lz_tol;                   // stop when the Ritz residual is below lz_tol theta
   double lz_alpha[kLanczosMax];
   double lz_beta[kLanczosMax];
   // adjoint results
@@ -213,7 +214,7 @@ int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
 int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);  // also beta_const
-int launch_lanczos_init(const SolveArgs &a, hipStream_t s);
+int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s);
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.
 int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,

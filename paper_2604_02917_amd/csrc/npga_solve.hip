@@ -631,16 +631,17 @@ int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s) {
 }
 
 // Lanczos start: v_0 = xbuf0 (the random unit vector), v_{-1} = 0.
-__global__ __launch_bounds__(256) void k_lanczos_init(SolveArgs a) {
+__global__ __launch_bounds__(256) void k_lanczos_init(SolveArgs a, double tol) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) a.xbuf1[i] = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.st->lz_m = 0;
     a.st->lz_theta = 0.0;
+    a.st->lz_tol = tol;
   }
 }
 
-int launch_lanczos_init(const SolveArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_init, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_init, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, tol);
   return (int)hipGetLastError();
 }
 

@@ -266,10 +266,10 @@ __device__ inline double ritz_last_component(const double *al, const double *be,
 // xbuf0, the previous basis vector in xbuf1).  The largest Ritz value of
 // T_m is a lower bound of ||L_eff||_2^2 that converges far faster than the
 // power method's Rayleigh quotient on a clustered top spectrum.  The phase
-// ends when the Ritz pair's residual beta_m |s_m| falls to 1e-4 theta (an
-// eigenvalue of A then lies within 1e-4 theta of theta, far inside the step
-// safety margin, and the Ritz value's own error is of the order of the
-// squared residual) or the recurrence breaks down; rho2 receives theta.
+// ends when the Ritz pair's residual beta_m |s_m| falls to lz_tol theta (an
+// eigenvalue of A then lies within lz_tol theta of theta, and the Ritz
+// value's own error is of the order of the squared residual) or the
+// recurrence breaks down; rho2 receives theta.
 template <int E>
 __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   DevState *st = a.st;
@@ -314,7 +314,7 @@ __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
   if (tid == 0) msh[6] = (j > 0) ? be * fabs(ritz_last_component(tal, tbe, j + 1, theta, lzw, lzy)) : INFINITY;
   __syncthreads();
   const double ritz_res = msh[6];
-  const bool conv = ritz_res <= 1e-4 * theta || !(be > 1e-13 * theta) || j + 1 >= kLanczosMax;
+  const bool conv = ritz_res <= st->lz_tol * theta || !(be > 1e-13 * theta) || j + 1 >= kLanczosMax;
   if (!conv) {
     const double inv = 1.0 / be;
 #pragma unroll
