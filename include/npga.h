@@ -120,6 +120,11 @@ typedef struct npga_options {
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
                             (see npga_batched_tune), or -1 for the built-in choice
                             from the shape; default -1                               */
+  double alpha;          /* > 0: the fixed step of Algorithm 1, given by the caller
+                            (Algorithm 1 takes alpha as an input; convergence needs
+                            alpha <= 1/L_f); no step estimate is made.  0 (default):
+                            alpha = 1/(step_safety L_f_hat) from the estimate.  Any
+                            other value: NPGA_ERR_INVALID                            */
 } npga_options;
 
 /* Result of a solve (host). */
@@ -154,6 +159,11 @@ void npga_default_options(npga_options *opt);
 
 /* Text for a status code (static storage). */
 const char *npga_status_string(int status);
+
+/* sizeof of this header's structures, for bindings that lay them out themselves:
+ * which = 0 npga_options, 1 npga_result, 2 npga_factor, 3 npga_str_options,
+ * 4 npga_backward_result; 0 for any other value.  Host only.               */
+size_t npga_struct_size(int32_t which);
 
 /* ---------------------------------------------------------------------------
  * npga_build_factor - sample mean and centred covariance factor (Sec. 2.1):

@@ -19,6 +19,6 @@ Modules
   philox      Philox4x32-10 counter RNG + Box-Muller        (Salmon et al., SC'11)
 
 Parity status: every function is pinned by a CPU test against a closed
-form, brute force or an invariant, except the NPGA iterate trajectory,
-which is "parity unpinned" (only its limit is pinned).
+form, brute force or an invariant; the NPGA iterate trajectory by a scalar
+FISTA on the two-asset segment (projection = clamp).
 """

@@ -14,8 +14,9 @@ Stop when ||Pi_F(x^k - alpha grad f(x^k)) - x^k||_2 <= eps (Sec. 3.1
 benchmarks of Sec. 5.1.  Fixed step 0 < alpha <= 1/L_f with
 L_f = 2 ||L_eff||_2^2 + 2 gamma (Sec. 3.1 "Fixed step").
 
-Parity unpinned: the iterate trajectory.  Only its limit (the exact QP
-minimiser, pinned in ``qp``) and the qualitative rates are checked.
+Pins: the limit (the exact QP minimiser, pinned in ``qp``), the rates, and
+the trajectory itself against a scalar FISTA on the two-asset segment, where
+the projection is a clamp (tests/test_oracle_factor_npga.py).
 """
 import numpy as np
 

@@ -44,7 +44,7 @@ class _Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
                 ("momentum", ctypes.c_int32), ("step_estimator", ctypes.c_int32),
-                ("batch_config", ctypes.c_int32)]
+                ("batch_config", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 class _StrOptions(ctypes.Structure):
@@ -87,6 +87,7 @@ def _load():
     sig = {
         "npga_default_options": (None, [ctypes.POINTER(_Options)]),
         "npga_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "npga_struct_size": (sz, [i32]),
         "npga_solve_workspace_size": (sz, [i64, i64, ctypes.POINTER(_Options)]),
         "npga_solve": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, ctypes.POINTER(_Options), vp,
                                       ctypes.POINTER(_Result), vp, sz, vp]),
@@ -151,6 +152,7 @@ class Options:
     batch_config: int = -1
     momentum: str = "fista"   # "fista" (Algorithm 1) or "constant" (strongly convex, gamma > 0)
     step_estimator: str = "lanczos"   # or "power" (the paper's Remark)
+    alpha: float = 0.0   # > 0: the caller's fixed step (no estimate)
 
     def _c(self):
         o = _Options()
@@ -163,6 +165,7 @@ class Options:
         o.batch_config = self.batch_config
         o.momentum = {"fista": 0, "constant": 1}[self.momentum]
         o.step_estimator = {"lanczos": 0, "power": 1}[self.step_estimator]
+        o.alpha = self.alpha
         return o
 
 

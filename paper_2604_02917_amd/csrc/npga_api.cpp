@@ -121,7 +121,7 @@ bool options_valid(const npga_options &o) {
          (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
          is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0 && o.batch_config >= -1 &&
          o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1) &&
-         (o.step_estimator == 0 || o.step_estimator == 1);
+         (o.step_estimator == 0 || o.step_estimator == 1) && is_fin(o.alpha) && o.alpha >= 0.0;
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -218,6 +218,7 @@ double step_lanczos_tol(const npga_options &o) {
 }
 
 int estimate_step(const Carved &c, int path, int slots, const npga_options &o, hipStream_t s, double lz_tol) {
+  if (o.alpha > 0.0) return npga::launch_set_alpha(c.st, o.step_safety, s, o.alpha);  // given by the caller
   if (npga::launch_random_unit(c.a.xbuf0, c.a.xs, c.a.n, o.seed, s)) return 1;
   Carved cp = c;
   int steps = o.power_iters;
@@ -345,6 +346,18 @@ void npga_default_options(npga_options *o) {
   o->batch_config = -1;
   o->momentum = 0;
   o->step_estimator = 0;
+  o->alpha = 0.0;
+}
+
+size_t npga_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return sizeof(npga_options);
+    case 1: return sizeof(npga_result);
+    case 2: return sizeof(npga_factor);
+    case 3: return sizeof(npga_str_options);
+    case 4: return sizeof(npga_backward_result);
+    default: return 0;
+  }
 }
 
 const char *npga_status_string(int status) {
@@ -518,7 +531,7 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     res->return_active = fin.nu_c > 0.0 ? 1 : 0;
     res->refined = refined;
     res->path_used = path;
-    res->step_sweeps = o.step_estimator == 0 ? after_main.lz_m : o.power_iters;
+    res->step_sweeps = o.alpha > 0.0 ? 0 : (o.step_estimator == 0 ? after_main.lz_m : o.power_iters);
     res->residual = after_main.stop_residual;
     res->final_residual = fin.residual;
     res->objective = fin.objective;
@@ -1247,7 +1260,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
     rj.return_active = fin.nu_c > 0.0 ? 1 : 0;
     rj.refined = refined[j];
     rj.path_used = NPGA_PATH_GEMV;
-    rj.step_sweeps = o.step_estimator == 0 ? after_main[j].lz_m : o.power_iters;
+    rj.step_sweeps = o.alpha > 0.0 ? 0 : (o.step_estimator == 0 ? after_main[j].lz_m : o.power_iters);
     rj.residual = am.stop_residual;
     rj.final_residual = fin.residual;
     rj.objective = fin.objective;

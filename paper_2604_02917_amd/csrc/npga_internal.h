@@ -213,7 +213,7 @@ int launch_finalize(const SolveArgs &a, float *x_out, int slots, hipStream_t s);
 int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter, int32_t restart,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
-int launch_set_alpha(DevState *st, double step_safety, hipStream_t s);  // also beta_const
+int launch_set_alpha(DevState *st, double step_safety, hipStream_t s, double alpha_fixed = 0.0);  // also beta_const
 int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s);
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.

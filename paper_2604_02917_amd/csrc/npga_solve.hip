@@ -131,12 +131,19 @@ __global__ void k_set_tolphi(DevState *st, double proj_tol) {
 }
 
 // alpha = 1 / (safety * L_f_hat), L_f_hat = 2 (rho^2 + gamma) (Sec. 3.1 "Fixed step").
-__global__ void k_set_alpha(DevState *st, double safety) {
+// alpha = 1/(safety L_f_hat) with L_f_hat = 2 (rho2 + gamma), or the caller's
+// alpha_fixed > 0 (L_f_hat then reports 1/alpha_fixed).
+__global__ void k_set_alpha(DevState *st, double safety, double alpha_fixed) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (st->done == kConverged) st->done = kRunning;  // end of a Lanczos estimate
-    const double lf = 2.0 * (st->rho2 + st->gamma);
-    st->lipschitz = lf;
-    st->alpha = (lf > 0.0) ? 1.0 / (safety * lf) : 1.0;
+    if (alpha_fixed > 0.0) {
+      st->alpha = alpha_fixed;
+      st->lipschitz = 1.0 / alpha_fixed;
+    } else {
+      const double lf = 2.0 * (st->rho2 + st->gamma);
+      st->lipschitz = lf;
+      st->alpha = (lf > 0.0) ? 1.0 / (safety * lf) : 1.0;
+    }
     // strongly convex specialization: m_f = 2 gamma
     const double q = sqrt(st->alpha * 2.0 * st->gamma);
     st->beta_const = (1.0 - q) / (1.0 + q);
@@ -645,8 +652,8 @@ int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-int launch_set_alpha(DevState *st, double step_safety, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_alpha, dim3(1), dim3(64), 0, s, st, step_safety);
+int launch_set_alpha(DevState *st, double step_safety, hipStream_t s, double alpha_fixed) {
+  hipLaunchKernelGGL(k_set_alpha, dim3(1), dim3(64), 0, s, st, step_safety, alpha_fixed);
   return (int)hipGetLastError();
 }
 

@@ -137,3 +137,48 @@ def test_constant_momentum_linear_rate():
     out = npga(model, mu, r, alpha, x0, tol=1e-12, check_every=5, max_iter=20000, beta_const=beta)
     assert out["converged"]
     np.testing.assert_allclose(out["x"], ref["x"], atol=1e-9)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_npga_trajectory_two_assets(case):
+    """Pins the iterate trajectory of Algorithm 1 (not only its limit): with
+    two assets F is the segment {(s, 1 - s) : s_min <= s <= s_max}, the
+    projection is the clamp of s = (v_1 - v_2 + 1)/2, and the momentum point
+    y stays on the same line.  A scalar FISTA written on s must reproduce
+    every iterate of the oracle (a wrong momentum index, a gradient taken at
+    x instead of y, or a missing projection would not)."""
+    rng = np.random.default_rng(40 + case)
+    B = rng.standard_normal((2, 2))
+    Q = B @ B.T + 0.05 * np.eye(2)
+    mu = rng.normal(5e-4, 3e-4, size=2)
+    lo_mu, hi_mu = mu.min(), mu.max()
+    r = lo_mu + (0.3 + 0.5 * rng.random()) * (hi_mu - lo_mu) if case % 2 else lo_mu - 1e-4  # active / inactive
+    # feasible s range for x = (s, 1 - s): mu_2 + s (mu_1 - mu_2) >= r
+    d = mu[0] - mu[1]
+    if d > 0:
+        s_min, s_max = max(0.0, (r - mu[1]) / d), 1.0
+    else:
+        s_min, s_max = 0.0, min(1.0, (r - mu[1]) / d) if d < 0 else 1.0
+    alpha = 1.0 / (2.0 * np.linalg.eigvalsh(Q)[-1]) * (0.5 + 0.5 * rng.random())
+    x0 = rng.random(2)
+    K = 25
+    out = npga.npga(npga.CovarianceModel(Q), mu, r, alpha, x0, tol=0.0, check_every=1, max_iter=0)
+    traj = [out["x"]]
+    for k in range(1, K + 1):
+        traj.append(npga.npga(npga.CovarianceModel(Q), mu, r, alpha, x0, tol=0.0, check_every=1,
+                              max_iter=k)["x"])
+    # scalar FISTA on s
+    clamp = lambda s: min(max(s, s_min), s_max)
+    s = clamp((x0[0] - x0[1] + 1.0) / 2.0)
+    s_prev, t, beta = s, 1.0, 0.0
+    assert abs(traj[0][0] - s) <= 1e-14 and abs(traj[0][1] - (1 - s)) <= 1e-14
+    for k in range(1, K + 1):
+        ys = s + beta * (s - s_prev)
+        y = np.array([ys, 1.0 - ys])
+        v = y - alpha * (2.0 * Q @ y)
+        s_new = clamp((v[0] - v[1] + 1.0) / 2.0)
+        t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        beta = (t - 1.0) / t_new
+        t = t_new
+        s_prev, s = s, s_new
+        assert abs(traj[k][0] - s) <= 1e-13 and abs(traj[k][1] - (1.0 - s)) <= 1e-13, (k, traj[k], s)
