@@ -84,3 +84,27 @@ def test_fixed_step_solve_reaches_the_minimiser(npga):
     x, info = npga.solve(Ld, mud, r, alpha=alpha)
     assert info["status"] == 0 and info["step_sweeps"] == 0 and info["alpha"] == alpha
     assert np.abs(x.cpu().numpy().astype(np.float64) - ref["x"]).max() <= 1e-5
+
+
+def test_full_model_trajectory(npga):
+    """At the full model (n = 5440, T = 48374; the benchmark's launch
+    configuration), the first ten iterates against the oracle's.  The step
+    1/(2 ||L||_F^2) (||L||_F^2 >= ||L||_2^2, so alpha <= 1/L_f) needs no
+    eigen-solve on the host."""
+    spec = gen.SPECS["c2"]
+    Rt = gen.returns_TxN(spec)
+    r = gen.target_return(spec, Rt)
+    mu, L = ofactor.build_factor(Rt.T)
+    alpha = 1.0 / (2.0 * float(np.sum(L * L)))
+    model = onpga.FactorModel(L)
+    n = L.shape[0]
+    banner("full-model trajectory: device factor")
+    Ld, mud = npga.build_factor(to_dev(Rt))
+    del Rt
+    for k in (1, 4, 10):
+        ref = onpga.npga(model, mu, r, alpha, np.full(n, 1.0 / n), tol=0.0, check_every=5, max_iter=k)
+        x, info = npga.solve(Ld, mud, r, alpha=alpha, max_iter=k, refine=False, tol=1e-300)
+        assert info["status"] == 3 and info["iters"] == k
+        err = float(np.abs(x.cpu().numpy().astype(np.float64) - ref["x"]).max())
+        banner(f"full-model trajectory k={k}: max |x_gpu^k - x_oracle^k| = {err:.2e}")
+        assert err <= 1e-7, (k, err)
