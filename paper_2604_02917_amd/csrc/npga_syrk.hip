@@ -149,6 +149,9 @@ __global__ __launch_bounds__(512) void k_syrk(const float *__restrict__ L, int64
 }
 
 // g = 2 Sigma x (+ 2 gamma x); the serial tail runs as a separate launch.
+// A wavefront per column, the next column's loads in flight while the
+// current one is reduced (Sigma, 118 MB at n = 5440, stays in the MALL
+// between iterations, so the loads are ordinary cached ones).
 template <int E>
 __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restrict__ S, int64_t lds) {
   DevState *st = a.st;
@@ -165,24 +168,28 @@ __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restri
   const double *xk = cur ? a.xbuf1 : a.xbuf0;
   double *gk = (a.mode == kTailNpga) ? (cur ? a.gbuf1 : a.gbuf0) : a.gbuf0;
   const double *pv = a.pvec;
-  for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < n; col += W) {
+  auto load = [&](f4(&c)[E], int64_t col) {
     const f4 *p = reinterpret_cast<const f4 *>(S + col * lds) + lane;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t row0 = 4 * lane + 256 * j;
+      c[j] = (row0 < n) ? p[64 * j] : f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto process = [&](f4(&c)[E], int64_t col) {
     float d = 0.f;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int64_t row0 = 4 * lane + 256 * j;
-      if (row0 < n) {
-        f4 c = p[64 * j];
-        if (ragged) {
-          if (row0 + 1 >= n) c.y = 0.f;
-          if (row0 + 2 >= n) c.z = 0.f;
-          if (row0 + 3 >= n) c.w = 0.f;
-        }
-        d = fmaf(c.x, xr[j].x, d);
-        d = fmaf(c.y, xr[j].y, d);
-        d = fmaf(c.z, xr[j].z, d);
-        d = fmaf(c.w, xr[j].w, d);
+      if (ragged) {
+        if (row0 + 1 >= n) c[j].y = 0.f;
+        if (row0 + 2 >= n) c[j].z = 0.f;
+        if (row0 + 3 >= n) c[j].w = 0.f;
       }
+      d = fmaf(c[j].x, xr[j].x, d);
+      d = fmaf(c[j].y, xr[j].y, d);
+      d = fmaf(c[j].z, xr[j].z, d);
+      d = fmaf(c[j].w, xr[j].w, d);
     }
     d = wave_sum_f32(d);
     if (lane == 0) {
@@ -193,6 +200,19 @@ __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restri
       else
         gk[col] = 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col];
     }
+  };
+  f4 c0[E], c1[E];
+  int64_t col = (int64_t)blockIdx.x * 4 + wave;
+  if (col < n) load(c0, col);
+  while (col < n) {
+    const int64_t col1 = col + W;
+    if (col1 < n) load(c1, col1);
+    process(c0, col);
+    if (col1 >= n) break;
+    const int64_t col2 = col1 + W;
+    if (col2 < n) load(c0, col2);
+    process(c1, col1);
+    col = col2;
   }
 }
 
