@@ -1,6 +1,6 @@
 """MI355X (gfx950) NPGA mean-variance solver: Python binding of libnpga.
 
-The HIP library ``libnpga.so`` (built in-tree by ``paper_2604_02917_amd.build``)
+The HIP library ``libnpga.so`` (built in-tree by ``paper_2604_02917_amd/build.py``)
 does all the work; this package only marshals torch tensors and the current
 HIP stream into the C ABI declared in ``include/npga.h``.  Importing the
 package loads the library and raises if it is missing: there is no fallback.

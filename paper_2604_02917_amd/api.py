@@ -79,7 +79,7 @@ class _Result(ctypes.Structure):
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(
-            f"{_LIB_PATH} is missing: build it with `python -m paper_2604_02917_amd.build` "
+            f"{_LIB_PATH} is missing: build it with `python paper_2604_02917_amd/build.py` "
             "(there is no non-HIP fallback)")
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
@@ -95,6 +95,8 @@ def _load():
         "npga_gradient": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp, sz, vp]),
         "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, i32, vp, vp, vp, sz, vp]),
         "npga_syrk": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
+        "npga_syrk_split_workspace_size": (sz, [i64, i64]),
+        "npga_syrk_split": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
         "npga_to_bf16": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
         "npga_build_factor_workspace_size": (sz, [i64, i64]),
         "npga_build_factor": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp, vp, sz, vp]),
@@ -486,10 +488,20 @@ def to_bf16(L_TxN):
     return out if ldb == n else out[:, :n]
 
 
-def syrk(L_TxN):
-    """Sigma = L L^T (n x n float32, symmetric, both triangles)."""
+def syrk(L_TxN, method="fp32"):
+    """Sigma = L L^T (n x n float32, symmetric, both triangles).
+
+    method "fp32": float32 matrix cores; "split": bfloat16 matrix cores on
+    three-plane operands (npga_syrk_split)."""
     Lb, n, cols, ld = _as_colmajor(L_TxN)
     lds = ld
     S = torch.empty((n, lds), dtype=torch.float32, device=Lb.device)
-    _check(_lib.npga_syrk(_ptr(Lb), n, cols, ld, _ptr(S), lds, _stream()), "npga_syrk")
+    if method == "fp32":
+        _check(_lib.npga_syrk(_ptr(Lb), n, cols, ld, _ptr(S), lds, _stream()), "npga_syrk")
+    elif method == "split":
+        ws = _workspace(_lib.npga_syrk_split_workspace_size(n, cols), Lb.device)
+        _check(_lib.npga_syrk_split(_ptr(Lb), n, cols, ld, _ptr(S), lds, _ptr(ws), ws.numel(), _stream()),
+               "npga_syrk_split")
+    else:
+        raise ValueError(method)
     return S[:, :n]

@@ -1,6 +1,8 @@
 """Build libnpga.so for gfx950 with hipcc (in-tree).
 
-Usage: python -m paper_2604_02917_amd.build   (or build() from Python)
+Usage: python paper_2604_02917_amd/build.py   (or __graft_entry__.build()).
+Run it as a file: importing the package first would load the library that
+is about to be rebuilt.
 """
 import os
 import subprocess

@@ -125,3 +125,13 @@ def test_invalid_arguments_rejected_before_launch():
     o.alpha = float("inf")
     assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
                                   null, 0, null) == 1
+
+
+def test_build_script_runs_without_importing_the_package():
+    """The build must work on a checkout with no library: the build script
+    imports nothing from the package (whose import loads the library)."""
+    src = open(os.path.join(ROOT, "paper_2604_02917_amd", "build.py")).read()
+    assert "import paper_2604_02917_amd" not in src and "from paper_2604_02917_amd" not in src
+    assert "from ." not in src
+    entry = open(os.path.join(ROOT, "__graft_entry__.py")).read()
+    assert "spec_from_file_location" in entry
