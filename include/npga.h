@@ -245,7 +245,16 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  *
  * npga_syrk - Sigma = L L^T (n x n float32, column-major, leading dim lds,
  *   both triangles written) by float32 MFMA with float64 accumulation
- *   across k-chunks.  The explicit-covariance form of Sec. 3.1 uses it.
+ *   across k-chunks.  Explicit-covariance form of Sec. 3.1 (gradient 2 Sigma x).
+ *
+ * npga_syrk_split - the same Sigma on the bfloat16 matrix cores: every entry
+ *   of L is split exactly into three bfloat16 planes (24 significant bits)
+ *   and the six plane products of weight >= 2^-24 are accumulated in float32
+ *   (float64 every 256 periods), which matches the float32 product to its
+ *   rounding.  ws (device, 256-byte aligned) holds the planes:
+ *   npga_syrk_split_workspace_size(n, T) bytes (3 n ceil64(T) bfloat16).
+ *   L 16-byte aligned, ld % 4 == 0.  The solve's covariance path uses it.
+ *   NPGA_ERR_WORKSPACE if ws is missing or small.
  * ------------------------------------------------------------------------- */
 int npga_project(const double *v, const double *mu, int64_t n, double r, double *x,
                  double *nu_tau, void *ws, size_t ws_bytes, hipStream_t stream);
@@ -256,6 +265,9 @@ int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, in
                           hipStream_t stream);
 int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds,
               hipStream_t stream);
+size_t npga_syrk_split_workspace_size(int64_t n, int64_t T);
+int npga_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * npga_sketch_str - Sketch-Truncate-Ridge (Sec. 2.5; App. D):

@@ -93,8 +93,10 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
   if (path == NPGA_PATH_SYRK) {
     const int64_t lds = (n + 3) / 4 * 4;
     l.off_sigma = take(sizeof(float) * (size_t)lds * (size_t)n);
+    l.off_planes = take(syrk_split_bytes(n, cols));  // bfloat16 planes of L for the SYRK
   } else {
     l.off_sigma = 0;
+    l.off_planes = 0;
   }
   l.off_vecs = take(sizeof(double) * npad * 4);
   l.off_xa = take(sizeof(double) * npad);
@@ -138,6 +140,7 @@ struct Carved {
   SolveArgs a;
   DevState *st;
   float *sigma;
+  uint16_t *planes;  // SYRK path: three bfloat16 planes of L
   int64_t lds;
   bool precise = false;       // refinement steps with float64 products (H p by two float64 passes)
   double *uscratch = nullptr; // cols doubles for those passes
@@ -167,6 +170,7 @@ Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
   c.st = a.st;
   c.lds = (f->n + 3) / 4 * 4;
   c.sigma = (path == NPGA_PATH_SYRK) ? reinterpret_cast<float *>(base + l.off_sigma) : nullptr;
+  c.planes = (path == NPGA_PATH_SYRK) ? reinterpret_cast<uint16_t *>(base + l.off_planes) : nullptr;
   return c;
 }
 
@@ -435,7 +439,8 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
 
   // explicit covariance (SYRK path): Sigma = L L^T once
   if (path == NPGA_PATH_SYRK)
-    LAUNCHCHK(npga::launch_syrk(static_cast<const float *>(f->L), f->n, f->cols, f->ld, c.sigma, c.lds, stream));
+    LAUNCHCHK(npga::launch_syrk_split(static_cast<const float *>(f->L), f->n, f->cols, f->ld, c.planes, c.sigma,
+                                      c.lds, stream));
 
   // step size alpha = 1/(safety L_f_hat) from ||L_eff||_2^2 (Sec. 3.1 Remark)
   LAUNCHCHK(estimate_step(c, path, slots, o, stream, step_lanczos_tol(o)));
@@ -637,6 +642,20 @@ int npga_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, in
     return NPGA_ERR_INVALID;
   if (!aligned(L, 16) || !aligned(Sigma, 16)) return NPGA_ERR_INVALID;
   LAUNCHCHK(npga::launch_syrk(L, n, T, ld, Sigma, lds, stream));
+  return NPGA_OK;
+}
+
+size_t npga_syrk_split_workspace_size(int64_t n, int64_t T) {
+  if (n < 1 || T < 1) return 0;
+  return npga::syrk_split_bytes(n, T);
+}
+
+int npga_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, int64_t lds, void *ws,
+                    size_t ws_bytes, hipStream_t stream) {
+  if (!L || !Sigma || n < 1 || T < 1 || ld < n || (ld % 4) != 0 || lds < n || !aligned(L, 16))
+    return NPGA_ERR_INVALID;
+  if (!ws || !aligned(ws, 256) || ws_bytes < npga::syrk_split_bytes(n, T)) return NPGA_ERR_WORKSPACE;
+  LAUNCHCHK(npga::launch_syrk_split(L, n, T, ld, static_cast<uint16_t *>(ws), Sigma, lds, stream));
   return NPGA_OK;
 }
 

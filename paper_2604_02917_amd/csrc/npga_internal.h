@@ -188,7 +188,7 @@ int batch_default_config(int64_t n, int64_t cols, int32_t m);
 // Workspace carving for a solve.
 struct SolveLayout {
   size_t off_state, off_status_dev, off_xs, off_x0, off_x1, off_g0, off_g1, off_part, off_usq,
-      off_sigma, off_vecs, off_xa, off_ga, off_ua, total;
+      off_sigma, off_planes, off_vecs, off_xa, off_ga, off_ua, total;
   int32_t slots;
   int32_t sweep_grid;
   int64_t ldp;
@@ -222,6 +222,11 @@ int launch_syrk(const float *L, int64_t n, int64_t T, int64_t ld, float *Sigma, 
 int launch_symv_tail(const SolveArgs &a, const float *Sigma, int64_t lds, int slots,
                      hipStream_t s);
 int launch_symv(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, hipStream_t s);
+// Sigma = L L^T by bfloat16 matrix cores on three-plane operands; planes:
+// syrk_split_bytes(n, T) bytes of scratch (16-byte aligned)
+size_t syrk_split_bytes(int64_t n, int64_t T);
+int launch_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *planes, float *Sigma,
+                      int64_t lds, hipStream_t s);
 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,

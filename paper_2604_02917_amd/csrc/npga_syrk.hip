@@ -148,6 +148,218 @@ __global__ __launch_bounds__(512) void k_syrk(const float *__restrict__ L, int64
     }
 }
 
+// --------------------------------------------------------------------------
+// Sigma = L L^T on the bfloat16 matrix cores with three-plane operands.
+//
+// Every float32 entry is split exactly into three bfloat16 planes,
+// v = v_h + v_m + v_l (v_h = bf16(v), v_m = bf16(v - v_h), v_l = bf16(v -
+// v_h - v_m); each difference is exact in float32), which carries 24
+// significant bits.  A product of two such entries keeps the six plane
+// products whose weight is at least 2^-24 of the leading one (h h, h m,
+// m h, h l, m m, l h); each is exact in float32, and
+// v_mfma_f32_32x32x16_bf16 accumulates them in float32, flushed to float64
+// every 256 periods like the float32 kernel.  Six bfloat16 products run at
+// 2.5 PFLOP/s against one float32 product at 157 TFLOP/s.
+//
+// k_split_t: L (float32, column-major, ld) -> three planes stored
+//   row-major, P_pl[i ldt + t], with zeros for t in [T, ldt); one 64 x 64
+//   tile per workgroup, transposed through LDS.
+// k_syrk16: 128 x 128 tiles of the lower triangle, eight wavefronts of
+//   32 x 64; 32-period stages of both row panels (three planes each) in LDS,
+//   double buffered; the mirrored tile is written too.
+// --------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+constexpr int kSplitTile = 64;
+constexpr int kLDH = 40;  // LDS row length in bfloat16 (80 bytes, 16-byte aligned)
+
+__device__ __forceinline__ uint32_t rne_bf16(float f) {  // finite inputs
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+__global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ L, int64_t n, int64_t T, int64_t ld,
+                                                 uint16_t *__restrict__ P, int64_t ldt, int64_t plane) {
+  __shared__ float tile[kSplitTile][kSplitTile + 1];  // [t][i]
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * kSplitTile, i0 = (int64_t)blockIdx.y * kSplitTile;
+  const int il = 4 * (tid & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int tl = (tid >> 4) + 16 * q;
+    const int64_t t = t0 + tl, i = i0 + il;
+    f4 v = f4{0.f, 0.f, 0.f, 0.f};
+    if (t < T && i < n) {
+      v = *reinterpret_cast<const f4 *>(L + t * ld + i);
+      if (i + 1 >= n) v.y = 0.f;
+      if (i + 2 >= n) v.z = 0.f;
+      if (i + 3 >= n) v.w = 0.f;
+    }
+    tile[tl][il + 0] = v.x;
+    tile[tl][il + 1] = v.y;
+    tile[tl][il + 2] = v.z;
+    tile[tl][il + 3] = v.w;
+  }
+  __syncthreads();
+  // row i0 + (tid >> 2), periods t0 + 16 (tid & 3) .. +15: two 8-entry groups per plane
+  const int ir = tid >> 2, ts = 16 * (tid & 3);
+  const int64_t i = i0 + ir;
+  if (i >= n) return;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    uint32_t hw[4], mw[4], lw[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t h2[2], m2[2], l2[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float v = tile[ts + 8 * g + 2 * w + e][ir];
+        h2[e] = rne_bf16(v);
+        const float r1 = v - bf16_f32(h2[e]);
+        m2[e] = rne_bf16(r1);
+        l2[e] = rne_bf16(r1 - bf16_f32(m2[e]));
+      }
+      hw[w] = h2[0] | (h2[1] << 16);
+      mw[w] = m2[0] | (m2[1] << 16);
+      lw[w] = l2[0] | (l2[1] << 16);
+    }
+    const int64_t off = i * ldt + t0 + ts + 8 * g;
+    *reinterpret_cast<u4v *>(P + off) = u4v{hw[0], hw[1], hw[2], hw[3]};
+    *reinterpret_cast<u4v *>(P + plane + off) = u4v{mw[0], mw[1], mw[2], mw[3]};
+    *reinterpret_cast<u4v *>(P + 2 * plane + off) = u4v{lw[0], lw[1], lw[2], lw[3]};
+  }
+}
+
+__device__ __forceinline__ bf8 lds_bf8x(const uint16_t *p) {
+  return __builtin_bit_cast(bf8, *reinterpret_cast<const u4v *>(p));
+}
+
+__global__ __launch_bounds__(512) void k_syrk16(const uint16_t *__restrict__ P, int64_t n, int64_t ldt,
+                                                int64_t plane, float *__restrict__ S, int64_t lds, int nb) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][3][kTile * kLDH];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][3][kTile * kLDH];
+  const int ntiles = nb * (nb + 1) / 2;
+  const int b = blockIdx.x;
+  const int per_xcd = (ntiles + 7) / 8;
+  const int tix = (b % 8) * per_xcd + (b / 8);
+  if (tix >= ntiles) return;
+  int bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
+  const int bj = tix - bi * (bi + 1) / 2;
+  const int64_t row_a = (int64_t)bi * kTile, row_b = (int64_t)bj * kTile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32.., columns wc*64..
+  const int h = lane >> 5, r = lane & 31;
+
+  // staging: thread tid loads, for each plane, the 8 periods 8 (tid & 3) ..
+  // of panel row tid >> 2
+  const int prow = tid >> 2, pseg = 8 * (tid & 3);
+  const bool oka = row_a + prow < n, okb = row_b + prow < n;
+  const uint16_t *pa = P + (row_a + prow) * ldt + pseg;
+  const uint16_t *pb = P + (row_b + prow) * ldt + pseg;
+  u4v ra[3], rb[3];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      ra[pl] = oka ? *reinterpret_cast<const u4v *>(pa + pl * plane + k0) : u4v{0u, 0u, 0u, 0u};
+      rb[pl] = okb ? *reinterpret_cast<const u4v *>(pb + pl * plane + k0) : u4v{0u, 0u, 0u, 0u};
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+      *reinterpret_cast<u4v *>(&As[buf][pl][prow * kLDH + pseg]) = ra[pl];
+      *reinterpret_cast<u4v *>(&Bs[buf][pl][prow * kLDH + pseg]) = rb[pl];
+    }
+  };
+
+  v16f acc[2];
+  double acc64[2][16];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      acc[q][v] = 0.f;
+      acc64[q][v] = 0.0;
+    }
+  const int64_t nstages = ldt / kKB;  // ldt is a multiple of 64
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t st = 0; st < nstages; ++st) {
+    const int buf = (int)(st & 1);
+    if (st + 1 < nstages) gload((st + 1) * kKB);
+#pragma unroll
+    for (int ks = 0; ks < kKB / 16; ++ks) {
+      const int koff = 16 * ks + 8 * h;
+      bf8 a[3], bb[2][3];
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) a[pl] = lds_bf8x(&As[buf][pl][(wr * 32 + r) * kLDH + koff]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) bb[q][pl] = lds_bf8x(&Bs[buf][pl][(wc * 64 + 32 * q + r) * kLDH + koff]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        // smallest terms first
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], bb[q][0], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[q][1], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[q][2], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[q][0], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[q][1], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[q][0], acc[q], 0, 0, 0);
+      }
+    }
+    if (((st + 1) % kFlushStages) == 0 || st + 1 == nstages) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          acc64[q][v] += (double)acc[q][v];
+          acc[q][v] = 0.f;
+        }
+    }
+    if (st + 1 < nstages) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // the tile and its mirror; 32 x 32 output layout: lane (h, r), register v
+  // -> row 8 (v/4) + 4 h + (v%4), column r
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t rr = row_a + wr * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int64_t cc = row_b + wc * 64 + 32 * q + r;
+      // the plane products of (i, j) and (j, i) are summed in different
+      // orders, so a diagonal tile keeps its lower half and mirrors it
+      if (rr < n && cc < n && (bi != bj || rr >= cc)) {
+        const float val = (float)acc64[q][v];
+        S[rr + cc * lds] = val;
+        S[cc + rr * lds] = val;
+      }
+    }
+}
+
+int64_t split_ldt(int64_t T) { return (T + kSplitTile - 1) / kSplitTile * kSplitTile; }
+
+size_t syrk_split_bytes(int64_t n, int64_t T) { return (size_t)3 * (size_t)n * (size_t)split_ldt(T) * 2; }
+
+int launch_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *planes, float *Sigma,
+                      int64_t lds, hipStream_t s) {
+  const int64_t ldt = split_ldt(T);
+  const int64_t plane = n * ldt;
+  hipLaunchKernelGGL(k_split_t, dim3((unsigned)(ldt / kSplitTile), (unsigned)((n + kSplitTile - 1) / kSplitTile)),
+                     dim3(256), 0, s, L, n, T, ld, planes, ldt, plane);
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  const int nb = (int)((n + kTile - 1) / kTile);
+  const int ntiles = nb * (nb + 1) / 2;
+  const int grid = ((ntiles + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_syrk16, dim3(grid), dim3(512), 0, s, planes, n, ldt, plane, Sigma, lds, nb);
+  return (int)hipGetLastError();
+}
+
 // g = 2 Sigma x (+ 2 gamma x); the serial tail runs as a separate launch.
 // A wavefront per column, the next column's loads in flight while the
 // current one is reduced (Sigma, 118 MB at n = 5440, stays in the MALL

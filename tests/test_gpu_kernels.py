@@ -144,3 +144,28 @@ def test_syrk_matches_oracle(npga, n, T):
     # float64 across chunks, final rounding to float32
     assert np.all(np.abs(S - S_ref) <= (256 + 2) * U32 * B + U32 * np.abs(S_ref))
     assert np.array_equal(S, S.T)
+
+
+@pytest.mark.parametrize("n,T", [(64, 256), (130, 1000), (1000, 5000), (259, 77), (5440, 3000)])
+def test_syrk_split_matches_oracle(npga, n, T):
+    """Sigma from three bfloat16 planes per entry on the bfloat16 matrix
+    cores: the three dropped plane products weigh at most 3 2^-24 (plus the
+    planes' own rounding, 2^-25), the kept ones are exact in float32 and are
+    accumulated in float32 over 256-period chunks (six per period), float64
+    across chunks; the result is within the float32 kernel's bound and as
+    close to the exact Sigma as the float32 kernel's."""
+    banner(f"syrk split n={n} T={T}")
+    spec = spec_with("c2", n, T, seed=210 + n)
+    Rt = gen.returns_TxN(spec)
+    Ld = to_dev(Rt)
+    S = npga.syrk(Ld, method="split").cpu().numpy().astype(np.float64)
+    S32 = npga.syrk(Ld).cpu().numpy().astype(np.float64)
+    L = Rt.T.astype(np.float64)
+    S_ref = L @ L.T
+    B = np.abs(L) @ np.abs(L).T
+    assert np.all(np.abs(S - S_ref) <= (256 + 2) * U32 * B + U32 * np.abs(S_ref))
+    assert np.array_equal(S, S.T)
+    e_split = np.abs(S - S_ref).max() / np.abs(S_ref).max()
+    e_f32 = np.abs(S32 - S_ref).max() / np.abs(S_ref).max()
+    banner(f"  max rel error: split {e_split:.2e}, float32 {e_f32:.2e}")
+    assert e_split <= 4 * e_f32 + 4 * U32
