@@ -281,12 +281,16 @@ int npga_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, float *Sig
  *   Leff    device n x ell float32 output (ldle >= n, multiple of 4)
  *   sigma   device ell float32 output: leading singular values of Y
  *   gamma_out (host) receives gamma
- *   ws      npga_sketch_workspace_size(n, T, k, ell) bytes
- * Requires 1 <= ell <= k <= 8192.  The truncation computes the top-ell
- * eigenpairs of G = Y^T Y with a float64 Householder tridiagonalisation,
- * bisection and inverse iteration; L_eff = Y V_ell is then the same
- * Sigma_hat as U_ell S_ell^2 U_ell^T for any orthonormal basis V_ell of
- * that eigenspace.  Synchronises `stream`.
+ *   ws      npga_sketch_workspace_size(n, T, k, ell) bytes (it includes the
+ *           three bfloat16 planes of L and S, 6 (n + k) ceil64(T) bytes)
+ * Requires 1 <= ell <= k <= 8192.  Y = L S runs on the bfloat16 matrix
+ * cores with three-plane operands (the six plane products of weight
+ * >= 2^-24 per entry product; float32 accumulation, float64 every 256
+ * periods), as accurate as a float32 product.  The truncation computes the
+ * top-ell eigenpairs of G = Y^T Y with a float64 Householder
+ * tridiagonalisation, Sturm-count multisection and inverse iteration;
+ * L_eff = Y V_ell is then the same Sigma_hat as U_ell S_ell^2 U_ell^T for
+ * any orthonormal basis V_ell of that eigenspace.  Synchronises `stream`.
  * ------------------------------------------------------------------------- */
 size_t npga_sketch_workspace_size(int64_t n, int64_t T, int64_t k, int64_t ell);
 

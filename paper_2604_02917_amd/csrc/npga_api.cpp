@@ -702,13 +702,13 @@ int npga_build_factor(const float *R, int64_t n, int64_t T, int64_t ldr, float *
 namespace {
 
 struct SketchLayout {
-  size_t off_S, off_Y, off_A, off_vec, off_Z, off_work, off_V32, off_frob, off_gamma, total;
+  size_t off_S, off_Y, off_A, off_vec, off_Z, off_work, off_V32, off_frob, off_gamma, off_planes, total;
   int64_t ldS, ldy, stride;
 };
 
 constexpr int kFrobParts = 256;
 
-SketchLayout sketch_layout(int64_t n, int64_t T, int64_t k, int64_t ell, bool need_S) {
+SketchLayout sketch_layout(int64_t n, int64_t T, int64_t k, int64_t ell, bool need_S, bool gemm = true) {
   SketchLayout l{};
   l.ldS = (T + 3) / 4 * 4;
   l.ldy = (n + 3) / 4 * 4;
@@ -728,6 +728,8 @@ SketchLayout sketch_layout(int64_t n, int64_t T, int64_t k, int64_t ell, bool ne
   l.off_V32 = take(sizeof(float) * (size_t)k * (size_t)ell);
   l.off_frob = take(sizeof(double) * kFrobParts);
   l.off_gamma = take(sizeof(double) * 4);
+  // bfloat16 planes of L and S for the sketch product (Gaussian sketch)
+  l.off_planes = gemm ? take(npga::gemm_split_bytes(n, k, T)) : 0;
   l.total = off;
   return l;
 }
@@ -757,7 +759,9 @@ void npga_default_str_options(npga_str_options *so) {
 
 size_t npga_sketch_ex_workspace_size(int64_t n, int64_t T, const npga_str_options *so) {
   if (!so) return 0;
-  return npga_sketch_workspace_size(n, T, so->k, std::min(so->ell + 1, so->k));
+  const int64_t k = so->k, ell = std::min(so->ell + 1, so->k);
+  if (n < 1 || T < 1 || k < 1 || ell < 1 || k > NPGA_MAX_N) return 0;
+  return sketch_layout(n, T, k, ell, true, so->sketch != NPGA_SKETCH_COUNT).total;
 }
 
 int npga_sketch_str_ex(const float *L, int64_t n, int64_t T, int64_t ldl, const npga_str_options *so, float *Leff,
@@ -780,7 +784,7 @@ int npga_sketch_str_ex(const float *L, int64_t n, int64_t T, int64_t ldl, const 
   // eigenpairs computed: ell (fixed), or ell_cap + 1 eigenvalues for the knee rule
   const int64_t m_eig = so->ell_rule == NPGA_ELL_KNEE ? ell_cap + 1 : ell_cap;
   const bool draw_S = so->sketch == NPGA_SKETCH_GAUSSIAN && !so->S;
-  const SketchLayout lay = sketch_layout(n, T, k, m_eig, draw_S);
+  const SketchLayout lay = sketch_layout(n, T, k, m_eig, draw_S, so->sketch != NPGA_SKETCH_COUNT);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   char *base = static_cast<char *>(ws);
   float *Y = reinterpret_cast<float *>(base + lay.off_Y);
@@ -818,7 +822,9 @@ int npga_sketch_str_ex(const float *L, int64_t n, int64_t T, int64_t ldl, const 
       S = Sw;
       lds = lay.ldS;
     }
-    LAUNCHCHK(npga::launch_gemm_f32(L, ldl, S, lds, Y, lay.ldy, n, k, T, stream));
+    // Y = L S on the bfloat16 matrix cores with three-plane operands
+    LAUNCHCHK(npga::launch_gemm_split(L, ldl, S, lds, Y, lay.ldy, n, k, T,
+                                      reinterpret_cast<uint16_t *>(base + lay.off_planes), stream));
   }
   // truncation stage: eigenpairs of G = Y^T Y
   LAUNCHCHK(npga::launch_gram_f64(Y, lay.ldy, n, k, s.A, stream));

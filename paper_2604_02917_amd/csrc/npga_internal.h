@@ -227,6 +227,12 @@ int launch_symv(const SolveArgs &a, const float *Sigma, int64_t lds, int slots, 
 size_t syrk_split_bytes(int64_t n, int64_t T);
 int launch_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *planes, float *Sigma,
                       int64_t lds, hipStream_t s);
+// C (M x N) = A B, A[m + k lda] (rows contiguous), B[k + n ldb] (contraction
+// contiguous), on the same three-plane bfloat16 matrix cores; planes:
+// gemm_split_bytes(M, N, K) bytes of scratch (16-byte aligned)
+size_t gemm_split_bytes(int64_t m, int64_t ncols, int64_t K);
+int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                      int64_t N, int64_t K, uint16_t *planes, hipStream_t s);
 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,

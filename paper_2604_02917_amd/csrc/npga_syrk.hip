@@ -16,6 +16,7 @@
 // (atomic ticket) then runs the same NPGA tail as the factor path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "npga_device.h"
@@ -164,9 +165,10 @@ __global__ __launch_bounds__(512) void k_syrk(const float *__restrict__ L, int64
 // k_split_t: L (float32, column-major, ld) -> three planes stored
 //   row-major, P_pl[i ldt + t], with zeros for t in [T, ldt); one 64 x 64
 //   tile per workgroup, transposed through LDS.
-// k_syrk16: 128 x 128 tiles of the lower triangle, eight wavefronts of
+// k_mm16<true>: 128 x 128 tiles of the lower triangle, eight wavefronts of
 //   32 x 64; 32-period stages of both row panels (three planes each) in LDS,
-//   double buffered; the mirrored tile is written too.
+//   double buffered; the mirrored tile is written too.  k_mm16<false>: the
+//   same on all tiles of a general product C = A B (the sketch Y = L S).
 // --------------------------------------------------------------------------
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
@@ -232,23 +234,70 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ L, in
   }
 }
 
+// Three planes of a matrix whose rows are already contiguous along the
+// contraction (column j of S: S[t + j lds], t < T): P_pl[j ldt + t], zeros
+// for t in [T, ldt).  A thread splits 8 consecutive entries.
+__global__ __launch_bounds__(256) void k_split_rows(const float *__restrict__ X, int64_t rows, int64_t T,
+                                                    int64_t ldx, uint16_t *__restrict__ P, int64_t ldt,
+                                                    int64_t plane) {
+  const int64_t groups = ldt / 8;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows * groups; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / groups, t0 = 8 * (e % groups);
+    uint32_t hw[4], mw[4], lw[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t h2[2], m2[2], l2[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int64_t t = t0 + 2 * w + q;
+        const float v = (t < T) ? X[j * ldx + t] : 0.f;
+        h2[q] = rne_bf16(v);
+        const float r1 = v - bf16_f32(h2[q]);
+        m2[q] = rne_bf16(r1);
+        l2[q] = rne_bf16(r1 - bf16_f32(m2[q]));
+      }
+      hw[w] = h2[0] | (h2[1] << 16);
+      mw[w] = m2[0] | (m2[1] << 16);
+      lw[w] = l2[0] | (l2[1] << 16);
+    }
+    const int64_t off = j * ldt + t0;
+    *reinterpret_cast<u4v *>(P + off) = u4v{hw[0], hw[1], hw[2], hw[3]};
+    *reinterpret_cast<u4v *>(P + plane + off) = u4v{mw[0], mw[1], mw[2], mw[3]};
+    *reinterpret_cast<u4v *>(P + 2 * plane + off) = u4v{lw[0], lw[1], lw[2], lw[3]};
+  }
+}
+
 __device__ __forceinline__ bf8 lds_bf8x(const uint16_t *p) {
   return __builtin_bit_cast(bf8, *reinterpret_cast<const u4v *>(p));
 }
 
-__global__ __launch_bounds__(512) void k_syrk16(const uint16_t *__restrict__ P, int64_t n, int64_t ldt,
-                                                int64_t plane, float *__restrict__ S, int64_t lds, int nb) {
+// SYM: C = P P^T over the lower-triangle tiles (A = B = P, n x n, mirrored);
+// otherwise C (na x nb) = PA PB^T over all tiles.  Operands: three planes,
+// row-major along the contraction (leading dim ldt, plane strides planeA,
+// planeB); C column-major with leading dim ldc.
+template <bool SYM>
+__global__ __launch_bounds__(512) void k_mm16(const uint16_t *__restrict__ PA, const uint16_t *__restrict__ PB,
+                                              int64_t na, int64_t nbr, int64_t ldt, int64_t planeA,
+                                              int64_t planeB, float *__restrict__ S, int64_t lds, int tiles_a,
+                                              int tiles_b) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][3][kTile * kLDH];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][3][kTile * kLDH];
-  const int ntiles = nb * (nb + 1) / 2;
+  const int ntiles = SYM ? tiles_a * (tiles_a + 1) / 2 : tiles_a * tiles_b;
   const int b = blockIdx.x;
   const int per_xcd = (ntiles + 7) / 8;
-  const int tix = (b % 8) * per_xcd + (b / 8);
+  const int tix = (b % 8) * per_xcd + (b / 8);  // consecutive tiles on one XCD
   if (tix >= ntiles) return;
-  int bi = 0;
-  while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
-  const int bj = tix - bi * (bi + 1) / 2;
+  int bi = 0, bj = 0;
+  if (SYM) {
+    while ((bi + 1) * (bi + 2) / 2 <= tix) ++bi;
+    bj = tix - bi * (bi + 1) / 2;
+  } else {
+    bi = tix % tiles_a;
+    bj = tix / tiles_a;
+  }
   const int64_t row_a = (int64_t)bi * kTile, row_b = (int64_t)bj * kTile;
+  const int64_t n = na, plane = planeA;
+  const uint16_t *P = PA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // rows wr*32.., columns wc*64..
   const int h = lane >> 5, r = lane & 31;
@@ -256,15 +305,16 @@ __global__ __launch_bounds__(512) void k_syrk16(const uint16_t *__restrict__ P, 
   // staging: thread tid loads, for each plane, the 8 periods 8 (tid & 3) ..
   // of panel row tid >> 2
   const int prow = tid >> 2, pseg = 8 * (tid & 3);
-  const bool oka = row_a + prow < n, okb = row_b + prow < n;
+  const bool oka = row_a + prow < n, okb = row_b + prow < (SYM ? n : nbr);
   const uint16_t *pa = P + (row_a + prow) * ldt + pseg;
-  const uint16_t *pb = P + (row_b + prow) * ldt + pseg;
+  const uint16_t *pb = (SYM ? P : PB) + (row_b + prow) * ldt + pseg;
+  const int64_t planeb = SYM ? plane : planeB;
   u4v ra[3], rb[3];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int pl = 0; pl < 3; ++pl) {
       ra[pl] = oka ? *reinterpret_cast<const u4v *>(pa + pl * plane + k0) : u4v{0u, 0u, 0u, 0u};
-      rb[pl] = okb ? *reinterpret_cast<const u4v *>(pb + pl * plane + k0) : u4v{0u, 0u, 0u, 0u};
+      rb[pl] = okb ? *reinterpret_cast<const u4v *>(pb + pl * planeb + k0) : u4v{0u, 0u, 0u, 0u};
     }
   };
   auto sstore = [&](int buf) {
@@ -332,12 +382,16 @@ __global__ __launch_bounds__(512) void k_syrk16(const uint16_t *__restrict__ P, 
     for (int v = 0; v < 16; ++v) {
       const int64_t rr = row_a + wr * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
       const int64_t cc = row_b + wc * 64 + 32 * q + r;
-      // the plane products of (i, j) and (j, i) are summed in different
-      // orders, so a diagonal tile keeps its lower half and mirrors it
-      if (rr < n && cc < n && (bi != bj || rr >= cc)) {
-        const float val = (float)acc64[q][v];
-        S[rr + cc * lds] = val;
-        S[cc + rr * lds] = val;
+      if (SYM) {
+        // the plane products of (i, j) and (j, i) are summed in different
+        // orders, so a diagonal tile keeps its lower half and mirrors it
+        if (rr < n && cc < n && (bi != bj || rr >= cc)) {
+          const float val = (float)acc64[q][v];
+          S[rr + cc * lds] = val;
+          S[cc + rr * lds] = val;
+        }
+      } else if (rr < n && cc < nbr) {
+        S[rr + cc * lds] = (float)acc64[q][v];
       }
     }
 }
@@ -356,7 +410,31 @@ int launch_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t
   const int nb = (int)((n + kTile - 1) / kTile);
   const int ntiles = nb * (nb + 1) / 2;
   const int grid = ((ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_syrk16, dim3(grid), dim3(512), 0, s, planes, n, ldt, plane, Sigma, lds, nb);
+  hipLaunchKernelGGL(k_mm16<true>, dim3(grid), dim3(512), 0, s, planes, planes, n, n, ldt, plane, plane, Sigma,
+                     lds, nb, nb);
+  return (int)hipGetLastError();
+}
+
+size_t gemm_split_bytes(int64_t m, int64_t ncols, int64_t K) {
+  return (size_t)3 * (size_t)(m + ncols) * (size_t)split_ldt(K) * 2;
+}
+
+int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                      int64_t N, int64_t K, uint16_t *planes, hipStream_t s) {
+  const int64_t ldt = split_ldt(K);
+  const int64_t planeA = M * ldt, planeB = N * ldt;
+  uint16_t *PA = planes, *PB = planes + 3 * planeA;
+  hipLaunchKernelGGL(k_split_t, dim3((unsigned)(ldt / kSplitTile), (unsigned)((M + kSplitTile - 1) / kSplitTile)),
+                     dim3(256), 0, s, A, M, K, lda, PA, ldt, planeA);
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  const int64_t groups = N * (ldt / 8);
+  const int sgrid = (int)std::min<int64_t>((groups + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_rows, dim3(sgrid), dim3(256), 0, s, B, N, K, ldb, PB, ldt, planeB);
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  const int ta = (int)((M + kTile - 1) / kTile), tb = (int)((N + kTile - 1) / kTile);
+  const int grid = ((ta * tb + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_mm16<false>, dim3(grid), dim3(512), 0, s, PA, PB, M, N, ldt, planeA, planeB, C, ldc, ta,
+                     tb);
   return (int)hipGetLastError();
 }
 
