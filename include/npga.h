@@ -114,7 +114,8 @@ typedef struct npga_options {
                             needs gamma > 0, else NPGA_ERR_INVALID                     */
   int32_t step_estimator; /* 0: Lanczos on L_eff L_eff^T (default), stopped when the
                             Ritz residual beta_m |s_m| is below tol theta, tol =
-                            min(1e-2, max((step_safety - 1)/4, 1e-4)); 1: the power
+                            min(1e-2, max((step_safety - 1)/4, 1e-4)) for a single
+                            solve and 1e-4 for a batched one; 1: the power
                             method of the paper's Remark.  Both approach ||L_eff||^2
                             from below; step_safety covers the remainder              */
   int32_t batch_config;  /* batched solves: tile configuration 0..NPGA_BATCH_CONFIGS-1
