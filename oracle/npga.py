@@ -41,6 +41,12 @@ class FactorModel:
         n = self.L.shape[0]
         return 2.0 * (self.L @ self.L.T + self.gamma * np.eye(n))
 
+    def curv(self, d):
+        """d^T Q d = ||L^T d||^2 + gamma ||d||^2: for this quadratic f,
+        f(x) - f(y) - <grad f(y), x - y> equals curv(x - y) exactly."""
+        u = self.L.T @ d
+        return float(u @ u + self.gamma * (d @ d))
+
     def lipschitz_exact(self):
         """L_f = 2 ||L||_2^2 + 2 gamma."""
         s = np.linalg.norm(self.L, 2)
@@ -61,6 +67,10 @@ class CovarianceModel:
 
     def hessian(self):
         return 2.0 * self.S
+
+    def curv(self, d):
+        """d^T Sigma d (= f(x) - f(y) - <grad f(y), x - y> with d = x - y)."""
+        return float(d @ (self.S @ d))
 
     def lipschitz_exact(self):
         return 2.0 * float(np.linalg.eigvalsh(self.S)[-1])
@@ -92,7 +102,7 @@ def constant_momentum(alpha, m_f):
 
 
 def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
-         restart=False, record=False, beta_const=None):
+         restart=False, record=False, beta_const=None, backtrack=None):
     """Algorithm 1 with the fixed step ``alpha``.
 
     ``x0`` is projected onto F first (Algorithm 1 requires x^0 in F).
@@ -103,6 +113,18 @@ def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
     when (y^k - x^{k+1})^T (x^{k+1} - x^k) > 0); it is off by default.
     ``beta_const`` replaces the t_k sequence by a constant momentum (used
     from the second step on; the first step has beta = 0).
+    ``backtrack = rho`` (0 < rho < 1) turns on the adaptive backtracking of
+    Sec. 3.1: starting from the previous accepted step (``alpha`` at k = 0),
+    the trial step is multiplied by rho until the point
+    x^{k+1} = Pi_F(y^k - alpha_k grad f(y^k)) satisfies
+    f(x^{k+1}) <= f(y^k) + <grad f(y^k), x^{k+1} - y^k>
+                 + ||x^{k+1} - y^k||^2 / (2 alpha_k).
+    The steps are then nonincreasing; the returned dict adds ``alpha`` (the
+    last accepted step) and ``rejections`` (trial steps refused).  f is
+    quadratic, so the test is evaluated in its exact rearranged form
+    curv(d) <= ||d||^2 / (2 alpha_k), d = x^{k+1} - y^k (curv(d) = d^T Q d is
+    f(x^{k+1}) - f(y^k) - <grad f(y^k), d>), which avoids the cancellation
+    of the direct form once the steps are small.
     """
     mu = np.asarray(mu, dtype=np.float64)
     x, _, _ = proj_F(np.asarray(x0, dtype=np.float64), mu, r)
@@ -111,6 +133,7 @@ def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
     trace = []
     res = np.inf
     k = 0
+    rejections = 0
     while True:
         if k % check_every == 0:
             gx = model.grad(x)
@@ -119,12 +142,23 @@ def npga(model, mu, r, alpha, x0, tol=1e-6, check_every=5, max_iter=100000,
             if record:
                 trace.append((k, res))
             if res <= tol:
-                return dict(x=x, iters=k, residual=res, converged=True, trace=trace)
+                return dict(x=x, iters=k, residual=res, converged=True, trace=trace, alpha=alpha,
+                            rejections=rejections)
         if k >= max_iter:
-            return dict(x=x, iters=k, residual=res, converged=False, trace=trace)
+            return dict(x=x, iters=k, residual=res, converged=False, trace=trace, alpha=alpha,
+                        rejections=rejections)
         y = x + beta * (x - x_prev)
-        v = y - alpha * model.grad(y)
+        gy = model.grad(y)
+        v = y - alpha * gy
         x_new, _, _ = proj_F(v, mu, r)
+        if backtrack is not None:
+            while True:
+                d = x_new - y
+                if model.curv(d) <= (d @ d) / (2.0 * alpha):
+                    break
+                alpha *= backtrack
+                rejections += 1
+                x_new, _, _ = proj_F(y - alpha * gy, mu, r)
         if restart and (y - x_new) @ (x_new - x) > 0:
             t = 1.0
         t_new = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))

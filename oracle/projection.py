@@ -106,3 +106,41 @@ def proj_F(v, mu, r, max_double=2000, max_bisect=400):
             hi = mid
     x = proj_simplex(v + hi * mu)
     return x, hi, simplex_threshold_sort(v + hi * mu)
+
+
+def proj_halfspace(z, mu, r):
+    """Pi_H(z) for H = {x : mu^T x >= r}: z + max(0, r - mu^T z)/||mu||^2 mu."""
+    z = np.asarray(z, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    s = float(mu @ z)
+    if s >= r:
+        return z.copy()
+    return z + ((r - s) / float(mu @ mu)) * mu
+
+
+def dykstra(v, mu, r, max_iter=100000, tol=1e-12):
+    """Pi_F(v) by Dykstra's alternating projections onto the simplex Delta
+    and the half-space H = {mu^T x >= r}, the safeguarded fallback of Sec. 3.1
+    (Bauschke and Borwein, 1996).  With x_0 = v and p_0 = q_0 = 0:
+        y_k = Pi_Delta(x_k + p_k),   p_{k+1} = x_k + p_k - y_k,
+        x_{k+1} = Pi_H(y_k + q_k),   q_{k+1} = y_k + q_k - x_{k+1};
+    both sequences converge to Pi_{Delta cap H}(v).  Stops when
+    ||x_{k+1} - y_k||_2 and ||y_k - y_{k-1}||_2 are both <= tol.
+    Returns (y, iterations); y lies in Delta exactly."""
+    v = np.asarray(v, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    x = v.copy()
+    p = np.zeros_like(v)
+    q = np.zeros_like(v)
+    y = np.zeros_like(v)
+    for k in range(1, max_iter + 1):
+        y_new = proj_simplex(x + p)
+        p = x + p - y_new
+        x_new = proj_halfspace(y_new + q, mu, r)
+        q = y_new + q - x_new
+        dy = float(np.linalg.norm(y_new - y))
+        dx = float(np.linalg.norm(x_new - y_new))
+        x, y = x_new, y_new
+        if k > 1 and dx <= tol and dy <= tol:
+            return y, k
+    return y, max_iter

@@ -182,3 +182,34 @@ def test_npga_trajectory_two_assets(case):
         t = t_new
         s_prev, s = s, s_new
         assert abs(traj[k][0] - s) <= 1e-13 and abs(traj[k][1] - (1.0 - s)) <= 1e-13, (k, traj[k], s)
+
+
+def test_backtracking_accepts_admissible_steps_and_converges():
+    """The backtracking rule of Sec. 3.1: from a trial step 8/L_f the
+    accepted steps shrink geometrically, never below rho/L_f (the condition
+    holds for every alpha <= 1/L_f), every accepted point satisfies the
+    sufficient-decrease inequality, and the limit is the exact minimiser."""
+    rng = np.random.default_rng(77)
+    n, T = 30, 120
+    L = rng.standard_normal((n, T)) / np.sqrt(T)
+    mu = rng.normal(5e-4, 3e-4, size=n)
+    r = float(np.quantile(mu, 0.6))
+    model = npga.FactorModel(L)
+    lf = model.lipschitz_exact()
+    rho = 0.5
+    out = npga.npga(model, mu, r, 8.0 / lf, np.full(n, 1.0 / n), tol=1e-10, max_iter=20000, backtrack=rho)
+    assert out["converged"] and out["rejections"] >= 3
+    assert rho / lf <= out["alpha"] <= 8.0 / lf
+    # the test's rearranged form is the paper's inequality: for this
+    # quadratic f, f(x) - f(y) - <grad f(y), x - y> = curv(x - y)
+    for _ in range(5):
+        x1, y1 = rng.standard_normal(n), rng.standard_normal(n)
+        lhs = model.value(x1) - model.value(y1) - model.grad(y1) @ (x1 - y1)
+        assert lhs == pytest.approx(model.curv(x1 - y1), rel=1e-10)
+    ref = exact_mv_factor(L, 0.0, mu, r)
+    assert np.abs(out["x"] - ref["x"]).max() <= 1e-7
+    # an admissible trial step is never shrunk
+    out2 = npga.npga(model, mu, r, 1.0 / lf, np.full(n, 1.0 / n), tol=1e-10, max_iter=20000, backtrack=rho)
+    assert out2["rejections"] == 0 and out2["alpha"] == 1.0 / lf
+    fixed = npga.npga(model, mu, r, 1.0 / lf, np.full(n, 1.0 / n), tol=1e-10, max_iter=20000)
+    assert out2["iters"] == fixed["iters"] and np.array_equal(out2["x"], fixed["x"])

@@ -116,3 +116,28 @@ def test_projF_target_equals_max_mu():
     x, nu, _ = P.proj_F(np.array([0.5, 0.0, 0.5, 0.1]), mu, 3e-3)
     assert x[0] == 0 and x[2] == 0
     assert abs(x.sum() - 1) < 1e-14 and abs(mu @ x - 3e-3) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_dykstra_converges_to_exact_projection(seed):
+    """Dykstra's alternating projections (the paper's fallback) reach the
+    exact Pi_F computed by the dual search; the half-space step is checked
+    against its closed form on its own."""
+    from oracle.projection import dykstra, proj_halfspace
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(2, 60))
+    mu = rng.normal(5e-4, 3e-4, size=n)
+    v = rng.normal(1.0 / n, 0.05, size=n)
+    q = [0.2, 0.5, 0.8, 0.95][seed % 4]
+    r = float(np.quantile(mu, q)) if seed % 3 else float(mu.min()) - 1e-3  # active / inactive
+    x_exact, _, _ = P.proj_F(v, mu, r)
+    y, k = dykstra(v, mu, r, tol=1e-14)
+    assert np.abs(y - x_exact).max() <= 1e-10, (k, np.abs(y - x_exact).max())
+    assert y.min() >= 0 and abs(y.sum() - 1) <= 1e-12
+    # the half-space projection: feasible, and the move is along mu
+    z = rng.normal(size=n)
+    h = proj_halfspace(z, mu, float(mu @ z) + 1e-3)
+    assert mu @ h == pytest.approx(float(mu @ z) + 1e-3, rel=1e-12)
+    d = h - z
+    assert np.allclose(d, (d @ mu) / (mu @ mu) * mu, rtol=0, atol=1e-15)
+    assert np.array_equal(proj_halfspace(z, mu, float(mu @ z) - 1.0), z)
