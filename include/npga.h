@@ -126,6 +126,21 @@ typedef struct npga_options {
                             alpha <= 1/L_f); no step estimate is made.  0 (default):
                             alpha = 1/(step_safety L_f_hat) from the estimate.  Any
                             other value: NPGA_ERR_INVALID                            */
+  int32_t projection;    /* step projections Pi_F: 0 = the exact scalar dual search,
+                            falling back to Dykstra's alternating projections onto
+                            Delta and H (Sec. 3.1) if it cannot bracket nu (default);
+                            1 = Dykstra only (to 1e-14 or dykstra_iters sweeps; the
+                            result lies on the simplex, mu^T x >= r to that accuracy) */
+  int32_t dykstra_iters; /* sweep budget of Dykstra's method; default 5000            */
+  double backtrack_rho;  /* 0 (default): fixed step.  In (0, 1): the adaptive
+                            backtracking of Sec. 3.1 from the trial step alpha
+                            (estimated, or the caller's): a new iterate x^{k+1} is
+                            kept if f(x^{k+1}) <= f(y^k) + <grad f(y^k), d> +
+                            ||d||^2/(2 alpha), d = x^{k+1} - y^k (tested as d^T Q d <=
+                            ||d||^2/(2 alpha), exact for this quadratic f, with 1e-6
+                            of sum |d|(|grad f(x)| + |grad f(y)|) allowed for the
+                            float32 products), else alpha <- rho alpha and the step
+                            is redone.  Single solves only (batched: INVALID)      */
 } npga_options;
 
 /* Result of a solve (host). */
@@ -152,7 +167,11 @@ typedef struct npga_result {
                              covariance-path SYMV+tail), timed with HIP events on
                              `stream` around one launch per chunk of the main phase   */
   int32_t sweep_samples;  /* number of launches averaged into sweep_ms               */
-  int32_t reserved2;
+  int32_t dykstra_used;   /* 1 if the step projections ran by Dykstra's method: asked
+                             for (projection = 1), or the dual search could not
+                             bracket nu and the solve was repeated with it          */
+  int32_t backtracks;     /* trial steps refused by backtracking (main phase)       */
+  int32_t reserved3;
 } npga_result;
 
 /* Fill `opt` (host) with the defaults documented above. */
@@ -225,6 +244,15 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  * Step-level entry points (each is one step of the solve, exposed so that
  * it can be checked on its own).
  *
+ * npga_project_dykstra - x = Pi_F(v) by Dykstra's alternating projections
+ *   onto Delta and H = {mu^T x >= r} (Sec. 3.1 fallback; Bauschke and
+ *   Borwein 1996): y = Pi_Delta(x + p), p += x - y, x = Pi_H(y + q), q += y - x
+ *   from x = v, until ||x - y||_2 and the change of y are <= tol, or max_iter
+ *   sweeps (then NPGA_ERR_NOT_CONVERGED, x still returned).  x receives y (on
+ *   the simplex exactly); nu_tau (host, may be NULL) the multipliers fitted on
+ *   its support; iters (host, may be NULL) the sweeps.  Arguments as for
+ *   npga_project.
+ *
  * npga_project - x = Pi_F(v) for F above (Sec. 3.1: simplex threshold of
  *   eq. simplex-tau / simplex-proj, return face by eq. projF-dualpath).
  *   v, mu device float64 (n); x device float64 (n) output; nu_tau (host,
@@ -259,6 +287,9 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  * ------------------------------------------------------------------------- */
 int npga_project(const double *v, const double *mu, int64_t n, double r, double *x,
                  double *nu_tau, void *ws, size_t ws_bytes, hipStream_t stream);
+int npga_project_dykstra(const double *v, const double *mu, int64_t n, double r, int32_t max_iter,
+                         double tol, double *x, double *nu_tau, int32_t *iters, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
 int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out,
                   void *ws, size_t ws_bytes, hipStream_t stream);
 int npga_spectral_norm_sq(const npga_factor *f, int32_t iters, uint64_t seed, int32_t method,

@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     gradient,
     lib_path,
     project,
+    project_dykstra,
     sketch_str,
     sketch_str_ex,
     philox_sketch,

@@ -44,7 +44,9 @@ class _Options(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("refine_max_iter", ctypes.c_int32),
                 ("momentum", ctypes.c_int32), ("step_estimator", ctypes.c_int32),
-                ("batch_config", ctypes.c_int32), ("alpha", ctypes.c_double)]
+                ("batch_config", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("projection", ctypes.c_int32), ("dykstra_iters", ctypes.c_int32),
+                ("backtrack_rho", ctypes.c_double)]
 
 
 class _StrOptions(ctypes.Structure):
@@ -73,7 +75,8 @@ class _Result(ctypes.Structure):
                 ("lipschitz", ctypes.c_double), ("time_ms", ctypes.c_double),
                 ("time_to_tol_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweep_samples", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("dykstra_used", ctypes.c_int32), ("backtracks", ctypes.c_int32),
+                ("reserved3", ctypes.c_int32)]
 
 
 def _load():
@@ -92,6 +95,7 @@ def _load():
         "npga_solve": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, ctypes.POINTER(_Options), vp,
                                       ctypes.POINTER(_Result), vp, sz, vp]),
         "npga_project": (ctypes.c_int, [vp, vp, i64, dbl, vp, vp, vp, sz, vp]),
+        "npga_project_dykstra": (ctypes.c_int, [vp, vp, i64, dbl, i32, dbl, vp, vp, vp, vp, sz, vp]),
         "npga_gradient": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp, sz, vp]),
         "npga_spectral_norm_sq": (ctypes.c_int, [ctypes.POINTER(_Factor), i32, u64, i32, vp, vp, vp, sz, vp]),
         "npga_syrk": (ctypes.c_int, [vp, i64, i64, i64, vp, i64, vp]),
@@ -155,6 +159,9 @@ class Options:
     momentum: str = "fista"   # "fista" (Algorithm 1) or "constant" (strongly convex, gamma > 0)
     step_estimator: str = "lanczos"   # or "power" (the paper's Remark)
     alpha: float = 0.0   # > 0: the caller's fixed step (no estimate)
+    projection: str = "exact"   # or "dykstra" (alternating projections only)
+    dykstra_iters: int = 5000
+    backtrack_rho: float = 0.0   # in (0, 1): adaptive backtracking from the trial step
 
     def _c(self):
         o = _Options()
@@ -168,6 +175,9 @@ class Options:
         o.momentum = {"fista": 0, "constant": 1}[self.momentum]
         o.step_estimator = {"lanczos": 0, "power": 1}[self.step_estimator]
         o.alpha = self.alpha
+        o.projection = {"exact": 0, "dykstra": 1}[self.projection]
+        o.dykstra_iters = self.dykstra_iters
+        o.backtrack_rho = self.backtrack_rho
         return o
 
 
@@ -421,6 +431,23 @@ def project(v, mu, r):
     _check(_lib.npga_project(_ptr(v), _ptr(mu), n, float(r), _ptr(x), nt, _ptr(ws), ws.numel(),
                              _stream()), "npga_project")
     return x, nt[0], nt[1]
+
+
+def project_dykstra(v, mu, r, max_iter=5000, tol=1e-14):
+    """Pi_F(v) by Dykstra's alternating projections (the Sec. 3.1 fallback).
+    Returns (x, nu, tau, sweeps, converged)."""
+    v = v.to(torch.float64).contiguous()
+    mu = mu.to(torch.float64).contiguous()
+    n = v.numel()
+    x = torch.empty_like(v)
+    ws = _workspace(_lib.npga_solve_workspace_size(n, 1, None), v.device)
+    nt = (ctypes.c_double * 2)()
+    it = ctypes.c_int32(0)
+    code = _lib.npga_project_dykstra(_ptr(v), _ptr(mu), n, float(r), int(max_iter), float(tol), _ptr(x), nt,
+                                     ctypes.byref(it), _ptr(ws), ws.numel(), _stream())
+    if code not in (NPGA_OK, 3):
+        raise NpgaError(code, "npga_project_dykstra")
+    return x, nt[0], nt[1], it.value, code == NPGA_OK
 
 
 def gradient(L_TxN, x, gamma=0.0):

@@ -99,6 +99,7 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
     l.off_planes = 0;
   }
   l.off_vecs = take(sizeof(double) * npad * 4);
+  l.off_bt = take(sizeof(double) * npad * 2);  // backtracking: y and grad f(y) of the pending trial
   l.off_xa = take(sizeof(double) * npad);
   l.off_ga = take(sizeof(double) * npad);
   l.off_ua = take(sizeof(double) * (size_t)cols);
@@ -123,7 +124,9 @@ bool options_valid(const npga_options &o) {
          (o.path == NPGA_PATH_AUTO || o.path == NPGA_PATH_GEMV || o.path == NPGA_PATH_SYRK) &&
          is_fin(o.refine_tol) && o.refine_tol > 0 && o.refine_max_iter >= 0 && o.batch_config >= -1 &&
          o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1) &&
-         (o.step_estimator == 0 || o.step_estimator == 1) && is_fin(o.alpha) && o.alpha >= 0.0;
+         (o.step_estimator == 0 || o.step_estimator == 1) && is_fin(o.alpha) && o.alpha >= 0.0 &&
+         (o.projection == 0 || o.projection == 1) && o.dykstra_iters >= 1 && is_fin(o.backtrack_rho) &&
+         o.backtrack_rho >= 0.0 && o.backtrack_rho < 1.0;
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -171,6 +174,8 @@ Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
   c.lds = (f->n + 3) / 4 * 4;
   c.sigma = (path == NPGA_PATH_SYRK) ? reinterpret_cast<float *>(base + l.off_sigma) : nullptr;
   c.planes = (path == NPGA_PATH_SYRK) ? reinterpret_cast<uint16_t *>(base + l.off_planes) : nullptr;
+  a.ybt = reinterpret_cast<double *>(base + l.off_bt);
+  a.gybt = a.ybt + l.ldp;
   return c;
 }
 
@@ -190,6 +195,8 @@ DevState initial_state(const npga_factor *f, double r, const npga_options &o) {
   s.residual = INFINITY;
   s.stop_residual = INFINITY;
   s.const_momentum = o.momentum == 1 ? 1 : 0;
+  s.dykstra_iters = o.dykstra_iters;
+  s.bt_rho = o.backtrack_rho;
   return s;
 }
 
@@ -351,6 +358,9 @@ void npga_default_options(npga_options *o) {
   o->momentum = 0;
   o->step_estimator = 0;
   o->alpha = 0.0;
+  o->projection = 0;
+  o->dykstra_iters = 5000;
+  o->backtrack_rho = 0.0;
 }
 
 size_t npga_struct_size(int32_t which) {
@@ -388,8 +398,8 @@ size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *op
   return npga::solve_layout(n, cols, path).total;
 }
 
-int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x, npga_result *res,
-               void *ws, size_t ws_bytes, hipStream_t stream) {
+static int solve_once(const npga_factor *f, double r, const npga_options *opt, float *x, npga_result *res,
+                      void *ws, size_t ws_bytes, hipStream_t stream) {
   const auto t0 = Clock::now();
   npga_options o;
   npga_default_options(&o);
@@ -403,6 +413,8 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
   Carved c = carve(f, lay, ws, path);
+  c.a.dykstra = o.projection == 1 ? 1 : 0;
+  c.a.backtrack = o.backtrack_rho > 0.0 ? 1 : 0;
   const int slots = lay.slots;
 
   hipEvent_t ev0, evs[2], ev_setup;
@@ -453,7 +465,8 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
 
   int done = 0;
   double tol_ms = 0.0;
-  const int64_t main_chunks = (int64_t)o.max_iter / o.check_every + 4;
+  // refused backtracking trials take launches without advancing the iteration
+  const int64_t main_chunks = ((int64_t)o.max_iter + (c.a.backtrack ? 4096 : 0)) / o.check_every + 4;
   int e = run_phase(c, path, slots, o.check_every, main_chunks, stream, pin, evs, ev0, &done, &tol_ms, &tm);
   if (e) return e;
   const int main_done = done;
@@ -549,8 +562,25 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
     res->setup_ms = setup_ms;
     res->sweep_ms = tm.samples ? tm.total_ms / tm.samples : 0.0;
     res->sweep_samples = tm.samples;
+    res->dykstra_used = o.projection == 1 ? 1 : 0;
+    res->backtracks = after_main.bt_rejections;
   }
   return status;
+}
+
+// Algorithm 1 with the exact dual-search projection; should that search fail
+// to bracket the return multiplier (NPGA_ERR_BRACKET), the solve is run
+// again with Dykstra's alternating projections, the safeguarded fallback of
+// Sec. 3.1 (res->dykstra_used = 1).
+int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x, npga_result *res,
+               void *ws, size_t ws_bytes, hipStream_t stream) {
+  npga_options o;
+  npga_default_options(&o);
+  if (opt) o = *opt;
+  const int e = solve_once(f, r, &o, x, res, ws, ws_bytes, stream);
+  if (e != NPGA_ERR_BRACKET || o.projection == 1) return e;
+  o.projection = 1;
+  return solve_once(f, r, &o, x, res, ws, ws_bytes, stream);
 }
 
 int npga_project(const double *v, const double *mu, int64_t n, double r, double *x, double *nu_tau,
@@ -585,6 +615,41 @@ int npga_project(const double *v, const double *mu, int64_t n, double r, double 
   }
   if (pin[3].proj_flags & 2) return NPGA_ERR_BRACKET;
   return NPGA_OK;
+}
+
+int npga_project_dykstra(const double *v, const double *mu, int64_t n, double r, int32_t max_iter, double tol,
+                         double *x, double *nu_tau, int32_t *iters, void *ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  if (!v || !mu || !x || n < 1 || n > NPGA_MAX_N || !is_fin(r) || max_iter < 1 || !is_fin(tol) || tol < 0)
+    return NPGA_ERR_INVALID;
+  npga_options o;
+  npga_default_options(&o);
+  const SolveLayout lay = npga::solve_layout(n, 1, NPGA_PATH_GEMV);
+  if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
+  DevState *pin = pinned_status();
+  if (!pin) return NPGA_ERR_HIP;
+  DevState *st = reinterpret_cast<DevState *>(static_cast<char *>(ws) + lay.off_state);
+  npga_factor f{n, 1, (n + 3) / 4 * 4, ws, mu, 0.0, NPGA_F32, 0};
+  pin[2] = initial_state(&f, r, o);
+  HIPCHK(hipMemcpyAsync(st, &pin[2], sizeof(DevState), hipMemcpyHostToDevice, stream));
+  SolveArgs a{};
+  a.mu = mu;
+  a.n = n;
+  a.st = st;
+  LAUNCHCHK(npga::launch_prepare(a, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pin[3].n_nonfinite > 0) return NPGA_ERR_NUMERIC;
+  if (r > pin[3].mu_max) return NPGA_ERR_INFEASIBLE;
+  LAUNCHCHK(npga::launch_project_dykstra(v, mu, n, x, st, max_iter, tol, lay.slots, stream));
+  HIPCHK(hipMemcpyAsync(&pin[3], st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (nu_tau) {
+    nu_tau[0] = pin[3].nu;
+    nu_tau[1] = pin[3].tau;
+  }
+  if (iters) *iters = pin[3].iter;
+  return (pin[3].proj_flags & 1) ? NPGA_ERR_NOT_CONVERGED : NPGA_OK;
 }
 
 int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out, void *ws,
@@ -1148,6 +1213,8 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   npga_options o;
   npga_default_options(&o);
   if (opt) o = *opt;
+  // per-target steps (backtracking) and Dykstra's projections are single-solve options
+  if (o.backtrack_rho > 0.0 || o.projection != 0) return NPGA_ERR_INVALID;
   if (!factor_valid(f) || !r_targets || !X || m < 1 || m > NPGA_MAX_BATCH || ldx < f->n ||
       !options_valid(o) || !aligned(X, 4))
     return NPGA_ERR_INVALID;

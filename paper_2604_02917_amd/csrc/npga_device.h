@@ -181,7 +181,7 @@ struct PassSums {
 struct ProjResult {
   double nu, tau;
   int32_t passes;
-  int32_t flags;  // bit 0: pass cap hit, bit 1: bracket failure
+  int32_t flags;  // bit 0: pass or sweep cap hit, bit 1: bracket failure, bit 2: Dykstra used
 };
 
 template <int E>
@@ -256,12 +256,114 @@ __device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const
   return PassSums{a[0], a[1], a[2], a[3], a[4]};
 }
 
+// Dykstra's alternating projections onto Delta and H = {mu^T x >= r}, the
+// safeguarded fallback of Sec. 3.1 (Bauschke and Borwein, 1996): with x_0 = v
+// and p_0 = q_0 = 0,
+//   y_k = Pi_Delta(x_k + p_k),  p_{k+1} = x_k + p_k - y_k,
+//   x_{k+1} = Pi_H(y_k + q_k),  q_{k+1} = y_k + q_k - x_{k+1},
+// both converging to Pi_{Delta cap H}(v).  Stops when ||x_{k+1} - y_k||_2 and
+// ||y_k - y_{k-1}||_2 are <= tol (after at least two sweeps) or after
+// max_iter; v receives y (on the simplex exactly).  Returns the sweeps.
+// Multipliers of the result (the dual search's nu and tau, for warm starts
+// and the stopping test's KKT report) are fitted on the support S of y from
+// y_i = v_i + nu mu_i - tau (the original v is x + p + q at every sweep).
 template <int E>
+__device__ int dykstra_F(double (&v)[E], const double (&mu)[E], double r, int max_iter, double tol,
+                         BlockReducer<5> &red, int &flags, double &nu_out, double &tau_out) {
+  double a0[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) a0[0] = fma(mu[j], mu[j], a0[0]);  // invalid entries carry mu = 0
+  red.sum(a0);
+  const double mu2 = a0[0];
+  bool valid[E];
+  double pw[E], q[E], y[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    valid[j] = v[j] > -1.0e299;
+    pw[j] = 0.0;
+    q[j] = 0.0;
+    y[j] = 0.0;
+  }
+  double tau = -1.0e300;
+  int k = 0;
+  for (k = 1; k <= max_iter; ++k) {
+    // w = x + p (kept in pw), y = Pi_Delta(w), p = w - y
+#pragma unroll
+    for (int j = 0; j < E; ++j) pw[j] = valid[j] ? v[j] + pw[j] : -1.0e300;
+    PassSums s;
+    int passes = 0;
+    tau = simplex_tau<E>(pw, mu, 0.0, tau, s, red, passes, flags);
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const double yn = valid[j] ? fmax(pw[j] - tau, 0.0) : 0.0;
+      acc[1] = fma(yn - y[j], yn - y[j], acc[1]);
+      pw[j] = valid[j] ? pw[j] - yn : 0.0;
+      y[j] = yn;
+      acc[0] = fma(mu[j], yn + q[j], acc[0]);
+    }
+    red.sum(acc);
+    // x = Pi_H(y + q), q = y + q - x
+    const double shift = (acc[0] < r && mu2 > 0.0) ? (r - acc[0]) / mu2 : 0.0;
+    double acc2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const double z = y[j] + q[j];
+      const double xn = valid[j] ? fma(shift, mu[j], z) : -1.0e300;
+      if (valid[j]) {
+        q[j] = z - xn;
+        acc2[0] = fma(xn - y[j], xn - y[j], acc2[0]);
+      }
+      v[j] = xn;
+    }
+    red.sum(acc2);
+    if (k > 1 && sqrt(acc2[0]) <= tol && sqrt(acc[1]) <= tol) break;
+  }
+  if (k > max_iter) {
+    k = max_iter;
+    flags |= 1;
+  }
+  // d = y - v_orig on S; sums for the 2 x 2 fit of (nu, tau)
+  double f[5] = {0, 0, 0, 0, 0};  // |S|, sum d, sum mu d, sum mu, sum mu^2
+  double g[5] = {0, 0, 0, 0, 0};  // mu^T y
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (valid[j] && y[j] > 0.0) {
+      const double d = y[j] - (v[j] + pw[j] + q[j]);
+      f[0] += 1.0;
+      f[1] += d;
+      f[2] = fma(mu[j], d, f[2]);
+      f[3] += mu[j];
+      f[4] = fma(mu[j], mu[j], f[4]);
+    }
+    g[0] = fma(mu[j], y[j], g[0]);
+  }
+  red.sum(f);
+  red.sum(g);
+  double nu = 0.0;
+  const double den = f[4] - f[3] * (f[3] / fmax(f[0], 1.0));
+  if (g[0] <= r * (1.0 + 1e-12) && den > 0.0) nu = fmax((f[2] - f[3] * (f[1] / fmax(f[0], 1.0))) / den, 0.0);
+  nu_out = nu;
+  tau_out = (nu * f[3] - f[1]) / fmax(f[0], 1.0);
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = valid[j] ? y[j] : -1.0e300;
+  return k;
+}
+
+// DYK: Dykstra's alternating projections (dyk_iters sweeps, bit 2 of the
+// flags) instead of the dual search; a separate instantiation, so the dual
+// search's kernels carry none of its registers.
+template <int E, bool DYK = false>
 __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r, double tolphi,
-                                double nu_warm, double tau_warm, BlockReducer<5> &red) {
+                                double nu_warm, double tau_warm, BlockReducer<5> &red, int dyk_iters = 0) {
   ProjResult out{0.0, 0.0, 0, 0};
   int passes = 0, flags = 0;
   PassSums s;
+  if constexpr (DYK) {
+    out.passes = dykstra_F<E>(v, mu, r, dyk_iters, 1e-14, red, flags, out.nu, out.tau);
+    out.flags = flags | 4;
+    return out;
+  }
   // Fast path from a warm start with the return constraint binding: joint
   // Newton on (tau, nu).  On a support S the two conditions
   //   |S| tau - nu sum_S mu = sum_S v - 1,  tau sum_S mu - nu sum_S mu^2 = sum_S mu v - r

@@ -89,6 +89,12 @@ struct alignas(256) DevState {
   int32_t lz_m;
   double lz_theta;                 // largest Ritz value of T_m
   double lz_tol;                   // stop when the Ritz residual is below lz_tol theta
+  int32_t dykstra_iters;           // sweep budget of Dykstra's projections (when the tails run them)
+  // adaptive backtracking (Sec. 3.1)
+  double bt_rho;                   // step shrink factor
+  int32_t bt_pending;              // 1: x^k is a trial point of the step from y^{k-1}
+  int32_t bt_rejections;           // trial steps refused so far
+  int32_t bt_consec;               // refusals of the current trial
   double lz_alpha[kLanczosMax];
   double lz_beta[kLanczosMax];
   // adjoint results
@@ -127,6 +133,10 @@ struct SolveArgs {
   int64_t ldp;         // leading dimension of partials (>= 256 * slots)
   int32_t sweep_grid;  // number of workgroups of the sweep launch
   int32_t mode;        // TailMode
+  int32_t dykstra;     // 1: the tails project by Dykstra's method (their DYK instantiation)
+  int32_t backtrack;   // 1: adaptive backtracking (the tails' BT instantiation)
+  double *ybt;         // backtracking: y^k of the pending trial (n)
+  double *gybt;        // backtracking: grad f(y^k) (n)
   DevState *st;
   // refinement anchor (all null outside the refinement phase): the sweep
   // runs on d = x - xa and adds the float64 anchor terms
@@ -188,7 +198,7 @@ int batch_default_config(int64_t n, int64_t cols, int32_t m);
 // Workspace carving for a solve.
 struct SolveLayout {
   size_t off_state, off_status_dev, off_xs, off_x0, off_x1, off_g0, off_g1, off_part, off_usq,
-      off_sigma, off_planes, off_vecs, off_xa, off_ga, off_ua, total;
+      off_sigma, off_planes, off_vecs, off_bt, off_xa, off_ga, off_ua, total;
   int32_t slots;
   int32_t sweep_grid;
   int64_t ldp;
@@ -209,6 +219,8 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s);
 int launch_project_init(const SolveArgs &a, int slots, int use_x0, hipStream_t s);
 int launch_project_only(const double *v, const double *mu, int64_t n, double *x, DevState *st,
                         int slots, hipStream_t s);
+int launch_project_dykstra(const double *v, const double *mu, int64_t n, double *x, DevState *st, int max_iter,
+                           double tol, int slots, hipStream_t s);
 int launch_finalize(const SolveArgs &a, float *x_out, int slots, hipStream_t s);
 int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter, int32_t restart,
                  hipStream_t s);

@@ -455,10 +455,23 @@ __global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
     tail_grad<E>(a, usq, redbuf);
 }
 
+// The NPGA tail with Dykstra's projections (options.projection = 1) and/or
+// adaptive backtracking (options.backtrack_rho > 0).
+template <int E, bool DYK, bool BT>
+__global__ __launch_bounds__(256) void k_tail_var(SolveArgs a, int covariance) {
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  __shared__ double redbuf[64];
+  tail_npga<E, DYK, BT>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+}
+
 template <int E>
 __global__ __launch_bounds__(256) void k_project_init(SolveArgs a) {
   __shared__ double redbuf[64];
-  project_init_body<E>(a, redbuf);
+  if (a.dykstra)
+    project_init_body<E, true>(a, redbuf);
+  else
+    project_init_body<E>(a, redbuf);
 }
 
 template <int E>
@@ -492,6 +505,38 @@ __global__ __launch_bounds__(256) void k_project_only(const double *vin, const d
     st->tau = pr.tau;
     st->proj_flags = pr.flags;
     st->iter = pr.passes;
+  }
+}
+
+// Pi_F(v) by Dykstra's alternating projections alone (the fallback of the
+// dual search), for checking it on its own.
+template <int E>
+__global__ __launch_bounds__(256) void k_project_dykstra(const double *vin, const double *muin, int64_t n,
+                                                         double *xout, DevState *st, int max_iter,
+                                                         double tol) {
+  __shared__ double redbuf[64];
+  BlockReducer<5> red{redbuf, 0};
+  const int tid = threadIdx.x;
+  double mu[E], v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    mu[j] = (i < n) ? muin[i] : 0.0;
+    v[j] = (i < n) ? vin[i] : -1.0e300;
+  }
+  int flags = 0;
+  double nu = 0.0, tau = 0.0;
+  const int k = dykstra_F<E>(v, mu, st->r, max_iter, tol, red, flags, nu, tau);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + 256 * j;
+    if (i < n) xout[i] = v[j];
+  }
+  if (tid == 0) {
+    st->nu = nu;
+    st->tau = tau;
+    st->proj_flags = flags;
+    st->iter = k;
   }
 }
 
@@ -593,6 +638,24 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
 }
 
 int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
+  if ((a.dykstra || a.backtrack) && a.mode == kTailNpga) {
+    // the NPGA tail with Dykstra's projections and/or backtracking: own
+    // instantiations, so k_tail carries none of their registers
+    if (a.dykstra && a.backtrack) {
+#define CALL(E) hipLaunchKernelGGL((k_tail_var<E, true, true>), dim3(1), dim3(256), 0, s, a, covariance)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+    } else if (a.dykstra) {
+#define CALL(E) hipLaunchKernelGGL((k_tail_var<E, true, false>), dim3(1), dim3(256), 0, s, a, covariance)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+    } else {
+#define CALL(E) hipLaunchKernelGGL((k_tail_var<E, false, true>), dim3(1), dim3(256), 0, s, a, covariance)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+    }
+    return (int)hipGetLastError();
+  }
 #define CALL(E) hipLaunchKernelGGL(k_tail<E>, dim3(1), dim3(256), 0, s, a, covariance)
   NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
@@ -616,6 +679,14 @@ int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s) {
 int launch_project_only(const double *v, const double *mu, int64_t n, double *x, DevState *st,
                         int slots, hipStream_t s) {
 #define CALL(E) hipLaunchKernelGGL(k_project_only<E>, dim3(1), dim3(256), 0, s, v, mu, n, x, st)
+  NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  return (int)hipGetLastError();
+}
+
+int launch_project_dykstra(const double *v, const double *mu, int64_t n, double *x, DevState *st, int max_iter,
+                           double tol, int slots, hipStream_t s) {
+#define CALL(E) hipLaunchKernelGGL(k_project_dykstra<E>, dim3(1), dim3(256), 0, s, v, mu, n, x, st, max_iter, tol)
   NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
   return (int)hipGetLastError();

@@ -12,14 +12,22 @@
 
 namespace npga {
 
-template <int E>
+// DYK: step projections by Dykstra's method.  BT: adaptive backtracking
+// (Sec. 3.1): each new iterate is a trial point; the next launch, which has
+// its gradient, accepts it if f(x) <= f(y) + <grad f(y), x - y> +
+// ||x - y||^2/(2 alpha), evaluated in the exact form of a quadratic f,
+// (x - y)^T Q (x - y) <= ||x - y||^2/(2 alpha) with Q (x - y) = (grad f(x) -
+// grad f(y))/2, plus an allowance for the float32 products of the sweep;
+// otherwise alpha <- rho alpha and the trial is recomputed from the stored
+// y and grad f(y).
+template <int E, bool DYK = false, bool BT = false>
 __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) {
   DevState *st = a.st;
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   const int k = st->iter;
   const int cur = k & 1;
-  const double *xk_p = cur ? a.xbuf1 : a.xbuf0;
+  double *xk_p = cur ? a.xbuf1 : a.xbuf0;
   double *xn_p = cur ? a.xbuf0 : a.xbuf1;  // holds x_{k-1}; receives x_{k+1}
   const double *gk_p = cur ? a.gbuf1 : a.gbuf0;
   const double *gp_p = cur ? a.gbuf0 : a.gbuf1;
@@ -39,11 +47,62 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     xp[j] = ok ? xn_p[i] : 0.0;
     gp[j] = ok ? gp_p[i] : 0.0;
   }
+  if constexpr (BT) {
+    if (st->bt_pending) {
+      double acc[5] = {0, 0, 0, 0, 0};  // d^T Q d, ||d||^2, float32 allowance
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t i = tid + 256 * j;
+        if (i < n) {
+          const double yb = a.ybt[i], gyb = a.gybt[i];
+          const double d = xk[j] - yb;
+          acc[0] = fma(d, 0.5 * (gk[j] - gyb), acc[0]);
+          acc[1] = fma(d, d, acc[1]);
+          acc[2] = fma(fabs(d), fabs(gk[j]) + fabs(gyb), acc[2]);
+        }
+      }
+      red.sum(acc);
+      const bool accept = !(acc[1] > 0.0) || acc[0] <= acc[1] / (2.0 * alpha) + 1e-6 * acc[2] ||
+                          st->bt_consec >= 40;
+      if (!accept) {
+        // alpha <- rho alpha; a new trial x^k = Pi_F(y - alpha grad f(y))
+        const double an = alpha * st->bt_rho;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int64_t i = tid + 256 * j;
+          v[j] = (i < n) ? fma(-an, a.gybt[i], a.ybt[i]) : -1.0e300;
+        }
+        const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int64_t i = tid + 256 * j;
+          if (i < n) {
+            xk_p[i] = v[j];
+            a.xs[i] = (float)(a.xa ? v[j] - a.xa[i] : v[j]);
+          }
+        }
+        if (tid == 0) {
+          st->alpha = an;
+          st->bt_rejections += 1;
+          st->bt_consec += 1;
+          st->nu = pr.nu;
+          st->tau = pr.tau;
+          st->proj_flags |= pr.flags;
+          if (pr.flags & 2) st->done = kBracket;
+        }
+        return;
+      }
+      if (tid == 0) {
+        st->bt_pending = 0;
+        st->bt_consec = 0;
+      }
+    }
+  }
 
   if (k % st->check_every == 0) {
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = (tid + 256 * j < n) ? fma(-alpha, gk[j], xk[j]) : -1.0e300;
-    const ProjResult pr = project_F<E>(v, mu, r, tolphi, st->nu_c, st->tau_c, red);
+    const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu_c, st->tau_c, red, st->dykstra_iters);
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -85,12 +144,19 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   const double beta = st->beta;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const bool ok = tid + 256 * j < n;
+    const int64_t i = tid + 256 * j;
+    const bool ok = i < n;
     const double y = fma(beta, xk[j] - xp[j], xk[j]);
     const double gy = fma(beta, gk[j] - gp[j], gk[j]);
     v[j] = ok ? fma(-alpha, gy, y) : -1.0e300;
+    if constexpr (BT) {
+      if (ok) {
+        a.ybt[i] = y;
+        a.gybt[i] = gy;
+      }
+    }
   }
-  const ProjResult pr = project_F<E>(v, mu, r, tolphi, st->nu, st->tau, red);
+  const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
   double t = st->t;
   int restarted = 0;
   if (st->restart) {
@@ -125,6 +191,7 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     st->proj_flags |= pr.flags;
     st->n_restarts += restarted;
     if (pr.flags & 2) st->done = kBracket;
+    if constexpr (BT) st->bt_pending = 1;
   }
 }
 
@@ -657,7 +724,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 }
 
 // x0 = Pi_F(xbuf0) (Algorithm 1 requires x^0 in F); initialises the iteration.
-template <int E>
+template <int E, bool DYK = false>
 __device__ void project_init_body(const SolveArgs &a, double *redbuf) {
   DevState *st = a.st;
   BlockReducer<5> red{redbuf, 0};
@@ -669,7 +736,7 @@ __device__ void project_init_body(const SolveArgs &a, double *redbuf) {
     mu[j] = (i < a.n) ? a.mu[i] : 0.0;
     v[j] = (i < a.n) ? a.xbuf0[i] : -1.0e300;
   }
-  const ProjResult pr = project_F<E>(v, mu, st->r, st->tolphi, 0.0, -1.0e300, red);
+  const ProjResult pr = project_F<E, DYK>(v, mu, st->r, st->tolphi, 0.0, -1.0e300, red, st->dykstra_iters);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + 256 * j;

@@ -125,6 +125,18 @@ def test_invalid_arguments_rejected_before_launch():
     o.alpha = float("inf")
     assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
                                   null, 0, null) == 1
+    # backtracking and Dykstra's projections are single-solve options
+    o.alpha = 0.0
+    o.backtrack_rho = 0.5
+    assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
+                                  null, 0, null) == 1
+    o.backtrack_rho = 1.0                                      # out of (0, 1)
+    assert lib.npga_solve(ctypes.byref(f), 0.0, ctypes.byref(o), ctypes.c_void_p(16), ctypes.byref(res), null, 0,
+                          null) == 1
+    o.backtrack_rho = 0.0
+    o.projection = 1
+    assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
+                                  null, 0, null) == 1
 
 
 def test_build_script_runs_without_importing_the_package():
