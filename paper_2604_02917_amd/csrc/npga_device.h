@@ -263,7 +263,7 @@ __device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const
 //   x_{k+1} = Pi_H(y_k + q_k),  q_{k+1} = y_k + q_k - x_{k+1},
 // both converging to Pi_{Delta cap H}(v).  Stops when ||x_{k+1} - y_k||_2 and
 // ||y_k - y_{k-1}||_2 are <= tol (after at least two sweeps) or after
-// max_iter; v receives y (on the simplex exactly).  Returns the sweeps.
+// max_iter; v receives y (on the simplex exactly; 0 past n).  Returns the sweeps.
 // Multipliers of the result (the dual search's nu and tau, for warm starts
 // and the stopping test's KKT report) are fitted on the support S of y from
 // y_i = v_i + nu mu_i - tau (the original v is x + p + q at every sweep).
@@ -345,8 +345,9 @@ __device__ int dykstra_F(double (&v)[E], const double (&mu)[E], double r, int ma
   if (g[0] <= r * (1.0 + 1e-12) && den > 0.0) nu = fmax((f[2] - f[3] * (f[1] / fmax(f[0], 1.0))) / den, 0.0);
   nu_out = nu;
   tau_out = (nu * f[3] - f[1]) / fmax(f[0], 1.0);
+  // entries past n leave as 0, like the dual search's result
 #pragma unroll
-  for (int j = 0; j < E; ++j) v[j] = valid[j] ? y[j] : -1.0e300;
+  for (int j = 0; j < E; ++j) v[j] = valid[j] ? y[j] : 0.0;
   return k;
 }
 
