@@ -27,8 +27,11 @@
  *     caller's workspace `ws` (256-byte aligned) of at least the size the
  *     matching *_workspace_size function returns.  The library keeps no
  *     state between calls except a small pinned host status buffer per
- *     call in flight.  Calls on different streams with distinct
- *     workspaces may run concurrently; calls sharing a workspace must not.
+ *     host thread (allocated on first use, kept until the process ends);
+ *     every entry point that uses it synchronises `stream` before
+ *     returning.  Calls from different host threads, on different streams
+ *     with distinct workspaces, may run concurrently; calls sharing a
+ *     workspace must not.
  *   - Return value: an npga_status code.  No C++ exception crosses the ABI.
  *     Arguments are validated before anything is enqueued; on
  *     NPGA_ERR_INVALID nothing has been launched.
@@ -262,7 +265,8 @@ int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x
  * npga_gradient - g = 2 L_eff (L_eff^T x) + 2 gamma x and
  *   f = ||L_eff^T x||^2 + gamma ||x||^2 (eq. npga-unified-grad) by the
  *   fused single-pass sweep.  x device float32 (n), g device float64 (n),
- *   f_out (host, may be NULL).  ws as for npga_solve.
+ *   f_out (host, may be NULL).  ws as for npga_solve.  Synchronises
+ *   `stream` before returning.
  *
  * npga_spectral_norm_sq - ||L_eff||_2^2 estimated from a seeded Gaussian
  *   start (Sec. 3.1 Remark): method 1 = `iters` power-method steps (the last

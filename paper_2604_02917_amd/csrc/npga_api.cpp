@@ -249,6 +249,25 @@ int estimate_step(const Carved &c, int path, int slots, const npga_options &o, h
 // writeback and invalidate) that a default event performs when recorded.
 hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
 
+// Owns up to N events; whatever was created is destroyed on every return
+// path, including a failure part-way through creating the set.
+template <int N>
+struct EventSet {
+  hipEvent_t ev[N];
+  int made = 0;
+  // one more event into *out: timestamp-only when `timing`, else a default
+  // event (its completion also orders the host after earlier copies)
+  hipError_t make(hipEvent_t *out, bool timing = true) {
+    if (made == N) return hipErrorInvalidValue;
+    const hipError_t e = timing ? timing_event(&ev[made]) : hipEventCreate(&ev[made]);
+    if (e == hipSuccess) *out = ev[made++];
+    return e;
+  }
+  ~EventSet() {
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
 int map_done(int done) {
   switch (done) {
     case npga::kConverged: return NPGA_OK;
@@ -418,24 +437,16 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
   const int slots = lay.slots;
 
   hipEvent_t ev0, evs[2], ev_setup;
-  HIPCHK(timing_event(&ev0));
-  HIPCHK(hipEventCreate(&evs[0]));
-  HIPCHK(hipEventCreate(&evs[1]));
-  HIPCHK(timing_event(&ev_setup));
-  struct EvGuard {
-    hipEvent_t *e;
-    int k;
-    ~EvGuard() {
-      for (int i = 0; i < k; ++i) (void)hipEventDestroy(e[i]);
-    }
-  };
   SweepTimer tm;
-  HIPCHK(timing_event(&tm.a[0]));
-  HIPCHK(timing_event(&tm.a[1]));
-  HIPCHK(timing_event(&tm.b[0]));
-  HIPCHK(timing_event(&tm.b[1]));
-  hipEvent_t all[8] = {ev0, evs[0], evs[1], ev_setup, tm.a[0], tm.a[1], tm.b[0], tm.b[1]};
-  EvGuard guard{all, 8};
+  EventSet<8> events;
+  HIPCHK(events.make(&ev0));
+  HIPCHK(events.make(&evs[0], false));
+  HIPCHK(events.make(&evs[1], false));
+  HIPCHK(events.make(&ev_setup));
+  for (int i = 0; i < 2; ++i) {
+    HIPCHK(events.make(&tm.a[i]));
+    HIPCHK(events.make(&tm.b[i]));
+  }
 
   HIPCHK(hipEventRecord(ev0, stream));
   // state, mu statistics and the feasibility check (the only sync before the loop)
@@ -670,11 +681,11 @@ int npga_gradient(const npga_factor *f, const float *x, double *g, double *f_out
   LAUNCHCHK(npga::launch_set_vector(c.a.xbuf0, x, nullptr, f->n, 0.0, c.a.xs, stream));
   LAUNCHCHK(npga::launch_sweep(c.a, lay.slots, stream));
   LAUNCHCHK(npga::launch_reduce_tail(c.a, lay.slots, stream));
-  if (f_out) {
-    HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    *f_out = pin[3].objective;
-  }
+  // always synchronise: the upload above reads the per-thread pinned buffer,
+  // which the next call from this thread overwrites
+  HIPCHK(hipMemcpyAsync(&pin[3], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (f_out) *f_out = pin[3].objective;
   return NPGA_OK;
 }
 
@@ -1234,21 +1245,16 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   int32_t *dev_status = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + lay.off_status);
 
   hipEvent_t ev0, evs[2], ev_setup;
-  HIPCHK(timing_event(&ev0));
-  HIPCHK(hipEventCreate(&evs[0]));
-  HIPCHK(hipEventCreate(&evs[1]));
-  HIPCHK(timing_event(&ev_setup));
   SweepTimer tm;
-  HIPCHK(timing_event(&tm.a[0]));
-  HIPCHK(timing_event(&tm.a[1]));
-  HIPCHK(timing_event(&tm.b[0]));
-  HIPCHK(timing_event(&tm.b[1]));
-  struct EvGuard {
-    hipEvent_t e[8];
-    ~EvGuard() {
-      for (auto &x : e) (void)hipEventDestroy(x);
-    }
-  } guard{{ev0, evs[0], evs[1], ev_setup, tm.a[0], tm.a[1], tm.b[0], tm.b[1]}};
+  EventSet<8> events;
+  HIPCHK(events.make(&ev0));
+  HIPCHK(events.make(&evs[0], false));
+  HIPCHK(events.make(&evs[1], false));
+  HIPCHK(events.make(&ev_setup));
+  for (int i = 0; i < 2; ++i) {
+    HIPCHK(events.make(&tm.a[i]));
+    HIPCHK(events.make(&tm.b[i]));
+  }
 
   HIPCHK(hipEventRecord(ev0, stream));
   // mu statistics and feasibility of every target (one synchronisation)
@@ -1409,15 +1415,9 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
   const BatchLayout lay = batch_layout(f->n, f->cols, m);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   hipEvent_t a, z;
-  HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&z));
-  struct G2 {
-    hipEvent_t a, z;
-    ~G2() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(z);
-    }
-  } guard{a, z};
+  EventSet<2> events;
+  HIPCHK(events.make(&a, false));
+  HIPCHK(events.make(&z, false));
   {
     const npga::BatchConfig &c0 = npga::kBatchConfigTable[0];
     npga::BatchArgs b0 = carve_batch(f, lay, ws, m, c0);
@@ -1507,15 +1507,10 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
   cg.a.mode = npga::kTailAdj;
   cg.a.ga = nullptr;
   hipEvent_t evs[2], ev0;
-  HIPCHK(timing_event(&ev0));
-  HIPCHK(hipEventCreate(&evs[0]));
-  HIPCHK(hipEventCreate(&evs[1]));
-  struct EvGuard3 {
-    hipEvent_t e[3];
-    ~EvGuard3() {
-      for (auto &x : e) (void)hipEventDestroy(x);
-    }
-  } guard{{ev0, evs[0], evs[1]}};
+  EventSet<3> events;
+  HIPCHK(events.make(&ev0));
+  HIPCHK(events.make(&evs[0], false));
+  HIPCHK(events.make(&evs[1], false));
   HIPCHK(hipEventRecord(ev0, stream));
   int cg_iters = 0, done = npga::kConverged;
   const int max_iter = 4 * (int)std::min<int64_t>(f->n, 5000) + 100;
