@@ -800,7 +800,8 @@ SketchLayout sketch_layout(int64_t n, int64_t T, int64_t k, int64_t ell, bool ne
   l.off_A = take(sizeof(double) * (size_t)k * (size_t)k);
   l.off_vec = take(sizeof(double) * (size_t)k * 8);
   l.off_Z = take(sizeof(double) * (size_t)k * (size_t)ell);
-  l.off_work = take(sizeof(double) * 5 * (size_t)l.stride * (size_t)k + (size_t)l.stride * (size_t)k);
+  l.off_work = take(std::max(sizeof(double) * 5 * (size_t)l.stride * (size_t)k + (size_t)l.stride * (size_t)k,
+                             npga::tri_scratch_bytes(k)));
   l.off_V32 = take(sizeof(float) * (size_t)k * (size_t)ell);
   l.off_frob = take(sizeof(double) * kFrobParts);
   l.off_gamma = take(sizeof(double) * 4);

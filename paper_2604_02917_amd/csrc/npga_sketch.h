@@ -20,7 +20,8 @@ struct SketchState {
   double *p;      // tau A v of the current step (k)
   double *lam;    // wanted eigenvalues, descending (ell)
   double *Z;      // eigenvectors of T, then of G (k x ell, leading dim k)
-  double *work;   // inverse-iteration factors (5 stride k doubles + stride k bytes)
+  double *work;   // tridiagonalisation scratch, then inverse-iteration factors
+                  // (5 stride k doubles + stride k bytes)
 };
 
 int launch_gemm_f32(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
@@ -28,6 +29,8 @@ int launch_gemm_f32(const float *A, int64_t lda, const float *B, int64_t ldb, fl
 int launch_gram_f64(const float *Y, int64_t ldy, int64_t n, int64_t k, double *G, hipStream_t st);
 int launch_frob(const float *Y, int64_t ldy, int64_t n, int64_t k, double *part, int nparts,
                 hipStream_t st);
+// Bytes of `work` the tridiagonalisation uses (partial sums and counters).
+size_t tri_scratch_bytes(int64_t k);
 int launch_tridiag(const SketchState &s, hipStream_t st);
 int launch_bisect(const SketchState &s, int64_t ell, hipStream_t st);
 int launch_inverse_iter(const SketchState &s, int64_t ell, int64_t stride, hipStream_t st);

@@ -285,9 +285,11 @@ __global__ __launch_bounds__(256) void k_frob_partial(const float *Y, int64_t ld
 //            reflector of x = A[i+1:, i] (LAPACK dlarfg convention):
 //            beta = -sign(x_0)||x||, tau = (beta - x_0)/beta,
 //            v = [1, x_1:/(x_0 - beta)], e_i = beta.
-// Step i, grid (k_tri_big): every column c > i of the trailing block gets
-//   the pending update from step i-1 (rows > i), is written back, and
-//   p_c = tau_i (A[i+1:, c] . v_i).
+// Step i, grid (k_tri_tiles): only the lower triangle r >= c > i of the
+//   trailing block is kept.  It gets the pending update from step i-1, is
+//   written back, and gives p = tau_i A v_i, where every stored entry adds
+//   A[r, c] v_r to p_c and, below the diagonal, A[r, c] v_c to p_r.
+//   The upper triangle is never read again.
 // --------------------------------------------------------------------------
 constexpr int kTriThreads = 1024;  // one-workgroup step: 16 wavefronts
 constexpr int kTriRows = 8;        // rows per thread (k <= 8192)
@@ -390,79 +392,106 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_small(SketchState s, int64_
   }
 }
 
-// One wavefront per pair of trailing columns (c, c + W): eight rows (512
-// entries) of both columns and of the three step vectors are loaded before
-// they are used, so each wavefront keeps many loads in flight and reads the
-// step vectors once for two columns.
-__global__ __launch_bounds__(256) void k_tri_big(SketchState s, int64_t i) {
+// k_tri_tiles: one workgroup per 64 x 64 tile (I, J), I >= J, of the
+// trailing lower triangle; lane = row of the tile, wavefront w = columns
+// 16 w .. 16 w + 15.  A tile writes its 64 column sums (for block J) and 64
+// row sums (for block I) to `work`.  k_tri_reduce: one workgroup per block
+// adds that block's partial sums in a fixed order and writes p for its
+// rows.  (A last-arriving-tile reduction inside k_tri_tiles needs a
+// device-scope fence per tile, which writes back and invalidates the L2 of
+// every XCD and costs more than the launch it saves.)
+constexpr int kTT = 64;  // tile edge
+
+__device__ __forceinline__ int64_t tri_tile_index(int64_t a, int64_t b) { return a * (a + 1) / 2 + b; }
+
+size_t tri_scratch_bytes(int64_t k) {
+  const int64_t nb = (k + kTT - 1) / kTT;
+  return sizeof(double) * 2 * (size_t)(nb * (nb + 1) / 2) * kTT;
+}
+
+__global__ __launch_bounds__(256) void k_tri_tiles(SketchState s, int64_t i, int64_t tiles_max) {
+  __shared__ double prod[kTT][kTT + 1];
+  __shared__ double rowp[4][kTT], colp[4][kTT];
+  __shared__ double cv[kTT], cvp[kTT], cwp[kTT];
   const int64_t k = s.k;
   double *A = s.A;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t W = (int64_t)gridDim.x * 4;
-  const double tau = s.tau[i];
+  double *prow = s.work;                   // tiles_max x 64 row sums
+  double *pcol = s.work + tiles_max * kTT;  // tiles_max x 64 column sums
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t J0 = (i + 1) / kTT;
+  // tile t = Ir (Ir + 1) / 2 + Jr of the block indices relative to J0
+  const int64_t t = blockIdx.x;
+  int64_t Ir = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (tri_tile_index(Ir + 1, 0) <= t) ++Ir;
+  while (tri_tile_index(Ir, 0) > t) --Ir;
+  const int64_t Jr = t - tri_tile_index(Ir, 0);
+  const int64_t r0 = (J0 + Ir) * kTT, c0 = (J0 + Jr) * kTT;
   const bool upd = i > 0;
-  const double *vcur = s.vcur, *vprev = s.vprev, *wprev = s.wprev;
-  for (int64_t c = i + 1 + (int64_t)blockIdx.x * 4 + wave; c < k; c += 2 * W) {
-    const int64_t c2 = c + W;
-    const bool two = c2 < k;  // uniform over the wavefront
-    const double wc = upd ? wprev[c] : 0.0, vc = upd ? vprev[c] : 0.0;
-    const double wc2 = (upd && two) ? wprev[c2] : 0.0, vc2 = (upd && two) ? vprev[c2] : 0.0;
-    double *col = A + c * k;
-    double *col2 = A + (two ? c2 : c) * k;
-    double dot = 0.0, dot2 = 0.0;
-    int64_t r = i + 1 + lane;
-    for (; r + 7 * 64 < k; r += 8 * 64) {
-      double a[8], a2[8], v[8];
+  if (tid < kTT) {
+    const int64_t c = c0 + tid;
+    const bool ok = c > i && c < k;
+    cv[tid] = ok ? s.vcur[c] : 0.0;
+    cvp[tid] = (ok && upd) ? s.vprev[c] : 0.0;
+    cwp[tid] = (ok && upd) ? s.wprev[c] : 0.0;
+  }
+  const int64_t r = r0 + lane;
+  const bool rok = r > i && r < k;
+  const double rv = rok ? s.vcur[r] : 0.0;
+  const double rvp = (rok && upd) ? s.vprev[r] : 0.0;
+  const double rwp = (rok && upd) ? s.wprev[r] : 0.0;
+  double a[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a[u] = col[r + 64 * u];
-        a2[u] = two ? col2[r + 64 * u] : 0.0;
-        v[u] = vcur[r + 64 * u];
-      }
-      if (upd) {
-        double pv[8], pw[8];
+  for (int j = 0; j < 16; ++j) {
+    const int64_t c = c0 + 16 * w + j;
+    const bool ok = rok && c > i && r >= c;
+    a[j] = ok ? A[r + c * k] : 0.0;
+  }
+  __syncthreads();  // cv, cvp, cwp
+  double racc = 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          pv[u] = vprev[r + 64 * u];
-          pw[u] = wprev[r + 64 * u];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          a[u] -= pv[u] * wc + pw[u] * vc;
-          col[r + 64 * u] = a[u];
-          if (two) {
-            a2[u] -= pv[u] * wc2 + pw[u] * vc2;
-            col2[r + 64 * u] = a2[u];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        dot = fma(a[u], v[u], dot);
-        dot2 = fma(a2[u], v[u], dot2);
-      }
+  for (int j = 0; j < 16; ++j) {
+    const int cl = 16 * w + j;
+    const int64_t c = c0 + cl;
+    const bool ok = rok && c > i && r >= c;
+    if (upd && ok) {
+      a[j] -= rvp * cwp[cl] + rwp * cvp[cl];
+      A[r + c * k] = a[j];
     }
-    for (; r < k; r += 64) {
-      double a = col[r], a2 = two ? col2[r] : 0.0;
-      if (upd) {
-        const double pv = vprev[r], pw = wprev[r];
-        a -= pv * wc + pw * vc;
-        col[r] = a;
-        if (two) {
-          a2 -= pv * wc2 + pw * vc2;
-          col2[r] = a2;
-        }
-      }
-      const double v = vcur[r];
-      dot = fma(a, v, dot);
-      dot2 = fma(a2, v, dot2);
-    }
-    dot = wave_sum_f64(dot);
-    dot2 = wave_sum_f64(dot2);
-    if (lane == 0) {
-      s.p[c] = tau * dot;
-      if (two) s.p[c2] = tau * dot2;
-    }
+    prod[lane][cl] = a[j] * rv;                   // to p_c (diagonal included)
+    if (r > c) racc = fma(a[j], cv[cl], racc);  // to p_r (a[j] = 0 off the triangle)
+  }
+  rowp[w][lane] = racc;
+  __syncthreads();
+  {
+    const int cl = tid & 63, g = tid >> 6;
+    double cs = 0.0;
+#pragma unroll
+    for (int l = 0; l < 16; ++l) cs += prod[16 * g + l][cl];
+    colp[g][cl] = cs;
+  }
+  __syncthreads();
+  if (tid < kTT) {
+    prow[t * kTT + tid] = ((rowp[0][tid] + rowp[1][tid]) + rowp[2][tid]) + rowp[3][tid];
+    pcol[t * kTT + tid] = ((colp[0][tid] + colp[1][tid]) + colp[2][tid]) + colp[3][tid];
+  }
+}
+
+// Block X (relative to J0): row sums of tiles (X, 0..X), then column sums
+// of tiles (X..nbr-1, X), in four interleaved groups added in group order.
+__global__ __launch_bounds__(256) void k_tri_reduce(SketchState s, int64_t i, int64_t nbr, int64_t tiles_max) {
+  __shared__ double part[4][kTT];
+  const double *prow = s.work, *pcol = s.work + tiles_max * kTT;
+  const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+  const int64_t X = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t q = g; q <= nbr; q += 4)
+    acc += (q <= X) ? prow[tri_tile_index(X, q) * kTT + lane] : pcol[tri_tile_index(q - 1, X) * kTT + lane];
+  part[g][lane] = acc;
+  __syncthreads();
+  if (tid < kTT) {
+    const int64_t rr = ((i + 1) / kTT + X) * kTT + tid;
+    const double tot = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    if (rr > i && rr < s.k) s.p[rr] = s.tau[i] * tot;
   }
 }
 
@@ -869,12 +898,14 @@ int launch_frob(const float *Y, int64_t ldy, int64_t n, int64_t k, double *part,
 
 int launch_tridiag(const SketchState &s, hipStream_t st) {
   const int64_t k = s.k;
+  const int64_t nb = (k + kTT - 1) / kTT;
+  const int64_t tiles_max = nb * (nb + 1) / 2;
   for (int64_t i = 0; i < k; ++i) {
     hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(kTriThreads), 0, st, s, i);
     if (i + 1 < k) {
-      const int64_t cols = k - i - 1;
-      const int grid = (int)std::min<int64_t>(512, (cols + 3) / 4);
-      hipLaunchKernelGGL(k_tri_big, dim3(grid), dim3(256), 0, st, s, i);
+      const int64_t nbr = nb - (i + 1) / kTT;
+      hipLaunchKernelGGL(k_tri_tiles, dim3((unsigned)(nbr * (nbr + 1) / 2)), dim3(256), 0, st, s, i, tiles_max);
+      hipLaunchKernelGGL(k_tri_reduce, dim3((unsigned)nbr), dim3(256), 0, st, s, i, nbr, tiles_max);
     }
   }
   return (int)hipGetLastError();
