@@ -397,9 +397,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_small(SketchState s, int64_
 // 16 w .. 16 w + 15.  A tile writes its 64 column sums (for block J) and 64
 // row sums (for block I) to `work`.  k_tri_reduce: one workgroup per block
 // adds that block's partial sums in a fixed order and writes p for its
-// rows.  (A last-arriving-tile reduction inside k_tri_tiles needs a
-// device-scope fence per tile, which writes back and invalidates the L2 of
-// every XCD and costs more than the launch it saves.)
+// rows.  (Letting the last tile of a block do its sum inside k_tri_tiles
+// needs a device-scope release fence per tile, an L2 write-back on its XCD;
+// measured, that costs four times the launch it saves.)
 constexpr int kTT = 64;  // tile edge
 
 __device__ __forceinline__ int64_t tri_tile_index(int64_t a, int64_t b) { return a * (a + 1) / 2 + b; }
@@ -477,20 +477,23 @@ __global__ __launch_bounds__(256) void k_tri_tiles(SketchState s, int64_t i, int
 }
 
 // Block X (relative to J0): row sums of tiles (X, 0..X), then column sums
-// of tiles (X..nbr-1, X), in four interleaved groups added in group order.
-__global__ __launch_bounds__(256) void k_tri_reduce(SketchState s, int64_t i, int64_t nbr, int64_t tiles_max) {
-  __shared__ double part[4][kTT];
+// of tiles (X..nbr-1, X), in sixteen interleaved groups added in group
+// order.
+__global__ __launch_bounds__(1024) void k_tri_reduce(SketchState s, int64_t i, int64_t nbr, int64_t tiles_max) {
+  __shared__ double part[16][kTT];
   const double *prow = s.work, *pcol = s.work + tiles_max * kTT;
   const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
   const int64_t X = blockIdx.x;
   double acc = 0.0;
-  for (int64_t q = g; q <= nbr; q += 4)
+  for (int64_t q = g; q <= nbr; q += 16)
     acc += (q <= X) ? prow[tri_tile_index(X, q) * kTT + lane] : pcol[tri_tile_index(q - 1, X) * kTT + lane];
   part[g][lane] = acc;
   __syncthreads();
   if (tid < kTT) {
     const int64_t rr = ((i + 1) / kTT + X) * kTT + tid;
-    const double tot = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    double tot = part[0][tid];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) tot += part[u][tid];
     if (rr > i && rr < s.k) s.p[rr] = s.tau[i] * tot;
   }
 }
@@ -905,7 +908,7 @@ int launch_tridiag(const SketchState &s, hipStream_t st) {
     if (i + 1 < k) {
       const int64_t nbr = nb - (i + 1) / kTT;
       hipLaunchKernelGGL(k_tri_tiles, dim3((unsigned)(nbr * (nbr + 1) / 2)), dim3(256), 0, st, s, i, tiles_max);
-      hipLaunchKernelGGL(k_tri_reduce, dim3((unsigned)nbr), dim3(256), 0, st, s, i, nbr, tiles_max);
+      hipLaunchKernelGGL(k_tri_reduce, dim3((unsigned)nbr), dim3(1024), 0, st, s, i, nbr, tiles_max);
     }
   }
   return (int)hipGetLastError();
