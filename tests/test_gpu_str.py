@@ -70,3 +70,27 @@ def test_str_build_and_solve(npga, n, T, k, ell):
     assert mu_o @ xg >= r - 1e-6 * max(1.0, abs(r))
     assert abs(f_gpu - ref["f"]) <= 1e-6 * ref["f"], (f_gpu, ref["f"])
     assert np.abs(xg - ref["x"]).max() <= 1e-5, np.abs(xg - ref["x"]).max()
+
+
+def test_str_largest_k(npga):
+    """k = 8192, the largest sketch size, with n = 700 < T < k: G = Y^T Y has
+    rank 700, so most Householder steps see an all-zero column (tau = 0).
+    Ten factors put a wide gap after sigma_10, so ell = 10 is well posed;
+    the oracle truncates the float64 SVD of Y built from the same S."""
+    n, T, k, ell = 700, 1000, 8192, 10
+    banner(f"STR largest k: n={n} T={T} k={k} ell={ell}")
+    Rt, r, S = _case(n, T, k, ell, seed=77)
+    L, mu = npga.build_factor(to_dev(Rt))
+    Leff, sigma, gamma = npga.sketch_str(L, to_dev(S), ell, ridge_coef=1e-4)
+    mu_o, L_o = ofactor.build_factor(Rt.T)
+    Y = osketch.sketch(L_o, S.astype(np.float64).T)
+    Le_o, sig_o, gam_o = osketch.str_factor(Y, ell, 1e-4)
+    assert sig_o[ell - 1] > 4 * sig_o[ell]  # the gap the test relies on
+    sig = sigma.cpu().numpy().astype(np.float64)
+    Le = Leff.cpu().numpy().astype(np.float64).T
+    np.testing.assert_allclose(sig, sig_o[:ell], rtol=2e-5)
+    assert abs(gamma - gam_o) <= 1e-5 * gam_o
+    C = Le.T @ Le
+    assert np.abs(C - np.diag(np.diag(C))).max() <= 1e-5 * sig_o[0] ** 2
+    Sh, Sh_o = Le @ Le.T, Le_o @ Le_o.T
+    assert np.linalg.norm(Sh - Sh_o, 2) <= 1e-5 * np.linalg.norm(Sh_o, 2)
