@@ -12,7 +12,7 @@ refinement).  ``value`` is the median over the timed steps of the GPU time
 from npga_solve entry until the stopping test first passed (residual
 <= 1e-6), in seconds; ``ms_per_step`` is the wall time of a whole step.
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: the solver runs on one GPU.
 """
 import argparse
 import json
@@ -216,7 +216,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
-              "has no multi-GPU path in this build.", file=sys.stderr)
+              "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -61,7 +61,7 @@ typedef enum npga_status {
   NPGA_ERR_NUMERIC = 5,       /* NaN or Inf met in the data or the iteration */
   NPGA_ERR_WORKSPACE = 6,     /* workspace missing, misaligned or too small  */
   NPGA_ERR_HIP = 7,           /* a HIP runtime call failed                   */
-  NPGA_ERR_UNSUPPORTED = 8    /* valid request this build does not implement */
+  NPGA_ERR_UNSUPPORTED = 8    /* valid request the library does not implement */
 } npga_status;
 
 typedef enum npga_path {

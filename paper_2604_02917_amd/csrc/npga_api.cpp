@@ -403,7 +403,7 @@ const char *npga_status_string(int status) {
     case NPGA_ERR_NUMERIC: return "non-finite value in the data or the iteration";
     case NPGA_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
     case NPGA_ERR_HIP: return "HIP runtime error";
-    case NPGA_ERR_UNSUPPORTED: return "not supported by this build";
+    case NPGA_ERR_UNSUPPORTED: return "not supported by the library";
     default: return "unknown status";
   }
 }
