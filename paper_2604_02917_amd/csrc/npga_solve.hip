@@ -274,28 +274,36 @@ __global__ __launch_bounds__(256) void k_sweep(SolveArgs a) {
 // layout as k_sweep: the float4 group q = 2l + h + 128j covers rows 4q..4q+3.
 // Requires 16-byte alignment of L and ld % 8 == 0 (checked by the launcher);
 // rows n..ld-1 of a column are read and masked to zero.
-template <int E2, bool RAGGED>
-__global__ __launch_bounds__(256) void k_sweep_b16(SolveArgs a) {
+template <int E2, bool RAGGED, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_b16(SolveArgs a) {
+  static_assert(NW == 4 || NW == 8, "four or eight wavefronts");
   constexpr int E = 2 * E2;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   if (a.st->done != kRunning) return;
   __shared__ f4 sh[4 * 64 * E];
-  __shared__ double shu[4];
+  __shared__ f4 xsh[64 * E];  // x, read by every wavefront; later the usq sums
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t n = a.n;
-  const int64_t W = (int64_t)gridDim.x * 4;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t W = (int64_t)gridDim.x * NW;
+  const int64_t gw = (int64_t)blockIdx.x * NW + wave;
+  // zero that the compiler cannot see through (this kernel runs on bfloat16
+  // factors only): the gradient update widens the raw column again instead
+  // of keeping the widened values of the dot product live across its sum
+  const unsigned int z = (unsigned int)(a.dtype - NPGA_BF16);
 
-  f4 xr[E], g[E];
+  // x in LDS (float4 2j + h of lane l at xsh[(2j + h) 64 + l]) leaves the
+  // registers to g and two raw columns, so up to n = 5632 (7168 when n % 8
+  // is 0) two wavefronts fit on a SIMD (NW = 8)
+  for (int q = threadIdx.x; q < 64 * E; q += 64 * NW) {
+    const int j2 = q >> 6, l = q & 63;
+    xsh[q] = *reinterpret_cast<const f4 *>(a.xs + 8 * l + 512 * (j2 >> 1) + 4 * (j2 & 1));
+  }
+  f4 g[E];
 #pragma unroll
-  for (int j = 0; j < E2; ++j)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      xr[2 * j + h] = *reinterpret_cast<const f4 *>(a.xs + 8 * lane + 512 * j + 4 * h);
-      g[2 * j + h] = f4{0.f, 0.f, 0.f, 0.f};
-    }
+  for (int j = 0; j < E; ++j) g[j] = f4{0.f, 0.f, 0.f, 0.f};
   double usq = 0.0;
+  __syncthreads();
 
   const uint16_t *Lt = static_cast<const uint16_t *>(a.L);
   auto load = [&](u4(&c)[E2], int64_t col) {
@@ -325,28 +333,33 @@ __global__ __launch_bounds__(256) void k_sweep_b16(SolveArgs a) {
     float d0 = 0.f, d1 = 0.f;
 #pragma unroll
     for (int j = 0; j < E2; ++j) {
-      d0 = fmaf(lo(m[j][0]), xr[2 * j].x, d0);
-      d1 = fmaf(hi(m[j][0]), xr[2 * j].y, d1);
-      d0 = fmaf(lo(m[j][1]), xr[2 * j].z, d0);
-      d1 = fmaf(hi(m[j][1]), xr[2 * j].w, d1);
-      d0 = fmaf(lo(m[j][2]), xr[2 * j + 1].x, d0);
-      d1 = fmaf(hi(m[j][2]), xr[2 * j + 1].y, d1);
-      d0 = fmaf(lo(m[j][3]), xr[2 * j + 1].z, d0);
-      d1 = fmaf(hi(m[j][3]), xr[2 * j + 1].w, d1);
+      const f4 xa = xsh[(2 * j) * 64 + lane], xb = xsh[(2 * j + 1) * 64 + lane];
+      d0 = fmaf(lo(m[j][0]), xa.x, d0);
+      d1 = fmaf(hi(m[j][0]), xa.y, d1);
+      d0 = fmaf(lo(m[j][1]), xa.z, d0);
+      d1 = fmaf(hi(m[j][1]), xa.w, d1);
+      d0 = fmaf(lo(m[j][2]), xb.x, d0);
+      d1 = fmaf(hi(m[j][2]), xb.y, d1);
+      d0 = fmaf(lo(m[j][3]), xb.z, d0);
+      d1 = fmaf(hi(m[j][3]), xb.w, d1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads of x next to their use
     }
     const float d = wave_sum_f32(d0 + d1);
     const double ut = a.ua ? a.ua[col_cur] + (double)d : (double)d;
     usq = fma(ut, ut, usq);
 #pragma unroll
     for (int j = 0; j < E2; ++j) {
-      g[2 * j].x = fmaf(lo(m[j][0]), d, g[2 * j].x);
-      g[2 * j].y = fmaf(hi(m[j][0]), d, g[2 * j].y);
-      g[2 * j].z = fmaf(lo(m[j][1]), d, g[2 * j].z);
-      g[2 * j].w = fmaf(hi(m[j][1]), d, g[2 * j].w);
-      g[2 * j + 1].x = fmaf(lo(m[j][2]), d, g[2 * j + 1].x);
-      g[2 * j + 1].y = fmaf(hi(m[j][2]), d, g[2 * j + 1].y);
-      g[2 * j + 1].z = fmaf(lo(m[j][3]), d, g[2 * j + 1].z);
-      g[2 * j + 1].w = fmaf(hi(m[j][3]), d, g[2 * j + 1].w);
+      u4 r;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) r[w] = (c[j][w] ^ z) & keep(j, w);
+      g[2 * j].x = fmaf(lo(r[0]), d, g[2 * j].x);
+      g[2 * j].y = fmaf(hi(r[0]), d, g[2 * j].y);
+      g[2 * j].z = fmaf(lo(r[1]), d, g[2 * j].z);
+      g[2 * j].w = fmaf(hi(r[1]), d, g[2 * j].w);
+      g[2 * j + 1].x = fmaf(lo(r[2]), d, g[2 * j + 1].x);
+      g[2 * j + 1].y = fmaf(hi(r[2]), d, g[2 * j + 1].y);
+      g[2 * j + 1].z = fmaf(lo(r[3]), d, g[2 * j + 1].z);
+      g[2 * j + 1].w = fmaf(hi(r[3]), d, g[2 * j + 1].w);
     }
   };
 
@@ -366,21 +379,42 @@ __global__ __launch_bounds__(256) void k_sweep_b16(SolveArgs a) {
     col = col2;
   }
 
+  // combine the wavefronts in a fixed order (with eight: wavefront w + 4
+  // into w first), then the four sums
+  __syncthreads();  // every wavefront is done with x
+  double *shu = reinterpret_cast<double *>(xsh);
+  const int slot = wave & 3;
+  if (NW == 4 || wave >= 4) {
 #pragma unroll
-  for (int j = 0; j < E2; ++j)
+    for (int j = 0; j < E2; ++j)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) sh[wave * 64 * E + 2 * lane + h + 128 * j] = g[2 * j + h];
+      for (int h = 0; h < 2; ++h) sh[slot * 64 * E + 2 * lane + h + 128 * j] = g[2 * j + h];
+  }
   if (lane == 0) shu[wave] = usq;
   __syncthreads();
+  if (NW == 8 && wave < 4) {
+#pragma unroll
+    for (int j = 0; j < E2; ++j)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        f4 &t = sh[slot * 64 * E + 2 * lane + h + 128 * j];
+        t = g[2 * j + h] + t;
+      }
+  }
+  if (NW == 8) __syncthreads();
   float *out = a.partials + (int64_t)blockIdx.x * a.ldp;
-  for (int q = threadIdx.x; q < 64 * E; q += 256) {
+  for (int q = threadIdx.x; q < 64 * E; q += 64 * NW) {
     f4 s = sh[q];
     s += sh[64 * E + q];
     s += sh[2 * 64 * E + q];
     s += sh[3 * 64 * E + q];
     *reinterpret_cast<f4 *>(out + 4 * q) = s;
   }
-  if (threadIdx.x == 0) a.usq_part[blockIdx.x] = ((shu[0] + shu[1]) + shu[2]) + shu[3];
+  if (threadIdx.x == 0) {
+    a.usq_part[blockIdx.x] =
+        NW == 8 ? (((shu[0] + shu[4]) + (shu[1] + shu[5])) + (shu[2] + shu[6])) + (shu[3] + shu[7])
+                : ((shu[0] + shu[1]) + shu[2]) + shu[3];
+  }
 }
 
 // Row blocks of 64 sum the sweep partials in a fixed order (deterministic)
@@ -602,8 +636,13 @@ int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
     if (wide) {
 #define CALL(E2)                                                                          \
   do {                                                                                    \
-    if (a.n & 7) hipLaunchKernelGGL((k_sweep_b16<E2, true>), dim3(a.sweep_grid), dim3(256), 0, s, a); \
-    else hipLaunchKernelGGL((k_sweep_b16<E2, false>), dim3(a.sweep_grid), dim3(256), 0, s, a);        \
+    if (a.n & 7) {                                                                        \
+      constexpr int NW = (E2 <= 11) ? 8 : 4;                                              \
+      hipLaunchKernelGGL((k_sweep_b16<E2, true, NW>), dim3(a.sweep_grid), dim3(64 * NW), 0, s, a); \
+    } else {                                                                              \
+      constexpr int NW = (E2 <= 14) ? 8 : 4;                                              \
+      hipLaunchKernelGGL((k_sweep_b16<E2, false, NW>), dim3(a.sweep_grid), dim3(64 * NW), 0, s, a); \
+    }                                                                                     \
   } while (0)
       switch (slots / 2) {
         case 1: CALL(1); break;
