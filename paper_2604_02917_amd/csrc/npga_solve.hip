@@ -422,18 +422,26 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_b16(SolveArgs a) {
 // signalling: the serial tail is a separate one-workgroup launch, so the
 // kernel boundary orders the writes (a per-workgroup device-scope fence
 // costs more than that launch).
-__global__ __launch_bounds__(256) void k_reduce(SolveArgs a) {
+__global__ __launch_bounds__(1024) void k_reduce(SolveArgs a) {
   DevState *st = a.st;
   if (st->done != kRunning) return;
-  __shared__ double red[4][64];
+  // sixteen groups of 64 rows, so that each thread has at most 16 of the
+  // (at most 256) partials to load and all of them are in flight at once
+  __shared__ double red[16][64];
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
   if (blockIdx.x == 0) {
     // ||L^T x||^2 from the per-workgroup partials (one per sweep workgroup)
-    __shared__ double ubuf[8];
-    BlockReducer<1> red1{ubuf, 0};
-    double u[1] = {threadIdx.x < a.sweep_grid ? a.usq_part[threadIdx.x] : 0.0};
-    red1.sum(u);
-    if (threadIdx.x == 0) st->usq_sweep = u[0];
+    __shared__ double ubuf[16];
+    double u = threadIdx.x < a.sweep_grid ? a.usq_part[threadIdx.x] : 0.0;
+    u = wave_sum_f64(u);
+    if (r == 0) ubuf[q] = u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = ubuf[0];
+#pragma unroll
+      for (int w = 1; w < 16; ++w) t += ubuf[w];
+      st->usq_sweep = t;
+    }
   }
   const int64_t i = (int64_t)blockIdx.x * 64 + r;
   const int G = a.sweep_grid;
@@ -441,12 +449,14 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a) {
   if (i < a.n) {
     const float *p = a.partials + i;
 #pragma unroll 16
-    for (int w = q; w < G; w += 4) s += (double)p[(int64_t)w * a.ldp];
+    for (int w = q; w < G; w += 16) s += (double)p[(int64_t)w * a.ldp];
   }
   red[q][r] = s;
   __syncthreads();
   if (q == 0 && i < a.n) {
-    const double tot = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+    double tot = red[0][r];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) tot += red[u][r];
     if (a.mode == kTailNpga) {
       const int cur = st->iter & 1;
       const double *xk = cur ? a.xbuf1 : a.xbuf0;
@@ -671,7 +681,7 @@ int launch_sweep(const SolveArgs &a, int slots, hipStream_t s) {
 
 int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
   const int grid = (int)((a.n + 63) / 64);
-  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(1024), 0, s, a);
   if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
   return launch_tail(a, slots, 0, s);
 }
