@@ -37,10 +37,6 @@ class FactorModel:
     def grad(self, x):
         return 2.0 * (self.L @ (self.L.T @ x)) + 2.0 * self.gamma * x
 
-    def hessian(self):
-        n = self.L.shape[0]
-        return 2.0 * (self.L @ self.L.T + self.gamma * np.eye(n))
-
     def curv(self, d):
         """d^T Q d = ||L^T d||^2 + gamma ||d||^2: for this quadratic f,
         f(x) - f(y) - <grad f(y), x - y> equals curv(x - y) exactly."""
@@ -64,9 +60,6 @@ class CovarianceModel:
 
     def grad(self, x):
         return 2.0 * (self.S @ x)
-
-    def hessian(self):
-        return 2.0 * self.S
 
     def curv(self, d):
         """d^T Sigma d (= f(x) - f(y) - <grad f(y), x - y> with d = x - y)."""

@@ -85,13 +85,31 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
 }
 
-// Workgroup-wide sum of K doubles for a 256-thread workgroup.  Every thread
-// receives bitwise identical totals: the wave sums are uniform, and the four
-// wave totals are combined in a fixed order.  Two
-// LDS buffers alternate so a single barrier per call suffices.
-template <int K>
+// Workgroup-wide sum of K doubles for a workgroup of NW wavefronts.  Every
+// thread receives bitwise identical totals: the wave sums are uniform, and
+// the NW wave totals are combined in a fixed order (sequentially for four
+// wavefronts; beyond, the even and the odd wavefronts in two sequential
+// chains, then their sum).  Two LDS buffers alternate so a single barrier
+// per call suffices.
+template <int NW>
+__device__ __forceinline__ double combine_waves(const double *b, int stride) {
+  if constexpr (NW == 4) {
+    return ((b[0] + b[stride]) + b[2 * stride]) + b[3 * stride];
+  } else {
+    double e = b[0], o = b[stride];
+#pragma unroll
+    for (int w = 2; w < NW; w += 2) {
+      e += b[w * stride];
+      o += b[(w + 1) * stride];
+    }
+    return e + o;
+  }
+}
+
+template <int K, int NW = 4>
 struct BlockReducer {
-  double *buf;  // shared: 2 * 4 * K doubles
+  static constexpr int kWaves = NW;
+  double *buf;  // shared: 2 * NW * K doubles
   int parity;
 
   __device__ __forceinline__ void sum(double (&a)[K]) {
@@ -99,17 +117,24 @@ struct BlockReducer {
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) a[k] = wave_sum_f64(a[k]);
-    double *b = buf + parity * (4 * K);
+    double *b = buf + parity * (NW * K);
     if (lane == 0) {
 #pragma unroll
       for (int k = 0; k < K; ++k) b[wave * K + k] = a[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) a[k] = ((b[k] + b[K + k]) + b[2 * K + k]) + b[3 * K + k];
+    for (int k = 0; k < K; ++k) a[k] = combine_waves<NW>(b + k, K);
     parity ^= 1;
   }
 };
+
+// LDS doubles a reducer set of NW wavefronts needs: BlockReducer<5> (both
+// halves) and the masked pass's BlockReducer<6> (one half).
+template <int NW>
+constexpr int red_buf_doubles() {
+  return 2 * NW * 5 + NW * 6;
+}
 
 // Workgroup-wide minimum of (value, index) pairs; ties go to the smaller
 // index, so every thread receives the same pair.
@@ -123,8 +148,9 @@ __device__ __forceinline__ MinLoc minloc_pick(MinLoc a, MinLoc b) {
   return a;
 }
 
-__device__ __forceinline__ MinLoc block_minloc(MinLoc m, double *buf /* 8 doubles */, int64_t *ibuf /* 8 */,
-                                               int &parity) {
+// buf, ibuf: 2 * NW entries each
+template <int NW = 4>
+__device__ __forceinline__ MinLoc block_minloc(MinLoc m, double *buf, int64_t *ibuf, int &parity) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     MinLoc o;
@@ -133,8 +159,8 @@ __device__ __forceinline__ MinLoc block_minloc(MinLoc m, double *buf /* 8 double
     m = minloc_pick(m, o);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double *b = buf + parity * 4;
-  int64_t *bi = ibuf + parity * 4;
+  double *b = buf + parity * NW;
+  int64_t *bi = ibuf + parity * NW;
   if (lane == 0) {
     b[wave] = m.v;
     bi[wave] = m.i;
@@ -142,7 +168,7 @@ __device__ __forceinline__ MinLoc block_minloc(MinLoc m, double *buf /* 8 double
   __syncthreads();
   MinLoc r{b[0], bi[0]};
 #pragma unroll
-  for (int w = 1; w < 4; ++w) r = minloc_pick(r, MinLoc{b[w], bi[w]});
+  for (int w = 1; w < NW; ++w) r = minloc_pick(r, MinLoc{b[w], bi[w]});
   parity ^= 1;
   return r;
 }
@@ -152,8 +178,9 @@ struct PassSums {
   double c, sv, sm, smm, smv;
 };
 
-// Projection of the n-vector held in registers (thread t owns entries
-// i = t + 256 j, j < E; invalid entries carry v = -1e300, mu = 0).
+// Projection of the n-vector held in registers (thread t of the NW
+// wavefronts owns entries i = t + 64 NW j, j < E; invalid entries carry
+// v = -1e300, mu = 0).
 //
 // Pi_F(v) = Pi_Delta(v + nu mu) for the nu >= 0 that satisfies the
 // complementarity of the return constraint (eq. projF-dualpath), with
@@ -184,9 +211,9 @@ struct ProjResult {
   int32_t flags;  // bit 0: pass or sweep cap hit, bit 1: bracket failure, bit 2: Dykstra used
 };
 
-template <int E>
+template <int E, int NW>
 __device__ __forceinline__ PassSums proj_pass(const double (&v)[E], const double (&mu)[E], double nu,
-                                              double tau, BlockReducer<5> &red) {
+                                              double tau, BlockReducer<5, NW> &red) {
   double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -206,13 +233,13 @@ __device__ __forceinline__ double tau_of(const PassSums &s, double nu) {
   return (fma(nu, s.sm, s.sv) - 1.0) / s.c;
 }
 
-template <int E>
+template <int E, int NW>
 __device__ __forceinline__ double simplex_tau(const double (&v)[E], const double (&mu)[E], double nu,
-                                              double guess, PassSums &s, BlockReducer<5> &red,
+                                              double guess, PassSums &s, BlockReducer<5, NW> &red,
                                               int &passes, int &flags) {
   double tau = guess;
   for (int it = 0; it < 96; ++it) {
-    s = proj_pass<E>(v, mu, nu, tau, red);
+    s = proj_pass<E, NW>(v, mu, nu, tau, red);
     ++passes;
     if (s.c < 0.5) {  // guess at or above max w: restart from the full set
       tau = -1.0e300;
@@ -228,13 +255,14 @@ __device__ __forceinline__ double simplex_tau(const double (&v)[E], const double
 
 // One pass that also counts membership changes against the previous pass
 // (per-thread bit masks, E <= 32).
-template <int E>
+template <int E, int NW>
 __device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const double (&mu)[E], double nu,
                                                      double tau, uint32_t &mask, double &changed,
                                                      double *buf) {
-  // buf holds 64 doubles: BlockReducer<5> uses [0, 40); this pass uses
-  // [40, 64) and is followed by a barrier before its next use
-  BlockReducer<6> red6{buf + 40, 0};
+  // buf holds red_buf_doubles<NW>() doubles: BlockReducer<5> uses the first
+  // 10 NW; this pass uses the next 6 NW and is followed by a barrier before
+  // its next use
+  BlockReducer<6, NW> red6{buf + 10 * NW, 0};
   double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   uint32_t nm = 0u;
 #pragma unroll
@@ -267,9 +295,9 @@ __device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const
 // Multipliers of the result (the dual search's nu and tau, for warm starts
 // and the stopping test's KKT report) are fitted on the support S of y from
 // y_i = v_i + nu mu_i - tau (the original v is x + p + q at every sweep).
-template <int E>
+template <int E, int NW>
 __device__ int dykstra_F(double (&v)[E], const double (&mu)[E], double r, int max_iter, double tol,
-                         BlockReducer<5> &red, int &flags, double &nu_out, double &tau_out) {
+                         BlockReducer<5, NW> &red, int &flags, double &nu_out, double &tau_out) {
   double a0[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < E; ++j) a0[0] = fma(mu[j], mu[j], a0[0]);  // invalid entries carry mu = 0
@@ -292,7 +320,7 @@ __device__ int dykstra_F(double (&v)[E], const double (&mu)[E], double r, int ma
     for (int j = 0; j < E; ++j) pw[j] = valid[j] ? v[j] + pw[j] : -1.0e300;
     PassSums s;
     int passes = 0;
-    tau = simplex_tau<E>(pw, mu, 0.0, tau, s, red, passes, flags);
+    tau = simplex_tau<E, NW>(pw, mu, 0.0, tau, s, red, passes, flags);
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -354,14 +382,14 @@ __device__ int dykstra_F(double (&v)[E], const double (&mu)[E], double r, int ma
 // DYK: Dykstra's alternating projections (dyk_iters sweeps, bit 2 of the
 // flags) instead of the dual search; a separate instantiation, so the dual
 // search's kernels carry none of its registers.
-template <int E, bool DYK = false>
+template <int E, bool DYK = false, int NW = 4>
 __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r, double tolphi,
-                                double nu_warm, double tau_warm, BlockReducer<5> &red, int dyk_iters = 0) {
+                                double nu_warm, double tau_warm, BlockReducer<5, NW> &red, int dyk_iters = 0) {
   ProjResult out{0.0, 0.0, 0, 0};
   int passes = 0, flags = 0;
   PassSums s;
   if constexpr (DYK) {
-    out.passes = dykstra_F<E>(v, mu, r, dyk_iters, 1e-14, red, flags, out.nu, out.tau);
+    out.passes = dykstra_F<E, NW>(v, mu, r, dyk_iters, 1e-14, red, flags, out.nu, out.tau);
     out.flags = flags | 4;
     return out;
   }
@@ -374,7 +402,7 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
   if (nu_warm > 0.0) {
     uint32_t mask = 0u;
     double changed = 0.0;
-    s = proj_pass_masked<E>(v, mu, nu_warm, tau_warm, mask, changed, red.buf);
+    s = proj_pass_masked<E, NW>(v, mu, nu_warm, tau_warm, mask, changed, red.buf);
     ++passes;
     __syncthreads();
     for (int it = 0; it < 4; ++it) {
@@ -385,7 +413,7 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
       const double tn = (b1 * s.smm - s.sm * b2) / det;
       const double nn = (s.sm * b1 - s.c * b2) / det;
       if (!(nn > 0.0) || !isfinite(tn)) break;
-      s = proj_pass_masked<E>(v, mu, nn, tn, mask, changed, red.buf);
+      s = proj_pass_masked<E, NW>(v, mu, nn, tn, mask, changed, red.buf);
       ++passes;
       __syncthreads();
       if (changed == 0.0) {
@@ -401,7 +429,7 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
   }
   const double INF = 1.0e308;
   double nu = (nu_warm > 0.0) ? nu_warm : 0.0;
-  double tau = simplex_tau<E>(v, mu, nu, tau_warm, s, red, passes, flags);
+  double tau = simplex_tau<E, NW>(v, mu, nu, tau_warm, s, red, passes, flags);
   double phi = fma(nu, s.smm, s.smv) - tau * s.sm;
   bool done = false;
   double lo = 0.0, hi = INF, tau_hi = 0.0;
@@ -439,7 +467,7 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
     }
     // affine prediction of tau(cand) from the current support
     const double guess = tau_of(s, cand);
-    tau = simplex_tau<E>(v, mu, cand, guess, s, red, passes, flags);
+    tau = simplex_tau<E, NW>(v, mu, cand, guess, s, red, passes, flags);
     nu = cand;
     phi = fma(nu, s.smm, s.smv) - tau * s.sm;
     if (nu == 0.0) {

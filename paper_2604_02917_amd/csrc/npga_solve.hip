@@ -1,16 +1,17 @@
 // NPGA solver kernels for gfx950 (paper Sec. 3.1, Algorithm 1).
 //
-// One NPGA iteration on the factor path is two launches:
-//   k_sweep        : every wavefront streams whole columns of L_eff and
-//                    computes u_t = L_{:,t}^T x (wavefront sum), accumulates
-//                    ||u||^2 and the partial gradient sum_t L_{:,t} u_t in
-//                    registers; each workgroup writes one partial n-vector.
-//                    L_eff is read from HBM exactly once per iteration.
-//   k_reduce_tail  : row blocks sum the partial vectors in a fixed order
-//                    (deterministic), giving g_k = 2 L(L^T x_k) + 2 gamma x_k;
-//                    the last workgroup to finish (atomic ticket, no spin
-//                    wait) runs the serial tail: stopping test, momentum
-//                    extrapolation, gradient step and the exact projection.
+// One NPGA iteration on the factor path is three launches on one stream:
+//   k_sweep   : every wavefront streams whole columns of L_eff and computes
+//               u_t = L_{:,t}^T x (wavefront sum), accumulates ||u||^2 and the
+//               partial gradient sum_t L_{:,t} u_t in registers; each
+//               workgroup writes one partial n-vector.  L_eff is read from
+//               HBM exactly once per iteration.
+//   k_reduce  : row blocks sum the partial vectors in a fixed order
+//               (deterministic), giving g_k = 2 L(L^T x_k) + 2 gamma x_k.
+//   k_tail_*  : one workgroup runs the serial tail of the current mode (for
+//               NPGA: stopping test, momentum extrapolation, gradient step
+//               and the exact projection).  The kernel boundaries order the
+//               writes; no workgroup waits on another.
 //
 // The sweep evaluates the gradient at the iterate x_k rather than at the
 // extrapolated point y_k: the gradient is affine in x, so
@@ -472,31 +473,55 @@ __global__ __launch_bounds__(1024) void k_reduce(SolveArgs a) {
   }
 }
 
-// The serial tail of one iteration (one workgroup).  `covariance` selects
-// the objective source: the sweep's ||L^T x||^2 partials on the factor path,
-// 1/2 x^T g on the covariance path.
+// The serial tails of one iteration, one kernel per mode (one workgroup
+// each), so that each carries only its own mode's registers.  `covariance`
+// selects the objective source: the sweep's ||L^T x||^2 partials on the
+// factor path, 1/2 x^T g on the covariance path.
+template <int E, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tail_npga(SolveArgs a, int covariance) {
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  __shared__ double redbuf[red_buf_doubles<NW>()];
+  tail_npga<E, false, false, NW>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+}
+
+template <int E, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tail_cg(SolveArgs a) {
+  if (a.st->done != kRunning) return;
+  __shared__ double redbuf[red_buf_doubles<NW>()];
+  __shared__ double mbuf[2 * NW];
+  __shared__ int64_t ibuf[2 * NW];
+  tail_cg<E, NW>(a, redbuf, mbuf, ibuf);
+}
+
 template <int E>
-__global__ __launch_bounds__(256) void k_tail(SolveArgs a, int covariance) {
+__global__ __launch_bounds__(256) void k_tail_adj(SolveArgs a) {
+  if (a.st->done != kRunning) return;
+  __shared__ double redbuf[64];
+  tail_adj<E>(a, redbuf);
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_tail_power(SolveArgs a, int covariance) {
   DevState *st = a.st;
   if (st->done != kRunning) return;
   __shared__ double redbuf[64];
-  __shared__ double mbuf[8];
-  __shared__ int64_t ibuf[8];
-  // the factor path's ||L^T x||^2 was summed by the reduce launch
-  const double usq =
-      (!covariance && (a.mode == kTailNpga || a.mode == kTailPower || a.mode == kTailGrad)) ? st->usq_sweep : -1.0;
-  if (a.mode == kTailNpga)
-    tail_npga<E>(a, usq, redbuf);
-  else if (a.mode == kTailCG)
-    tail_cg<E>(a, redbuf, mbuf, ibuf);
-  else if (a.mode == kTailAdj)
-    tail_adj<E>(a, redbuf);
-  else if (a.mode == kTailPower)
-    tail_power<E>(a, usq, redbuf);
-  else if (a.mode == kTailLanczos)
-    tail_lanczos<E>(a, redbuf);
-  else
-    tail_grad<E>(a, usq, redbuf);
+  tail_power<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_tail_lanczos(SolveArgs a) {
+  if (a.st->done != kRunning) return;
+  __shared__ double redbuf[64];
+  tail_lanczos<E>(a, redbuf);
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_tail_grad(SolveArgs a, int covariance) {
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  __shared__ double redbuf[64];
+  tail_grad<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
 }
 
 // The NPGA tail with Dykstra's projections (options.projection = 1) and/or
@@ -686,10 +711,32 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
   return launch_tail(a, slots, 0, s);
 }
 
+// Wavefronts of the NPGA and CG tails for n > 1024 (thread t of the
+// workgroup owns entries t + 64 NW j).  Four (one per SIMD) is the default:
+// with eight the tails' reductions alone hold ~50 more registers per lane
+// (the compiler keeps every wavefront's partials in flight) and the tails
+// spill from 2816 assets up; with four, a 5440-asset tail keeps its vectors
+// in registers and accumulation registers, with no scratch.
+#ifndef NPGA_TAIL_WAVES
+#define NPGA_TAIL_WAVES 4
+#endif
+
+// Per-thread entries of the NW-wavefront tails for the 256-thread slot count.
+#define NPGA_WIDE_SLOT_SWITCH(slots, CALL)                                                     \
+  switch (slots) {                                                                             \
+    case 8: CALL((8 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                       \
+    case 12: CALL((12 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                     \
+    case 16: CALL((16 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                     \
+    case 22: CALL((22 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                     \
+    case 28: CALL((28 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                     \
+    case 32: CALL((32 * 4 + NPGA_TAIL_WAVES - 1) / NPGA_TAIL_WAVES); break;                     \
+    default: return (int)hipErrorInvalidValue;                                                 \
+  }
+
 int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
   if ((a.dykstra || a.backtrack) && a.mode == kTailNpga) {
     // the NPGA tail with Dykstra's projections and/or backtracking: own
-    // instantiations, so k_tail carries none of their registers
+    // instantiations, so the plain tail carries none of their registers
     if (a.dykstra && a.backtrack) {
 #define CALL(E) hipLaunchKernelGGL((k_tail_var<E, true, true>), dim3(1), dim3(256), 0, s, a, covariance)
       NPGA_SLOT_SWITCH(slots, CALL)
@@ -705,9 +752,51 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
     }
     return (int)hipGetLastError();
   }
-#define CALL(E) hipLaunchKernelGGL(k_tail<E>, dim3(1), dim3(256), 0, s, a, covariance)
-  NPGA_SLOT_SWITCH(slots, CALL)
+  const bool wide = slots >= 8 && NPGA_TAIL_WAVES != 4;
+  switch (a.mode) {
+    case kTailNpga:
+      if (wide) {
+#define CALL(E) hipLaunchKernelGGL((k_tail_npga<E, NPGA_TAIL_WAVES>), dim3(1), dim3(64 * NPGA_TAIL_WAVES), 0, s, a, covariance)
+        NPGA_WIDE_SLOT_SWITCH(slots, CALL)
 #undef CALL
+      } else {
+#define CALL(E) hipLaunchKernelGGL((k_tail_npga<E, 4>), dim3(1), dim3(256), 0, s, a, covariance)
+        NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      }
+      break;
+    case kTailCG:
+      if (wide) {
+#define CALL(E) hipLaunchKernelGGL((k_tail_cg<E, NPGA_TAIL_WAVES>), dim3(1), dim3(64 * NPGA_TAIL_WAVES), 0, s, a)
+        NPGA_WIDE_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      } else {
+#define CALL(E) hipLaunchKernelGGL((k_tail_cg<E, 4>), dim3(1), dim3(256), 0, s, a)
+        NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      }
+      break;
+    case kTailAdj:
+#define CALL(E) hipLaunchKernelGGL(k_tail_adj<E>, dim3(1), dim3(256), 0, s, a)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      break;
+    case kTailPower:
+#define CALL(E) hipLaunchKernelGGL(k_tail_power<E>, dim3(1), dim3(256), 0, s, a, covariance)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      break;
+    case kTailLanczos:
+#define CALL(E) hipLaunchKernelGGL(k_tail_lanczos<E>, dim3(1), dim3(256), 0, s, a)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      break;
+    default:
+#define CALL(E) hipLaunchKernelGGL(k_tail_grad<E>, dim3(1), dim3(256), 0, s, a, covariance)
+      NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      break;
+  }
   return (int)hipGetLastError();
 }
 

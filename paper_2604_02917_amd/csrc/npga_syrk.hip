@@ -10,10 +10,11 @@
 // float64 registers every 256 periods, which bounds the float32 rounding
 // to partial sums of 256 products.
 //
-// k_symv_tail: g = 2 Sigma x + 2 gamma x.  Sigma is symmetric, so
-// (Sigma x)_i is the dot product of column i with x; every wavefront owns
-// whole columns (contiguous) and writes g_i directly.  The last workgroup
-// (atomic ticket) then runs the same NPGA tail as the factor path.
+// k_symv: g = 2 Sigma x + 2 gamma x.  Sigma is symmetric, so (Sigma x)_i
+// is the dot product of column i with x; every wavefront owns whole columns
+// (contiguous) and writes g_i directly, so no partial sums are needed.  The
+// serial tail (the same one as the factor path's) is the next launch on the
+// stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,5 +1,6 @@
-// Serial tails of the NPGA iteration, run by the one workgroup that
-// finishes a gradient launch last (paper Sec. 3.1, Algorithm 1).
+// Serial tails of the NPGA iteration (paper Sec. 3.1, Algorithm 1), each
+// run by a one-workgroup launch after the gradient launches of an
+// iteration.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,9 +20,11 @@ namespace npga {
 // (x - y)^T Q (x - y) <= ||x - y||^2/(2 alpha) with Q (x - y) = (grad f(x) -
 // grad f(y))/2, plus an allowance for the float32 products of the sweep;
 // otherwise alpha <- rho alpha and the trial is recomputed from the stored
-// y and grad f(y).
-template <int E, bool DYK = false, bool BT = false>
+// y and grad f(y).  NW: wavefronts of the workgroup (thread t owns entries
+// t + 64 NW j, j < E).
+template <int E, bool DYK = false, bool BT = false, int NW = 4>
 __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) {
+  constexpr int NT = 64 * NW;
   DevState *st = a.st;
   const int tid = threadIdx.x;
   const int64_t n = a.n;
@@ -31,28 +34,47 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   double *xn_p = cur ? a.xbuf0 : a.xbuf1;  // holds x_{k-1}; receives x_{k+1}
   const double *gk_p = cur ? a.gbuf1 : a.gbuf0;
   const double *gp_p = cur ? a.gbuf0 : a.gbuf1;
-  const double alpha = st->alpha, r = st->r, tolphi = st->tolphi;
-  BlockReducer<5> red{redbuf, 0};
+  const double alpha = st->alpha, r = st->r, tolphi = st->tolphi, beta = st->beta;
+  BlockReducer<5, NW> red{redbuf, 0};
 
   // every vector the iteration reads is loaded up front, so the loads of
-  // all five overlap
-  double mu[E], xk[E], gk[E], v[E], xp[E], gp[E];
+  // all five overlap; the step input v = y - alpha grad f(y) and the
+  // momentum direction dx = x_k - x_{k-1} are formed at once, after which
+  // x_{k-1} and g_{k-1} are dead (fewer live vectors in the projections).
+  // With backtracking the step is formed after the test of the pending
+  // trial, which reads that trial's y and grad f(y) from ybt and gybt.
+  double mu[E], xk[E], gk[E], v[E], dx[E];
+  auto form_step = [&](int j) {
+    const int64_t i = tid + NT * j;
+    const bool ok = i < n;
+    const double xp = ok ? xn_p[i] : 0.0;
+    const double gp = ok ? gp_p[i] : 0.0;
+    dx[j] = xk[j] - xp;
+    const double y = fma(beta, dx[j], xk[j]);
+    const double gy = fma(beta, gk[j] - gp, gk[j]);
+    v[j] = ok ? fma(-alpha, gy, y) : -1.0e300;
+    if constexpr (BT) {
+      if (ok) {
+        a.ybt[i] = y;
+        a.gybt[i] = gy;
+      }
+    }
+  };
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
+    const int64_t i = tid + NT * j;
     const bool ok = i < n;
     mu[j] = ok ? a.mu[i] : 0.0;
     xk[j] = ok ? xk_p[i] : 0.0;
     gk[j] = ok ? gk_p[i] : 0.0;
-    xp[j] = ok ? xn_p[i] : 0.0;
-    gp[j] = ok ? gp_p[i] : 0.0;
+    if constexpr (!BT) form_step(j);
   }
   if constexpr (BT) {
     if (st->bt_pending) {
       double acc[5] = {0, 0, 0, 0, 0};  // d^T Q d, ||d||^2, float32 allowance
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const int64_t i = tid + 256 * j;
+        const int64_t i = tid + NT * j;
         if (i < n) {
           const double yb = a.ybt[i], gyb = a.gybt[i];
           const double d = xk[j] - yb;
@@ -69,13 +91,13 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
         const double an = alpha * st->bt_rho;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-          const int64_t i = tid + 256 * j;
+          const int64_t i = tid + NT * j;
           v[j] = (i < n) ? fma(-an, a.gybt[i], a.ybt[i]) : -1.0e300;
         }
-        const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
+        const ProjResult pr = project_F<E, DYK, NW>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-          const int64_t i = tid + 256 * j;
+          const int64_t i = tid + NT * j;
           if (i < n) {
             xk_p[i] = v[j];
             a.xs[i] = (float)(a.xa ? v[j] - a.xa[i] : v[j]);
@@ -97,20 +119,27 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
         st->bt_consec = 0;
       }
     }
+    // every thread has read ybt and gybt (the reduction's barrier) before
+    // form_step overwrites its own entries; entries are per thread anyway
+#pragma unroll
+    for (int j = 0; j < E; ++j) form_step(j);
   }
 
   if (k % st->check_every == 0) {
-#pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = (tid + 256 * j < n) ? fma(-alpha, gk[j], xk[j]) : -1.0e300;
-    const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu_c, st->tau_c, red, st->dykstra_iters);
+    double w[E];
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const double d = v[j] - xk[j];
-      acc[0] = fma(d, d, acc[0]);
+      w[j] = (tid + NT * j < n) ? fma(-alpha, gk[j], xk[j]) : -1.0e300;
       acc[1] = fma(xk[j], xk[j], acc[1]);
       acc[2] += (xk[j] > 0.0) ? 1.0 : 0.0;
       acc[3] = fma(xk[j], gk[j], acc[3]);
+    }
+    const ProjResult pr = project_F<E, DYK, NW>(w, mu, r, tolphi, st->nu_c, st->tau_c, red, st->dykstra_iters);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const double d = w[j] - xk[j];
+      acc[0] = fma(d, d, acc[0]);
     }
     red.sum(acc);
     const double res = sqrt(acc[0]);
@@ -141,29 +170,16 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
     if (tid == 0) st->done = kMaxIter;
     return;
   }
-  const double beta = st->beta;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
-    const bool ok = i < n;
-    const double y = fma(beta, xk[j] - xp[j], xk[j]);
-    const double gy = fma(beta, gk[j] - gp[j], gk[j]);
-    v[j] = ok ? fma(-alpha, gy, y) : -1.0e300;
-    if constexpr (BT) {
-      if (ok) {
-        a.ybt[i] = y;
-        a.gybt[i] = gy;
-      }
-    }
-  }
-  const ProjResult pr = project_F<E, DYK>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
+  const ProjResult pr = project_F<E, DYK, NW>(v, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
   double t = st->t;
   int restarted = 0;
   if (st->restart) {
+    // gradient restart test (y - x_{k+1})^T (x_{k+1} - x_k) > 0 with
+    // y - x_k = beta dx
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const double y = fma(beta, xk[j] - xp[j], xk[j]);
+      const double y = fma(beta, dx[j], xk[j]);
       acc[0] = fma(y - v[j], v[j] - xk[j], acc[0]);
     }
     red.sum(acc);
@@ -176,7 +192,7 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   const double bn = st->const_momentum ? st->beta_const : (t - 1.0) / tn;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
+    const int64_t i = tid + NT * j;
     if (i < n) {
       xn_p[i] = v[j];
       a.xs[i] = (float)(a.xa ? v[j] - a.xa[i] : v[j]);
@@ -425,9 +441,9 @@ __device__ void tail_lanczos(const SolveArgs &a, double *redbuf) {
 // gradient; H p comes from the float32 sweep on the search direction.  The
 // stopping test is the NPGA residual ||Pi_F(x - alpha g) - x|| of Sec. 3.1.
 // ---------------------------------------------------------------------------
-template <int E>
+template <int E, int NW = 4>
 __device__ __forceinline__ void face_multipliers(const double (&g)[E], const double (&mu)[E],
-                                                 const double (&fr)[E], bool active, BlockReducer<5> &red,
+                                                 const double (&fr)[E], bool active, BlockReducer<5, NW> &red,
                                                  double &lam, double &nu) {
   double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
@@ -451,21 +467,22 @@ __device__ __forceinline__ void face_multipliers(const double (&g)[E], const dou
   }
 }
 
-template <int E>
+template <int E, int NW = 4>
 __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_t *ibuf) {
+  constexpr int NT = 64 * NW;
   DevState *st = a.st;
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   const int cur = st->iter & 1;
   double *x_p = cur ? a.xbuf1 : a.xbuf0;
-  BlockReducer<5> red{redbuf, 0};
+  BlockReducer<5, NW> red{redbuf, 0};
   int mpar = 0;
   const double INF = 1.0e308;
 
   double x[E], g[E], p[E], hp[E], mu[E], fr[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
+    const int64_t i = tid + NT * j;
     const bool ok = i < n;
     x[j] = ok ? x_p[i] : 0.0;
     g[j] = ok ? a.gvec[i] : 0.0;
@@ -484,7 +501,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   if (st->cg_pg) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int64_t i = tid + 256 * j;
+      const int64_t i = tid + NT * j;
       const bool ok = i < n;
       x[j] = ok ? xo_p[i] : 0.0;
       g[j] += hp[j];
@@ -492,7 +509,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     }
     const bool act = st->cg_pg_nu > 0.0;
     double lam0, nu0;
-    face_multipliers<E>(g, mu, fr, act, red, lam0, nu0);
+    face_multipliers<E, NW>(g, mu, fr, act, red, lam0, nu0);
     double acc0[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -502,7 +519,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     red.sum(acc0);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int64_t i = tid + 256 * j;
+      const int64_t i = tid + NT * j;
       if (i < n) {
         x_p[i] = x[j];
         a.gvec[i] = g[j];
@@ -539,9 +556,9 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   MinLoc m{INF, n};
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    if (fr[j] > 0.0 && p[j] < 0.0) m = minloc_pick(m, MinLoc{x[j] / (-p[j]), (int64_t)(tid + 256 * j)});
+    if (fr[j] > 0.0 && p[j] < 0.0) m = minloc_pick(m, MinLoc{x[j] / (-p[j]), (int64_t)(tid + NT * j)});
   }
-  m = block_minloc(m, mbuf, ibuf, mpar);
+  m = block_minloc<NW>(m, mbuf, ibuf, mpar);
   int block = 0;
   if (m.v < step) {
     step = m.v;
@@ -558,7 +575,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   for (int j = 0; j < E; ++j) {
     x[j] = fma(step, p[j], x[j]);
     g[j] = fma(step, hp[j], g[j]);
-    if (block == 1 && (int64_t)(tid + 256 * j) == m.i) {
+    if (block == 1 && (int64_t)(tid + NT * j) == m.i) {
       x[j] = 0.0;
       fr[j] = 0.0;
     }
@@ -569,13 +586,13 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 
   // (2) multipliers, projected gradient, reduced costs of the fixed entries
   double lam, nu;
-  face_multipliers<E>(g, mu, fr, active, red, lam, nu);
+  face_multipliers<E, NW>(g, mu, fr, active, red, lam, nu);
   double rv[E];
   MinLoc dm{INF, n};
   double acc2[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
+    const int64_t i = tid + NT * j;
     const double d = g[j] - lam - nu * mu[j];
     rv[j] = (fr[j] > 0.0) ? -d : 0.0;
     acc2[0] = fma(rv[j], rv[j], acc2[0]);
@@ -585,7 +602,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 #pragma unroll
   for (int j = 0; j < E; ++j) acc2[2] = fma(fr[j] * g[j], g[j], acc2[2]);
   red.sum(acc2);
-  dm = block_minloc(dm, mbuf, ibuf, mpar);
+  dm = block_minloc<NW>(dm, mbuf, ibuf, mpar);
   double rr_new = acc2[0];
   const double gscale = sqrt(acc2[1] / (double)n) + 1e-300;
   const double gs2 = acc2[2];  // ||g_S||^2 on the free entries
@@ -602,11 +619,11 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     const double alpha = st->alpha;
     double w[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) w[j] = (tid + 256 * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
-    const ProjResult pr = project_F<E>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    for (int j = 0; j < E; ++j) w[j] = (tid + NT * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
+    const ProjResult pr = project_F<E, false, NW>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int64_t i = tid + 256 * j;
+      const int64_t i = tid + NT * j;
       if (i < n) {
         xo_p[i] = w[j];
         x_p[i] = x[j];
@@ -629,7 +646,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     return;
   }
   if (restart) {
-    face_multipliers<E>(g, mu, fr, active, red, lam, nu);
+    face_multipliers<E, NW>(g, mu, fr, active, red, lam, nu);
     double acc3[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -663,8 +680,8 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     double w[E];
     const double alpha = st->alpha;
 #pragma unroll
-    for (int j = 0; j < E; ++j) w[j] = (tid + 256 * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
-    const ProjResult pr = project_F<E>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    for (int j = 0; j < E; ++j) w[j] = (tid + NT * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
+    const ProjResult pr = project_F<E, false, NW>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
     double acc4[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -699,7 +716,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
   const double beta = (!restart && rr > 0.0) ? rr_new / rr : 0.0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + 256 * j;
+    const int64_t i = tid + NT * j;
     p[j] = fma(beta, p[j], rv[j]);
     if (i < n) {
       x_p[i] = x[j];

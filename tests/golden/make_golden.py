@@ -106,6 +106,47 @@ def make_c4():
     print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
 
 
+def make_c4_bf16():
+    """The frontier workload on a bfloat16 factor: the oracle's float64 L
+    rounded to float32 (the precision the device builds it in), then to
+    bfloat16 by round-to-nearest-even (oracle.quantize), at the 128 targets
+    of c4_frontier.json.  The exact minimiser of every target on that
+    factor is the reference of the bfloat16 frontier's solver error; the
+    float32 frontier's stored objectives give its quantisation error."""
+    from oracle import quantize as oq
+    spec = gen.SPECS["c4"]
+    t0 = time.time()
+    with open(os.path.join(HERE, "c4_frontier.json")) as fh:
+        c4 = json.load(fh)
+    Rt = gen.returns_TxN(spec)
+    assert panel_digest(Rt) == c4["panel_sha256"]
+    mu, L = ofactor.build_factor(Rt.T)
+    del Rt
+    Lq = oq.round_to_bf16(L.astype(np.float32))
+    del L
+    Q = Lq @ Lq.T
+    rs = c4["targets"]
+    pts = []
+    for j, r in enumerate(rs):
+        out = exact_mv(Q, mu, float(r), fista_tol=1e-10)
+        x = out["x"]
+        rep = qp.kkt_report(2 * Q, np.zeros(spec.n), mu, float(r), x, out["lam"], out["nu"])
+        assert qp.certificate_ok(rep, tol_stat=1e-9, tol_feas=1e-12, r_scale=np.abs(mu).max()), rep
+        p = {"j": j, "r": float(r), "objective": factor_objective(Lq, 0.0, x), "nu": out["nu"],
+             "lambda": out["lam"], "support": int((x > 0).sum())}
+        if j in C4_SAMPLED:
+            p["x"] = [float(v) for v in x]
+        pts.append(p)
+        print(f"c4_bf16: target {j} f*={p['objective']:.6e} ({time.time() - t0:.1f}s)", flush=True)
+    doc = {"workload": "c4_bf16", "n": spec.n, "T": spec.T, "seed": spec.seed, "m": len(rs),
+           "panel_sha256": c4["panel_sha256"], "factor": "bf16(float32(L)), round to nearest even",
+           "targets": rs, "points": pts}
+    path = os.path.join(HERE, "c4_frontier_bf16.json")
+    with open(path, "w") as fh:
+        json.dump(doc, fh)
+    print(f"wrote {path} ({time.time() - t0:.1f}s)", flush=True)
+
+
 def make_c5():
     """Adjoint at full size: the out-of-sample loss l(w) = w^T Sigma_test w -
     mu_test^T w (held-out block: same B and drift, fresh draws, seed 105,
@@ -180,6 +221,8 @@ def make(name):
         return make_c3()
     if name == "c4":
         return make_c4()
+    if name == "c4_bf16":
+        return make_c4_bf16()
     spec = gen.SPECS[name]
     t0 = time.time()
     Rt = gen.returns_TxN(spec)

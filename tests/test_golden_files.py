@@ -139,3 +139,39 @@ def test_n8192_golden_consistent():
     assert np.abs(d[S]).max() <= 1e-9 * scale
     assert d[~S].min() >= -1e-8 * scale
     assert ref["nu"] >= 0 and ref["nu"] * (mu @ x - r) <= 1e-12 * scale
+
+
+GOLDEN_C4_BF16 = os.path.join(os.path.dirname(__file__), "golden", "c4_frontier_bf16.json")
+
+
+@pytest.mark.slow
+def test_c4_bf16_golden_consistent():
+    """Stored frontier on the bfloat16 factor: same panel and targets as the
+    float32 frontier, f* nondecreasing along the targets, and at the stored
+    minimisers feasibility, the stored objective and the KKT conditions
+    recomputed here in factor form on bf16(float32(L))."""
+    from oracle import quantize as oq
+    with open(GOLDEN_C4_BF16) as fh:
+        ref = json.load(fh)
+    with open(GOLDEN_C4) as fh:
+        c4 = json.load(fh)
+    assert ref["panel_sha256"] == c4["panel_sha256"] and ref["targets"] == c4["targets"]
+    spec = gen.SPECS["c4"]
+    Rt = gen.returns_TxN(spec)
+    assert panel_digest(Rt) == ref["panel_sha256"]
+    mu, L = ofactor.build_factor(Rt.T)
+    Lq = oq.round_to_bf16(L.astype(np.float32))
+    f = np.array([p["objective"] for p in ref["points"]])
+    assert np.all(np.diff(f) >= -1e-12 * f.max())
+    for p in ref["points"]:
+        if "x" not in p:
+            continue
+        x = np.asarray(p["x"])
+        assert x.min() >= 0 and abs(x.sum() - 1) <= 1e-12
+        assert mu @ x >= p["r"] - 1e-14
+        assert factor_objective(Lq, 0.0, x) == pytest.approx(p["objective"], rel=1e-12)
+        g = 2.0 * (Lq @ (Lq.T @ x))
+        d = g - p["lambda"] - p["nu"] * mu
+        S = x > 0
+        scale = np.abs(g).max()
+        assert np.abs(d[S]).max() <= 1e-9 * scale and d[~S].min() >= -1e-9 * scale

@@ -45,9 +45,13 @@ def _check_bf16_gradient(Rt, x, g, f):
 
 
 # 64: 8-byte loads (one 256-row slot); the rest: 16-byte loads, with n % 8
-# != 0 (rows past n masked inside a load) at 300, 1001, 2053 and 5437
+# != 0 (rows past n masked inside a load) at 300, 1001, 2053, 5437, 6001 and
+# 8191.  Above n = 5632 the sweep runs four wavefronts per workgroup except
+# for n % 8 == 0 up to 7168 (7168: eight wavefronts, 14 slot pairs; 8192:
+# four wavefronts, 16 slot pairs, the full 160 KiB of LDS)
 @pytest.mark.parametrize("n,T", [(64, 256), (300, 700), (1000, 4000), (1001, 3000), (2053, 1500),
-                                 (5437, 1200), (5440, 2000)])
+                                 (5437, 1200), (5440, 2000), (6001, 700), (7168, 600), (8191, 500),
+                                 (8192, 500)])
 def test_bf16_gradient(npga, n, T):
     spec = spec_with("c2", n, T, seed=70 + n)
     Rt = gen.returns_TxN(spec)
@@ -111,4 +115,5 @@ def test_bf16_solve(npga, n, T, q):
     f_full = factor_objective(L_o, 0.0, xg)
     gap = (f_full - full["f"]) / full["f"]
     banner(f"bf16 n={n}: quantisation gap {gap:.2e}, max|x - x*_fp32| {np.abs(xg - full['x']).max():.2e}")
-    assert 0.0 <= gap <= 1e-2
+    # observed gaps at these shapes are below 1e-6: the bar is ~100 times that
+    assert 0.0 <= gap <= 1e-4

@@ -1,5 +1,6 @@
 """Full-size frontier (n = 2000, T = 20000, 128 targets) against the stored
-oracle solutions tests/golden/c4_frontier.json (oracle-only script
+oracle solutions tests/golden/c4_frontier.json and, for the bfloat16
+factor, tests/golden/c4_frontier_bf16.json (oracle-only script
 tests/golden/make_golden.py): every target's objective, and the minimiser
 at a sample of targets, in the launch configuration the benchmark uses."""
 import json
@@ -19,9 +20,10 @@ from tests.gpu_util import banner, to_dev
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c4_frontier.json")
+GOLDEN_BF16 = os.path.join(os.path.dirname(__file__), "golden", "c4_frontier_bf16.json")
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="c4 golden not generated")
+@pytest.mark.skipif(not (os.path.exists(GOLDEN) and os.path.exists(GOLDEN_BF16)), reason="c4 goldens not generated")
 def test_c4_frontier_parity():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -54,14 +56,39 @@ def test_c4_frontier_parity():
         if "x" in p:
             assert np.abs(x - np.asarray(p["x"])).max() <= 1e-5, j
     banner(f"c4: worst relative objective error {worst:.2e}; iters max {max(i['iters'] for i in infos)}")
-    # bfloat16 storage of the same factor: solver parity is covered at small
-    # sizes; here the quantisation gap against the float32 frontier
-    Xb, infos_b = npga.solve_batched(npga.to_bf16(L), mu, rs)
+    # bfloat16 storage of the same factor, in the launch configuration the
+    # benchmark uses: solver error against the oracle run on the same
+    # bfloat16 values (tests/golden/c4_frontier_bf16.json) at every target,
+    # and the quantisation gap against the float32 frontier
+    Lb = npga.to_bf16(L)
+    best16, _ = npga.batched_tune(Lb, len(rs))
+    banner(f"c4 bf16: batched solve (config {best16})")
+    Xb, infos_b = npga.solve_batched(Lb, mu, rs, batch_config=best16)
     Xbh = Xb.cpu().numpy().astype(np.float64)
+    with open(GOLDEN_BF16) as fh:
+        refq = json.load(fh)
+    assert refq["targets"] == rs and refq["panel_sha256"] == ref["panel_sha256"]
+    from oracle import quantize as oq
+    Lq = oq.round_to_bf16(L_o.astype(np.float32))
+    worst_b = 0.0
+    for p in refq["points"]:
+        j = p["j"]
+        assert infos_b[j]["status"] == 0, (j, infos_b[j])
+        x = Xbh[j]
+        assert x.min() >= 0 and abs(x.sum() - 1) <= 1e-6
+        assert mu_o @ x >= rs[j] - 1e-6 * max(1.0, abs(rs[j]))
+        fq = factor_objective(Lq, 0.0, x)
+        rel = abs(fq - p["objective"]) / p["objective"]
+        worst_b = max(worst_b, rel)
+        assert rel <= 1e-6, (j, fq, p["objective"])
+        assert abs(infos_b[j]["objective"] - p["objective"]) <= 1e-6 * p["objective"], j
+        if "x" in p:
+            assert np.abs(x - np.asarray(p["x"])).max() <= 1e-5, j
     gaps = []
     for p in ref["points"]:
         j = p["j"]
-        assert infos_b[j]["status"] == 0
         gaps.append((factor_objective(L_o, 0.0, Xbh[j]) - p["objective"]) / p["objective"])
-    banner(f"c4 bf16: quantisation gap max {max(gaps):.2e} median {sorted(gaps)[len(gaps) // 2]:.2e}")
-    assert min(gaps) >= -1e-6 and max(gaps) <= 1e-2
+    banner(f"c4 bf16: solver error max {worst_b:.2e}; quantisation gap max {max(gaps):.2e} "
+           f"median {sorted(gaps)[len(gaps) // 2]:.2e}")
+    # observed gaps are <= 1.4e-6 on this frontier: the bar is ~100 times that
+    assert min(gaps) >= -1e-6 and max(gaps) <= 1e-4

@@ -120,3 +120,66 @@ def test_adjoint_two_asset_closed_form():
     assert np.abs(adj["dL"]).max() <= 1e-12
     np.testing.assert_allclose(adj["dmu"], [(g[0] - g[1]) * (-w / d), (g[0] - g[1]) * ((w - 1) / d)], rtol=1e-10)
     assert adj["dr"] == pytest.approx((g[0] - g[1]) / d, rel=1e-10)
+
+
+@pytest.mark.slow
+def test_adjoint_fd_at_config5_shape():
+    """The finite-difference check at the adjoint workload's own shape:
+    n = 200, T = 2000 (seed 5), r = 60th percentile of mu, loss = held-out
+    variance minus held-out mean return (5000 periods, seed 105), central
+    differences in float64 with h = 1e-6 on sampled mu entries (support and
+    off-support), on r and on sampled entries of L; every perturbed solve
+    must keep the face (support and return-row state) of the base solution."""
+    spec = gen.SPECS["c5fd"]
+    Rt = gen.returns_TxN(spec)
+    mu, L = ofactor.build_factor(Rt.T)
+    r = float(np.percentile(np.asarray(Rt, dtype=np.float64).mean(axis=0), 60))
+    Rh = gen.heldout_returns_TxN(spec, 5000, gen.factor_model.HELDOUT_SEED_C5)
+    mu_h, L_h = ofactor.build_factor(Rh.T)
+    A = L_h @ L_h.T
+
+    def loss(x):
+        return float(x @ A @ x - mu_h @ x)
+
+    n = spec.n
+    s, Q = _solve(L, 0.0, mu, r)
+    assert s["nu"] > 0, "want an active return constraint"
+    assert face_is_stable(Q, mu, s["x"], s["lam"], s["nu"])
+    x0 = s["x"]
+    adj = kkt_adjoint(L, 0.0, mu, r, x0, s["lam"], s["nu"], 2.0 * A @ x0 - mu_h)
+    supp = set(np.flatnonzero(x0 > 0).tolist())
+    h = 1e-6
+
+    def solve_at(Lp, mup, rp):
+        Qp = Lp @ Lp.T
+        sp = exact_mv(Qp, mup, rp, fista_tol=1e-12, x0=x0)
+        assert set(np.flatnonzero(sp["x"] > 0).tolist()) == supp   # same support at +-h
+        assert sp["nu"] > 0                                          # return row still in the face
+        return loss(sp["x"])
+
+    def fd(perturb):
+        lp = solve_at(*perturb(+h))
+        lm = solve_at(*perturb(-h))
+        return (lp - lm) / (2 * h)
+
+    rng = np.random.default_rng(205)
+    on = sorted(supp)
+    off = [i for i in range(n) if i not in supp]
+    idx = list(rng.choice(on, 6, replace=False)) + list(rng.choice(off, min(2, len(off)), replace=False))
+    scale_mu = np.abs(adj["dmu"]).max()
+    for i in idx:
+        def pm(d, i=int(i)):
+            m2 = mu.copy()
+            m2[i] += d
+            return L, m2, r
+        assert abs(fd(pm) - adj["dmu"][i]) <= 1e-6 * scale_mu, i   # observed ~1e-8
+    assert fd(lambda d: (L, mu, r + d)) == pytest.approx(adj["dr"], rel=1e-6)
+    scale_L = np.abs(adj["dL"]).max()
+    for _ in range(4):
+        i, t = int(rng.choice(on)), int(rng.integers(spec.T))
+
+        def pL(d, i=i, t=t):
+            L2 = L.copy()
+            L2[i, t] += d
+            return L2, mu, r
+        assert abs(fd(pL) - adj["dL"][i, t]) <= 1e-6 * scale_L, (i, t)
