@@ -476,6 +476,31 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
                   double *dl_dmu, float *dl_dL, int64_t ldg, npga_backward_result *res,
                   void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * npga_gradient_noalloc - npga_gradient without a workspace argument, for
+ * callers that cannot allocate device memory (code being captured into a
+ * HIP graph, serving loops that must not call the allocator).  Same result
+ * as npga_gradient on the same stream, bit for bit (same kernels, same
+ * launch shapes): g = 2 L_eff (L_eff^T x) + 2 gamma x, f = ||L_eff^T x||^2 +
+ * gamma ||x||^2.
+ *   f      (host) factor; any n <= NPGA_MAX_N and any cols fit
+ *   x      device n float32;  g  device n float64 (8-byte aligned) output
+ *   f_out  (host) objective, or NULL: then the call does not synchronise
+ *          `stream` and enqueues kernels only (capturable)
+ * Scratch: a file-scope device array of npga_gradient_noalloc_max_bytes()
+ * bytes (8.25 MiB), one per device, held until the process ends; the first
+ * call on a device looks up its address (make that call outside a graph
+ * capture).  Every call on a device uses the same array and overwrites the
+ * previous call's contents: calls that overlap on one device (two streams or
+ * two host threads) race and must be serialised by the caller.  Allocates
+ * nothing: no device, host or pinned allocation on any call.
+ * Errors: NPGA_ERR_INVALID (bad factor or pointers, nothing launched),
+ * NPGA_ERR_WORKSPACE (the request would not fit the array; cannot happen
+ * for a valid factor), NPGA_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+size_t npga_gradient_noalloc_max_bytes(void);
+int npga_gradient_noalloc(const npga_factor *f, const float *x, double *g, double *f_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -118,6 +118,8 @@ def _load():
         "npga_sketch_str_ex": (ctypes.c_int, [vp, i64, i64, i64, ctypes.POINTER(_StrOptions), vp, i64, vp,
                                               ctypes.POINTER(i64), ctypes.POINTER(dbl), vp, sz, vp]),
         "npga_philox_sketch": (ctypes.c_int, [u64, i64, i64, vp, i64, vp, vp]),
+        "npga_gradient_noalloc_max_bytes": (sz, []),
+        "npga_gradient_noalloc": (ctypes.c_int, [ctypes.POINTER(_Factor), vp, vp, vp, vp]),
         "npga_backward_workspace_size": (sz, [i64, i64]),
         "npga_backward": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, vp, vp, vp, vp, i64,
                                          ctypes.POINTER(_BackwardResult), vp, sz, vp]),
@@ -462,6 +464,21 @@ def gradient(L_TxN, x, gamma=0.0):
     _check(_lib.npga_gradient(ctypes.byref(f), _ptr(x), _ptr(g), ctypes.byref(fv), _ptr(ws),
                               ws.numel(), _stream()), "npga_gradient")
     return g, fv.value
+
+
+def gradient_noalloc(L_TxN, x, gamma=0.0, want_f=True):
+    """npga_gradient_noalloc: the same gradient as ``gradient`` with the
+    library's own per-device scratch array (no workspace).  With want_f =
+    False the call does not synchronise and f is None."""
+    Lb, n, cols, ld = _as_colmajor(L_TxN)
+    x = x.to(torch.float32).contiguous()
+    mu = torch.zeros(n, dtype=torch.float64, device=Lb.device)
+    g = torch.empty(n, dtype=torch.float64, device=Lb.device)
+    fv = ctypes.c_double(0.0)
+    f = _factor(Lb, n, cols, ld, mu, gamma)
+    _check(_lib.npga_gradient_noalloc(ctypes.byref(f), _ptr(x), _ptr(g), ctypes.byref(fv) if want_f else None,
+                                      _stream()), "npga_gradient_noalloc")
+    return g, (fv.value if want_f else None)
 
 
 def spectral_norm_sq(L_TxN, iters=30, seed=1, method="power", return_steps=False):

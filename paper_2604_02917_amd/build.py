@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libnpga.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["npga_api.cpp", "npga_solve.hip", "npga_factor.hip", "npga_syrk.hip", "npga_precise.hip", "npga_sketch.hip", "npga_batched.hip", "npga_batched16.hip", "npga_adjoint.hip", "npga_str.hip"]
+SOURCES = ["npga_api.cpp", "npga_solve.hip", "npga_factor.hip", "npga_syrk.hip", "npga_precise.hip", "npga_sketch.hip", "npga_batched.hip", "npga_batched16.hip", "npga_adjoint.hip", "npga_str.hip", "npga_noalloc.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
