@@ -174,7 +174,8 @@ typedef struct npga_result {
                              for (projection = 1), or the dual search could not
                              bracket nu and the solve was repeated with it          */
   int32_t backtracks;     /* trial steps refused by backtracking (main phase)       */
-  int32_t reserved3;
+  int32_t refine_fallback; /* 1 if the refinement's face updates did not settle and it
+                             finished with blocking face CG steps                   */
 } npga_result;
 
 /* Fill `opt` (host) with the defaults documented above. */

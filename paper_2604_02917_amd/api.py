@@ -76,7 +76,7 @@ class _Result(ctypes.Structure):
                 ("time_to_tol_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweep_samples", ctypes.c_int32),
                 ("dykstra_used", ctypes.c_int32), ("backtracks", ctypes.c_int32),
-                ("reserved3", ctypes.c_int32)]
+                ("refine_fallback", ctypes.c_int32)]
 
 
 def _load():

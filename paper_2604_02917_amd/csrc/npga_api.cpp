@@ -490,9 +490,11 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
 
   int refined = 0;
   int refine_iters = 0;
+  int refine_fallback = 0;
   if (main_done == npga::kConverged && o.refine && o.refine_max_iter > 0) {
-    // float64 gradient at the stopping point, then conjugate gradients on
-    // the identified face (the gradient is carried by linearity from there)
+    // float64 gradient at the stopping point, then the inexact primal-dual
+    // active-set method (CG on a face, sign rules for the face) with the
+    // gradient carried by linearity from there
     char *base = static_cast<char *>(ws);
     double *xa = reinterpret_cast<double *>(base + lay.off_xa);
     double *ga = reinterpret_cast<double *>(base + lay.off_ga);
@@ -504,16 +506,17 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
     LAUNCHCHK(npga::launch_precise_gradient(c.a, xa, ua, ga, reinterpret_cast<double *>(c.a.partials),
                                             slots, stream));
     c.a.ga = ga;
+    c.a.xa = xa;  // read by the refinement tails only (the objective from the anchor)
     c.a.pvec = vecs;
     c.a.fvec = vecs + npad;
     c.a.gvec = vecs + 2 * npad;
-    c.a.mode = npga::kTailCG;
     // rounds re-anchored in float64 at the previous round's result (removes
     // the drift of the gradient carried by linearity).  A round that ends
     // without the KKT test (stagnation of the float32 products, e.g. on a
     // badly conditioned face) switches the following rounds to float64
-    // products.
-    bool precise = false;
+    // products; a round whose face updates do not settle (x then projected
+    // onto F) switches them to the face CG with blocking steps.
+    bool precise = false, blocking = false;
     for (int round = 0; round < 4; ++round) {
       if (round > 0) {
         HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
@@ -530,12 +533,18 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
       Carved cr = c;
       cr.precise = precise;
       cr.uscratch = ua;
+      cr.a.mode = blocking ? npga::kTailCG : npga::kTailPdas;
       e = run_phase(cr, path, slots, o.check_every, ref_chunks, stream, pin, evs, ev0, &done, &rms, nullptr);
       if (e) return e;
       HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       refine_iters += pin[2].cg_iter;
       if (done != npga::kConverged) break;
+      if (!blocking && pin[2].pdas_failed) {
+        blocking = true;
+        refine_fallback = 1;
+        continue;
+      }
       if (pin[2].cg_kkt && round > 0) break;
       if (!pin[2].cg_kkt) precise = true;
     }
@@ -575,6 +584,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
     res->sweep_samples = tm.samples;
     res->dykstra_used = o.projection == 1 ? 1 : 0;
     res->backtracks = after_main.bt_rejections;
+    res->refine_fallback = refine_fallback;
   }
   return status;
 }

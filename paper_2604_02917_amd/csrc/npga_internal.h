@@ -31,7 +31,10 @@ enum TailMode : int32_t {
   kTailCG = 3,     // refinement: conjugate gradient on the identified face
   kTailAdj = 4,    // adjoint: projected conjugate gradient on the face's KKT system
   kTailLanczos = 5,  // Lanczos step for ||L_eff||_2^2 (step-size estimate)
+  kTailPdas = 6,   // refinement: inexact primal-dual active-set method (CG on the face)
 };
+
+constexpr int kPdasMaxOuter = 40;  // face updates of one refinement round before the fallback
 
 constexpr int kLanczosMax = 64;  // Lanczos steps kept in DevState
 
@@ -97,6 +100,12 @@ struct alignas(256) DevState {
   int32_t bt_consec;               // refusals of the current trial
   double lz_alpha[kLanczosMax];
   double lz_beta[kLanczosMax];
+  // inexact primal-dual active-set refinement
+  int32_t pdas_outer;              // face updates in the current round
+  int32_t pdas_final;              // 1: the face is settled, CG runs to the KKT tolerance
+  int32_t pdas_failed;             // 1: the round hit kPdasMaxOuter (x was projected onto F)
+  int32_t pdas_moved;              // indices moved by face updates in the current round
+  double pdas_eta2;                // inner CG tolerance ||r||^2 <= eta2 ||r_0||^2
   // adjoint results
   double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
   double adj_dgamma;         // dl/dgamma

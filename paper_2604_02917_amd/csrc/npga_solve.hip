@@ -465,7 +465,7 @@ __global__ __launch_bounds__(1024) void k_reduce(SolveArgs a) {
       gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
     } else if (a.mode == kTailGrad) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.xbuf0[i];
-    } else if (a.mode == kTailCG || a.mode == kTailAdj) {
+    } else if (a.mode == kTailCG || a.mode == kTailPdas || a.mode == kTailAdj) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.pvec[i];
     } else {
       a.gbuf0[i] = tot;
@@ -492,6 +492,13 @@ __global__ __launch_bounds__(64 * NW) void k_tail_cg(SolveArgs a) {
   __shared__ double mbuf[2 * NW];
   __shared__ int64_t ibuf[2 * NW];
   tail_cg<E, NW>(a, redbuf, mbuf, ibuf);
+}
+
+template <int E, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tail_pdas(SolveArgs a) {
+  if (a.st->done != kRunning) return;
+  __shared__ double redbuf[red_buf_doubles<NW>()];
+  tail_pdas<E, NW>(a, redbuf);
 }
 
 template <int E>
@@ -772,6 +779,17 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
 #undef CALL
       } else {
 #define CALL(E) hipLaunchKernelGGL((k_tail_cg<E, 4>), dim3(1), dim3(256), 0, s, a)
+        NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      }
+      break;
+    case kTailPdas:
+      if (wide) {
+#define CALL(E) hipLaunchKernelGGL((k_tail_pdas<E, NPGA_TAIL_WAVES>), dim3(1), dim3(64 * NPGA_TAIL_WAVES), 0, s, a)
+        NPGA_WIDE_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      } else {
+#define CALL(E) hipLaunchKernelGGL((k_tail_pdas<E, 4>), dim3(1), dim3(256), 0, s, a)
         NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
       }

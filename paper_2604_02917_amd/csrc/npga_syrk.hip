@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restri
     if (lane == 0) {
       if (a.mode == kTailPower || a.mode == kTailLanczos)
         gk[col] = (double)d;
-      else if (a.mode == kTailCG || a.mode == kTailAdj)
+      else if (a.mode == kTailCG || a.mode == kTailPdas || a.mode == kTailAdj)
         gk[col] = 2.0 * (double)d + 2.0 * st->gamma * pv[col];
       else
         gk[col] = 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col];

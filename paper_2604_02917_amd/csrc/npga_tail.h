@@ -682,13 +682,20 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 #pragma unroll
     for (int j = 0; j < E; ++j) w[j] = (tid + NT * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
     const ProjResult pr = project_F<E, false, NW>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    // objective from the float64 anchor as in tail_pdas (x^T g / 2 without one)
     double acc4[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
       const double d = w[j] - x[j];
       acc4[0] = fma(d, d, acc4[0]);
-      acc4[1] = fma(x[j], g[j], acc4[1]);
       acc4[2] += (x[j] > 0.0) ? 1.0 : 0.0;
+      if (i < n) {
+        const double xa = a.xa ? a.xa[i] : 0.0;
+        const double gaf = a.xa ? a.ga[i] + 2.0 * st->gamma * xa : 0.0;
+        acc4[1] = fma(xa, gaf, acc4[1]);
+        acc4[3] = fma(x[j] - xa, g[j] + gaf, acc4[3]);
+      }
     }
     red.sum(acc4);
     const double res = sqrt(acc4[0]);
@@ -696,7 +703,7 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
       st->residual = res;
       st->nu_c = pr.nu;
       st->tau_c = pr.tau;
-      st->objective = 0.5 * acc4[1];
+      st->objective = 0.5 * acc4[1] + 0.5 * acc4[3];
       st->support = (int32_t)acc4[2];
       st->lambda_kkt = -pr.tau / alpha;
       st->nu_kkt = pr.nu / alpha;
@@ -737,6 +744,316 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
     }
     if (block == 1) st->cg_blocked += 1;
     st->cg_active = active ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Float64 KKT refinement by an inexact primal-dual active-set method.
+//
+// The face of eq. mv is a guess of the support S and of the state of the
+// return constraint.  On a face, f restricted to {x_S : 1^T x_S = 1,
+// mu_S^T x_S = r (if held)} is minimised by conjugate gradients on the
+// projected gradient (multipliers by least squares, as in tail_cg), with no
+// step limit: entries may turn negative.  Once the projected gradient has
+// dropped by pdas_eta2 (or the face is settled and CG runs to the KKT
+// tolerance), the face is updated by the sign conditions of the KKT system
+// (the primal-dual active-set rule):
+//   * a free x_i <= 0 leaves S (x_i := 0);
+//   * a fixed index with reduced cost g_i - lam - nu mu_i < -1e-12 (the
+//     gradient's root mean square) enters S;
+//   * a held return row with nu < 0 is released, a free one with
+//     mu^T x < r is held;
+// and the equality rows are restored on the new face by adding c1 + c2 mu_i
+// to its entries.  The step to the new point needs H (x' - x): it is the
+// next sweep (pending step, as the projected-gradient step of tail_cg).
+// Many indices change per update, where blocking steps change one.  The
+// round ends when the face is unchanged, x > 0 on it and the projected
+// gradient is below 1e-10 of the gradient on S (KKT to rounding), or on
+// stagnation of the float32 products; after kPdasMaxOuter updates it
+// projects x onto F and reports the fallback (pdas_failed).
+// ---------------------------------------------------------------------------
+template <int E, int NW = 4>
+__device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
+  constexpr int NT = 64 * NW;
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  const int cur = st->iter & 1;
+  double *x_p = cur ? a.xbuf1 : a.xbuf0;
+  double *xo_p = cur ? a.xbuf0 : a.xbuf1;  // the pending point of a face update
+  BlockReducer<5, NW> red{redbuf, 0};
+  const double r = st->r;
+  const bool pending = st->cg_pg != 0;
+
+  double x[E], g[E], p[E], hp[E], mu[E], fr[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + NT * j;
+    const bool ok = i < n;
+    x[j] = ok ? (pending ? xo_p[i] : x_p[i]) : 0.0;
+    g[j] = ok ? a.gvec[i] : 0.0;
+    p[j] = ok ? a.pvec[i] : 0.0;
+    hp[j] = ok ? a.gbuf0[i] : 0.0;
+    mu[j] = ok ? a.mu[i] : 0.0;
+    fr[j] = ok ? a.fvec[i] : 0.0;
+  }
+  bool active = st->cg_active != 0;
+
+  if (pending) {
+    // the face update is taken: x <- x', g <- g + H (x' - x); CG restarts
+    // on the new face (fvec already holds it)
+#pragma unroll
+    for (int j = 0; j < E; ++j) g[j] += hp[j];
+    double lam, nu;
+    face_multipliers<E, NW>(g, mu, fr, active, red, lam, nu);
+    double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      p[j] = (fr[j] > 0.0) ? -(g[j] - lam - nu * mu[j]) : 0.0;
+      acc[0] = fma(p[j], p[j], acc[0]);
+    }
+    red.sum(acc);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      if (i < n) {
+        x_p[i] = x[j];
+        a.gvec[i] = g[j];
+        a.pvec[i] = p[j];
+        a.xs[i] = (float)p[j];
+      }
+    }
+    if (tid == 0) {
+      st->cg_pg = 0;
+      st->cg_rr = acc[0];
+      st->cg_rr0 = acc[0];
+      st->cg_best_rr = acc[0];
+      st->cg_iter += 1;
+      st->cg_best_it = st->cg_iter;
+      if (st->cg_iter >= st->max_iter) st->done = kMaxIter;
+    }
+    return;
+  }
+
+  // (1) CG step on the face, not limited by x >= 0
+  const double rr = st->cg_rr;
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) acc[0] = fma(fr[j] * p[j], hp[j], acc[0]);
+  red.sum(acc);
+  const double php = acc[0];
+  const double step = (php > 0.0 && rr > 0.0) ? rr / php : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    x[j] = fma(step * fr[j], p[j], x[j]);
+    g[j] = fma(step, hp[j], g[j]);
+  }
+  // (2) multipliers and projected gradient
+  double lam, nu;
+  face_multipliers<E, NW>(g, mu, fr, active, red, lam, nu);
+  double rv[E];
+  double acc2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    rv[j] = (fr[j] > 0.0) ? -(g[j] - lam - nu * mu[j]) : 0.0;
+    acc2[0] = fma(rv[j], rv[j], acc2[0]);
+    acc2[1] = fma(fr[j] * g[j], g[j], acc2[1]);
+    acc2[2] = fma(g[j], g[j], acc2[2]);
+  }
+  red.sum(acc2);
+  const double rr_new = acc2[0], gs2 = acc2[1];
+  const double gscale = sqrt(acc2[2] / (double)n) + 1e-300;
+  const int it = st->cg_iter + 1;
+  double best = st->cg_best_rr;
+  int best_it = st->cg_best_it;
+  if (rr_new < 0.5 * best) {
+    best = rr_new;
+    best_it = it;
+  }
+  const bool stalled = it - best_it > st->cg_window;
+  const bool tight = rr_new <= 1e-20 * gs2;
+  const bool inner_done = tight || stalled || (!st->pdas_final && rr_new <= st->pdas_eta2 * st->cg_rr0);
+
+  int face_change = 0;
+  bool act_new = active;
+  if (inner_done) {
+    // (3) sign conditions of the KKT system on the current point
+    double cnt[5] = {0, 0, 0, 0, 0};  // leaving, entering, mu^T x
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      const double d = g[j] - lam - nu * mu[j];
+      cnt[0] += (fr[j] > 0.0 && x[j] <= 0.0) ? 1.0 : 0.0;
+      cnt[1] += (i < n && fr[j] == 0.0 && d < -1e-12 * gscale) ? 1.0 : 0.0;
+      cnt[2] = fma(mu[j], x[j], cnt[2]);
+    }
+    red.sum(cnt);
+    if (active && nu < 0.0) act_new = false;
+    if (!active && cnt[2] < r - st->tolphi) act_new = true;
+    face_change = (cnt[0] > 0.0 || cnt[1] > 0.0 || act_new != active) ? 1 : 0;
+    if (face_change && st->pdas_outer < kPdasMaxOuter) {
+      // (4) the new face and the point x' on it: leaving entries set to 0,
+      // the equality rows restored by c1 + c2 mu_i on the new free set
+      double fn[E], xn[E];
+      double s[5] = {0, 0, 0, 0, 0};  // |S'|, sum mu, sum mu^2, sum x', sum mu x'
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t i = tid + NT * j;
+        const double d = g[j] - lam - nu * mu[j];
+        const bool leave = fr[j] > 0.0 && x[j] <= 0.0;
+        const bool enter = i < n && fr[j] == 0.0 && d < -1e-12 * gscale;
+        fn[j] = ((fr[j] > 0.0 && !leave) || enter) ? 1.0 : 0.0;
+        xn[j] = (fn[j] > 0.0) ? x[j] : 0.0;
+        s[0] += fn[j];
+        s[1] = fma(fn[j], mu[j], s[1]);
+        s[2] = fma(fn[j] * mu[j], mu[j], s[2]);
+        s[3] += xn[j];
+        s[4] = fma(mu[j], xn[j], s[4]);
+      }
+      red.sum(s);
+      const double b1 = 1.0 - s[3], b2 = r - s[4];
+      double c1 = (s[0] > 0.0) ? b1 / s[0] : 0.0, c2 = 0.0;
+      if (act_new && s[0] > 1.5) {
+        const double det = s[0] * s[2] - s[1] * s[1];
+        if (det > 1e-30 * s[0] * s[2]) {
+          c1 = (s[2] * b1 - s[1] * b2) / det;
+          c2 = (s[0] * b2 - s[1] * b1) / det;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t i = tid + NT * j;
+        if (fn[j] > 0.0) xn[j] += c1 + c2 * mu[j];
+        if (i < n) {
+          xo_p[i] = xn[j];
+          x_p[i] = x[j];
+          a.gvec[i] = g[j];
+          a.pvec[i] = xn[j] - x[j];
+          a.fvec[i] = fn[j];
+          a.xs[i] = (float)(xn[j] - x[j]);
+        }
+      }
+      if (tid == 0) {
+        st->cg_pg = 1;
+        st->cg_active = act_new ? 1 : 0;
+        st->pdas_outer += 1;
+        st->pdas_final = 0;
+        st->pdas_moved += (int32_t)(cnt[0] + cnt[1]);
+        st->cg_iter = it;
+        st->cg_rr = rr_new;
+        if (it >= st->max_iter) st->done = kMaxIter;
+      }
+      return;
+    }
+  }
+
+  // (5) end of the round: the KKT conditions hold on a settled face, the
+  // float32 products stagnate, or too many face updates (fallback: project
+  // x onto F and report it)
+  const bool kkt = inner_done && !face_change && tight;
+  const bool give_up = inner_done && face_change;  // kPdasMaxOuter reached
+  const bool stop = kkt || (inner_done && stalled) || give_up;
+  if (stop) {
+    const double alpha = st->alpha;
+    double w[E];
+    ProjResult pr{0.0, 0.0, 0, 0};
+    if (give_up) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) x[j] = (tid + NT * j < n) ? x[j] : -1.0e300;
+      pr = project_F<E, false, NW>(x, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    } else {
+      // entries below float64 rounding of the largest are zeros (a face
+      // that keeps an index the equality rows force to zero, e.g. at a
+      // vertex, leaves ~1e-16 there)
+      // largest entry: wave maxima, then the wave results through the last
+      // NW doubles of redbuf (unused by the sum reductions outside a pass)
+      double m2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) m2 = fmax(m2, x[j]);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off, 64));
+      double *mb = redbuf + red_buf_doubles<NW>() - NW;
+      if ((tid & 63) == 0) mb[tid >> 6] = m2;
+      __syncthreads();
+      double xmax = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) xmax = fmax(xmax, mb[w2]);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < E; ++j) x[j] = (x[j] <= 1e-13 * xmax) ? 0.0 : x[j];
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) w[j] = (tid + NT * j < n) ? fma(-alpha, g[j], x[j]) : -1.0e300;
+    pr = project_F<E, false, NW>(w, mu, r, st->tolphi, st->nu_c, st->tau_c, red);
+    // f(x) = f(x_a) + (x - x_a)^T (g(x) + g(x_a))/2 for the quadratic f: the
+    // float32 drift of the carried gradient g then enters through the small
+    // move from the float64 anchor only (x^T g / 2 would take all of it).
+    // ga = 2 L L^T x_a excludes the ridge.  Without an anchor (xa null)
+    // this is x^T g / 2.
+    double acc4[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      const double d = w[j] - x[j];
+      acc4[0] = fma(d, d, acc4[0]);
+      acc4[2] += (x[j] > 0.0) ? 1.0 : 0.0;
+      if (i < n) {
+        const double xa = a.xa ? a.xa[i] : 0.0;
+        const double gaf = a.xa ? a.ga[i] + 2.0 * st->gamma * xa : 0.0;
+        acc4[1] = fma(xa, gaf, acc4[1]);
+        acc4[3] = fma(x[j] - xa, g[j] + gaf, acc4[3]);
+      }
+    }
+    red.sum(acc4);
+    const double res = sqrt(acc4[0]);
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      if (i < n) {
+        x_p[i] = x[j];
+        a.gvec[i] = g[j];
+      }
+    }
+    if (tid == 0) {
+      st->residual = res;
+      st->nu_c = pr.nu;
+      st->tau_c = pr.tau;
+      st->objective = 0.5 * acc4[1] + 0.5 * acc4[3];
+      st->support = (int32_t)acc4[2];
+      st->lambda_kkt = -pr.tau / alpha;
+      st->nu_kkt = pr.nu / alpha;
+      st->proj_flags |= pr.flags;
+      st->cg_iter = it;
+      st->cg_rr = rr_new;
+      st->cg_active = active ? 1 : 0;
+      st->cg_kkt = kkt ? 1 : 0;
+      st->pdas_failed = give_up ? 1 : 0;
+      st->done = isfinite(res) ? kConverged : kNumeric;
+    }
+    return;
+  }
+  if (inner_done && tid == 0) st->pdas_final = 1;  // settled face: solve it to the KKT tolerance
+
+  // (6) next direction
+  const double beta = (rr > 0.0) ? rr_new / rr : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + NT * j;
+    p[j] = fma(beta, p[j], rv[j]);
+    if (i < n) {
+      x_p[i] = x[j];
+      a.gvec[i] = g[j];
+      a.pvec[i] = p[j];
+      a.xs[i] = (float)p[j];
+    }
+  }
+  if (tid == 0) {
+    st->cg_iter = it;
+    st->cg_rr = rr_new;
+    st->cg_best_rr = best;
+    st->cg_best_it = best_it;
+    if (!isfinite(rr_new)) st->done = kNumeric;
+    else if (it >= st->max_iter) st->done = kMaxIter;
   }
 }
 
@@ -833,6 +1150,11 @@ __device__ void cg_init_body(const SolveArgs &a, double *redbuf) {
     st->cg_kkt = 0;
     st->cg_pg = 0;
     st->ticket = 0u;
+    st->pdas_outer = 0;
+    st->pdas_final = 0;
+    st->pdas_failed = 0;
+    st->pdas_moved = 0;
+    st->pdas_eta2 = 1e-6;  // inner solves to 1e-3 of their initial projected gradient
   }
 }
 
