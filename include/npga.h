@@ -65,7 +65,9 @@ typedef enum npga_status {
 } npga_status;
 
 typedef enum npga_path {
-  NPGA_PATH_AUTO = 0, /* choose GEMV or SYRK from the shape                   */
+  NPGA_PATH_AUTO = 0, /* SYRK for a float32 factor with cols >= n whose SYRK
+                         workspace (Sigma + the split planes of L, about 1.5 L)
+                         is at most 4 GiB; GEMV otherwise (npga_auto_path)      */
   NPGA_PATH_GEMV = 1, /* grad = 2 L (L^T x): one fused sweep over L per step */
   NPGA_PATH_SYRK = 2  /* Sigma = L L^T once (MFMA), then grad = 2 Sigma x     */
 } npga_path;
@@ -144,6 +146,13 @@ typedef struct npga_options {
                             of sum |d|(|grad f(x)| + |grad f(y)|) allowed for the
                             float32 products), else alpha <- rho alpha and the step
                             is redone.  Single solves only (batched: INVALID)      */
+  int32_t refine_method; /* refinement of a single solve: 0 (default) = choose from the
+                            shape (below); 1 = inexact primal-dual active-set method:
+                            CG on a face without step limits, the face then moved by
+                            the KKT sign rules, several indices at once (falls back to 2
+                            when the face does not settle); 2 = face CG with blocking
+                            steps (one index fixed per block)                        */
+  int32_t reserved_opt;
 } npga_options;
 
 /* Result of a solve (host). */
@@ -241,6 +250,15 @@ int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb,
  * Synchronises `stream`.
  * ------------------------------------------------------------------------- */
 size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *opt);
+
+/* The path NPGA_PATH_AUTO runs for a factor of this shape and npga_dtype
+ * (Sec. 3.1: the factor form costs O(n cols) per iteration, the explicit
+ * covariance O(n^2) after an O(n^2 cols) product): NPGA_PATH_SYRK when dtype
+ * is NPGA_F32, cols >= n and the covariance path's workspace is at most
+ * 4 GiB, else NPGA_PATH_GEMV; -1 for an invalid shape or dtype.  Host only.
+ * npga_solve_workspace_size with opt->path = AUTO (or opt NULL) sizes for
+ * the float32 choice, which also covers a bfloat16 factor (GEMV).           */
+int npga_auto_path(int64_t n, int64_t cols, int32_t dtype);
 int npga_solve(const npga_factor *f, double r, const npga_options *opt, float *x,
                npga_result *res, void *ws, size_t ws_bytes, hipStream_t stream);
 

@@ -8,6 +8,7 @@ package loads the library and raises if it is missing: there is no fallback.
 from .api import (  # noqa: F401
     NPGAFunction,
     NpgaError,
+    auto_path,
     Options,
     backward,
     batched_tune,
@@ -15,6 +16,7 @@ from .api import (  # noqa: F401
     solve_batched,
     build_factor,
     gradient,
+    gradient_noalloc,
     lib_path,
     project,
     project_dykstra,

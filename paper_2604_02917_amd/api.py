@@ -46,7 +46,8 @@ class _Options(ctypes.Structure):
                 ("momentum", ctypes.c_int32), ("step_estimator", ctypes.c_int32),
                 ("batch_config", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("projection", ctypes.c_int32), ("dykstra_iters", ctypes.c_int32),
-                ("backtrack_rho", ctypes.c_double)]
+                ("backtrack_rho", ctypes.c_double), ("refine_method", ctypes.c_int32),
+                ("reserved_opt", ctypes.c_int32)]
 
 
 class _StrOptions(ctypes.Structure):
@@ -92,6 +93,7 @@ def _load():
         "npga_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "npga_struct_size": (sz, [i32]),
         "npga_solve_workspace_size": (sz, [i64, i64, ctypes.POINTER(_Options)]),
+        "npga_auto_path": (ctypes.c_int, [i64, i64, i32]),
         "npga_solve": (ctypes.c_int, [ctypes.POINTER(_Factor), dbl, ctypes.POINTER(_Options), vp,
                                       ctypes.POINTER(_Result), vp, sz, vp]),
         "npga_project": (ctypes.c_int, [vp, vp, i64, dbl, vp, vp, vp, sz, vp]),
@@ -164,6 +166,7 @@ class Options:
     projection: str = "exact"   # or "dykstra" (alternating projections only)
     dykstra_iters: int = 5000
     backtrack_rho: float = 0.0   # in (0, 1): adaptive backtracking from the trial step
+    refine_method: str = "auto"   # "auto", "pdas" (primal-dual active set) or "cg" (blocking face CG)
 
     def _c(self):
         o = _Options()
@@ -180,6 +183,7 @@ class Options:
         o.projection = {"exact": 0, "dykstra": 1}[self.projection]
         o.dykstra_iters = self.dykstra_iters
         o.backtrack_rho = self.backtrack_rho
+        o.refine_method = {"auto": 0, "pdas": 1, "cg": 2}[self.refine_method]
         return o
 
 
@@ -233,6 +237,14 @@ def build_factor(R_TxN):
     _check(_lib.npga_build_factor(_ptr(Rb), n, T, ld, _ptr(L), ld, _ptr(mu), _ptr(ws), ws.numel(),
                                   _stream()), "npga_build_factor")
     return (L if ld == n else L[:, :n]), mu
+
+
+def auto_path(n, cols, dtype="f32"):
+    """The path npga_solve's AUTO runs for this shape: "gemv" or "syrk"."""
+    code = _lib.npga_auto_path(int(n), int(cols), {"f32": 0, "bf16": 1}[dtype])
+    if code < 0:
+        raise ValueError("invalid shape or dtype")
+    return {1: "gemv", 2: "syrk"}[code]
 
 
 def solve(L_TxN, mu, r, gamma=0.0, x0=None, options=None, **kw):

@@ -111,11 +111,23 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
 
 namespace {
 
-int resolve_path(int requested, int64_t n, int64_t cols) {
+// NPGA_PATH_AUTO: the explicit covariance (Sigma = L L^T once, then one SYMV
+// per iteration) when the factor has at least as many columns as rows and
+// is float32, and its workspace (Sigma plus the bfloat16 planes of L the
+// SYRK reads, about 1.5 times L) stays within kAutoSyrkMaxBytes; else the
+// fused sweep.  Measured on MI355X over n = 64 ... 8192, T/n = 0.5 ... 16
+// (solves to residual 1e-6 with the refinement): with T >= n the covariance
+// path's whole solve is 1.1-2.9 times faster (n = 5440, T = 48374: 22.6
+// against 38.4 ms) and its time to 1e-6 no slower; with T = n/2 the sweep
+// reads half of Sigma's bytes per iteration and wins (n = 5440: 913 against
+// 1044 ms).
+constexpr size_t kAutoSyrkMaxBytes = (size_t)4 << 30;
+
+int resolve_path(int requested, int64_t n, int64_t cols, int dtype = NPGA_F32) {
   if (requested == NPGA_PATH_GEMV || requested == NPGA_PATH_SYRK) return requested;
-  (void)n;
-  (void)cols;
-  return NPGA_PATH_GEMV;
+  if (dtype != NPGA_F32 || cols < n) return NPGA_PATH_GEMV;
+  const SolveLayout l = npga::solve_layout(n, cols, NPGA_PATH_SYRK);
+  return l.total <= kAutoSyrkMaxBytes ? NPGA_PATH_SYRK : NPGA_PATH_GEMV;
 }
 
 bool options_valid(const npga_options &o) {
@@ -126,7 +138,7 @@ bool options_valid(const npga_options &o) {
          o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1) &&
          (o.step_estimator == 0 || o.step_estimator == 1) && is_fin(o.alpha) && o.alpha >= 0.0 &&
          (o.projection == 0 || o.projection == 1) && o.dykstra_iters >= 1 && is_fin(o.backtrack_rho) &&
-         o.backtrack_rho >= 0.0 && o.backtrack_rho < 1.0;
+         o.backtrack_rho >= 0.0 && o.backtrack_rho < 1.0 && o.refine_method >= 0 && o.refine_method <= 2;
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -148,6 +160,17 @@ struct Carved {
   bool precise = false;       // refinement steps with float64 products (H p by two float64 passes)
   double *uscratch = nullptr; // cols doubles for those passes
 };
+
+// Refinement method for refine_method = 0.  The primal-dual active-set
+// updates need inner solves accurate enough for the sign of every entry; a
+// factor with fewer columns than assets (the STR model, a short panel, with
+// a ridge) gives a face Hessian with a large cluster at 2 gamma far below
+// the rest, which the float32 products resolve poorly, and the face updates
+// do not settle.  Measured on MI355X (parity-grade solve, ms): cols >= n
+// favours the active-set updates (n = 5440: T = 48374 38 vs 66, T = 8160 27
+// vs 101, T = 5440 35 vs 133), cols < n the blocking CG (STR with ell = 512:
+// 8.8 vs 27.8; n = 1000, T = 500: 86 vs 141).
+bool pdas_suits(int64_t n, int64_t cols) { return cols >= n; }
 
 Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
   char *base = static_cast<char *>(ws);
@@ -380,6 +403,8 @@ void npga_default_options(npga_options *o) {
   o->projection = 0;
   o->dykstra_iters = 5000;
   o->backtrack_rho = 0.0;
+  o->refine_method = 0;
+  o->reserved_opt = 0;
 }
 
 size_t npga_struct_size(int32_t which) {
@@ -408,6 +433,11 @@ const char *npga_status_string(int status) {
   }
 }
 
+int npga_auto_path(int64_t n, int64_t cols, int32_t dtype) {
+  if (n < 1 || n > NPGA_MAX_N || cols < 1 || (dtype != NPGA_F32 && dtype != NPGA_BF16)) return -1;
+  return resolve_path(NPGA_PATH_AUTO, n, cols, dtype);
+}
+
 size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *opt) {
   if (n < 1 || n > NPGA_MAX_N || cols < 1) return 0;
   npga_options o;
@@ -425,7 +455,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
   if (opt) o = *opt;
   if (!factor_valid(f) || !x || !is_fin(r) || !options_valid(o)) return NPGA_ERR_INVALID;
   if (o.momentum == 1 && !(f->gamma > 0.0)) return NPGA_ERR_INVALID;
-  const int path = resolve_path(o.path, f->n, f->cols);
+  const int path = resolve_path(o.path, f->n, f->cols, f->dtype);
   if (path == NPGA_PATH_SYRK && f->dtype != NPGA_F32) return NPGA_ERR_UNSUPPORTED;
   const SolveLayout lay = npga::solve_layout(f->n, f->cols, path);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
@@ -516,7 +546,8 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
     // badly conditioned face) switches the following rounds to float64
     // products; a round whose face updates do not settle (x then projected
     // onto F) switches them to the face CG with blocking steps.
-    bool precise = false, blocking = false;
+    bool precise = false;
+    bool blocking = o.refine_method == 2 || (o.refine_method == 0 && !pdas_suits(f->n, f->cols));
     for (int round = 0; round < 4; ++round) {
       if (round > 0) {
         HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));

@@ -35,7 +35,8 @@ def test_backtracking_trajectory_matches_oracle(npga, n, T, q):
     Ld, mud = npga.build_factor(to_dev(Rt))
     for k in (1, 2, 5, 10, 30):
         ref = onpga.npga(model, mu, r, a0, np.full(n, 1.0 / n), tol=0.0, check_every=5, max_iter=k, backtrack=rho)
-        x, info = npga.solve(Ld, mud, r, alpha=a0, backtrack_rho=rho, max_iter=k, refine=False, tol=1e-300)
+        x, info = npga.solve(Ld, mud, r, alpha=a0, backtrack_rho=rho, max_iter=k, refine=False, tol=1e-300,
+                             path="gemv")
         err = float(np.abs(x.cpu().numpy().astype(np.float64) - ref["x"]).max())
         banner(f"backtracking n={n} k={k}: refusals gpu {info['backtracks']} oracle {ref['rejections']}, "
                f"alpha*L_f gpu {info['alpha'] * lf:.4f} oracle {ref['alpha'] * lf:.4f}, |dx| {err:.1e}")
@@ -53,7 +54,7 @@ def test_backtracking_solve_reaches_the_minimiser(npga):
     ref = exact_mv_factor(L, 0.0, mu, r)
     lf = onpga.FactorModel(L).lipschitz_exact()
     Ld, mud = npga.build_factor(to_dev(Rt))
-    x, info = npga.solve(Ld, mud, r, alpha=16.0 / lf, backtrack_rho=0.5)
+    x, info = npga.solve(Ld, mud, r, alpha=16.0 / lf, backtrack_rho=0.5, path="gemv")
     banner(f"backtracking solve: {info['iters']} iterations, {info['backtracks']} refusals, "
            f"alpha*L_f {info['alpha'] * lf:.3f}")
     assert info["status"] == 0 and info["backtracks"] >= 1

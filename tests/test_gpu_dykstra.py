@@ -53,8 +53,8 @@ def test_solve_with_dykstra_projections(npga, n, T, q):
     r = float(np.quantile(mu, q))
     ref = exact_mv_factor(L, 0.0, mu, r)
     Ld, mud = npga.build_factor(to_dev(Rt))
-    x, info = npga.solve(Ld, mud, r, projection="dykstra")
-    x_e, info_e = npga.solve(Ld, mud, r)
+    x, info = npga.solve(Ld, mud, r, projection="dykstra", path="gemv")
+    x_e, info_e = npga.solve(Ld, mud, r, path="gemv")
     banner(f"dykstra solve n={n}: iters {info['iters']} (exact {info_e['iters']}), refined {info['refined']}")
     assert info["status"] == 0 and info["dykstra_used"] == 1 and info_e["dykstra_used"] == 0
     xh = x.cpu().numpy().astype(np.float64)

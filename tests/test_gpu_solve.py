@@ -153,3 +153,20 @@ def test_warm_start_from_solution(npga):
     x2, info2 = npga.solve(L, mu, r, x0=x)
     assert info2["iters"] <= 5
     assert torch.allclose(x, x2, atol=1e-6)
+
+
+@pytest.mark.parametrize("n,T,want", [(300, 3000, 2), (500, 520, 2), (500, 480, 1)])
+def test_auto_path_parity(npga, n, T, want):
+    """NPGA_PATH_AUTO takes the covariance path at T >> n and T ~ n (T >= n)
+    and the fused sweep at T < n; either way the result matches the oracle."""
+    banner(f"auto path n={n} T={T}")
+    spec = spec_with("c2", n, T, seed=41 + n)
+    Rt, r, mu_ref, L_ref, ref = _case(spec, q=0.6)
+    gamma = 0.0
+    if T < n:
+        gamma = 1e-4 * float(np.trace(L_ref @ L_ref.T)) / n
+        ref = exact_mv_factor(L_ref, gamma, mu_ref, r)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, gamma=gamma)
+    assert info["status"] == 0 and info["path_used"] == want, info
+    _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, gamma, ref, f"auto {n}x{T}")

@@ -4,7 +4,11 @@ exactly k steps (max_iter = k, no refinement) matches the oracle's x^k, not
 only the limit.  The GPU computes the gradient at y^k from those at x^k and
 x^{k-1} by linearity and in float32 products; the trajectories agree to
 about 5e-9 over 60 steps (bar 1e-7; 1e-6 for the batched matrix-core
-products)."""
+products).  On the covariance path Sigma = L L^T is formed once, to float32
+accuracy (entries within ~4e-7 relative): a fixed perturbation of the
+quadratic that the momentum iteration carries from step to step, where the
+sweep's rounding is fresh each step; there the trajectories agree to about
+1e-7 at n = 37, T = 100 (bar 1e-6)."""
 import numpy as np
 import pytest
 
@@ -39,22 +43,23 @@ def _setup(n, T, seed, q):
     return Rt, mu, L, r, model, alpha
 
 
+@pytest.mark.parametrize("path", ["gemv", "syrk"])
 @pytest.mark.parametrize("n,T,q", [(64, 256, 0.6), (300, 1000, 0.8), (37, 100, 0.3)])
-def test_trajectory_matches_oracle(npga, n, T, q):
+def test_trajectory_matches_oracle(npga, n, T, q, path):
     Rt, mu, L, r, model, alpha = _setup(n, T, 900 + n, q)
     Ld, mud = npga.build_factor(to_dev(Rt))
     worst = 0.0
     for k in KS:
         ref = onpga.npga(model, mu, r, alpha, np.full(n, 1.0 / n), tol=0.0, check_every=5, max_iter=k)
         assert not ref["converged"] and ref["iters"] == k
-        x, info = npga.solve(Ld, mud, r, alpha=alpha, max_iter=k, refine=False, tol=1e-300)
+        x, info = npga.solve(Ld, mud, r, alpha=alpha, max_iter=k, refine=False, tol=1e-300, path=path)
         assert info["status"] == 3 and info["iters"] == k and info["alpha"] == alpha, info
         xh = x.cpu().numpy().astype(np.float64)
         assert xh.min() >= 0.0 and abs(xh.sum() - 1.0) <= 1e-6
         err = float(np.abs(xh - ref["x"]).max())
         worst = max(worst, err)
-        assert err <= 1e-7, (k, err)
-    banner(f"trajectory n={n} T={T}: max |x_gpu^k - x_oracle^k| over k in {KS} = {worst:.2e}")
+        assert err <= (1e-7 if path == "gemv" else 1e-6), (k, err)
+    banner(f"trajectory n={n} T={T} {path}: max |x_gpu^k - x_oracle^k| over k in {KS} = {worst:.2e}")
 
 
 def test_batched_trajectory_matches_oracle(npga):
@@ -103,7 +108,7 @@ def test_full_model_trajectory(npga):
     del Rt
     for k in (1, 4, 10):
         ref = onpga.npga(model, mu, r, alpha, np.full(n, 1.0 / n), tol=0.0, check_every=5, max_iter=k)
-        x, info = npga.solve(Ld, mud, r, alpha=alpha, max_iter=k, refine=False, tol=1e-300)
+        x, info = npga.solve(Ld, mud, r, alpha=alpha, max_iter=k, refine=False, tol=1e-300, path="gemv")
         assert info["status"] == 3 and info["iters"] == k
         err = float(np.abs(x.cpu().numpy().astype(np.float64) - ref["x"]).max())
         banner(f"full-model trajectory k={k}: max |x_gpu^k - x_oracle^k| = {err:.2e}")

@@ -72,7 +72,10 @@ def test_workspace_sizes():
     # the batched workspace holds the single-solve region plus per-target buffers
     b1 = lib.npga_batched_workspace_size(2000, 20000, 1, None)
     b128 = lib.npga_batched_workspace_size(2000, 20000, 128, None)
-    assert b128 > b1 > lib.npga_solve_workspace_size(2000, 20000, None)
+    og = api._Options()
+    lib.npga_default_options(ctypes.byref(og))
+    og.path = 1   # the batched solver runs the fused sweep's layout
+    assert b128 > b1 > lib.npga_solve_workspace_size(2000, 20000, ctypes.byref(og))
     assert lib.npga_batched_workspace_size(2000, 20000, 0, None) == 0
     assert lib.npga_batched_workspace_size(2000, 20000, 1025, None) == 0
     assert lib.npga_build_factor_workspace_size(64, 1) == 0
@@ -117,7 +120,10 @@ def test_invalid_arguments_rejected_before_launch():
                              ctypes.c_void_p(16), 63, None, null, 0, null) == 1      # ldg < n
     assert lib.npga_backward(ctypes.byref(f), 0.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              null, 64, None, null, 0, null) == 6                     # no workspace
-    assert lib.npga_backward_workspace_size(64, 256) > lib.npga_solve_workspace_size(64, 256, None)
+    og = api._Options()
+    lib.npga_default_options(ctypes.byref(og))
+    og.path = 1   # the adjoint runs on the fused sweep's layout
+    assert lib.npga_backward_workspace_size(64, 256) > lib.npga_solve_workspace_size(64, 256, ctypes.byref(og))
     # a negative or non-finite fixed step is rejected
     o.alpha = -1.0
     assert lib.npga_solve_batched(ctypes.byref(f), r, 1, ctypes.byref(o), ctypes.c_void_p(16), 64, None,
@@ -147,3 +153,33 @@ def test_build_script_runs_without_importing_the_package():
     assert "from ." not in src
     entry = open(os.path.join(ROOT, "__graft_entry__.py")).read()
     assert "spec_from_file_location" in entry
+
+
+def test_auto_path_rule():
+    """NPGA_PATH_AUTO: the covariance path for a float32 factor with at least
+    as many columns as assets (measured faster there), within its 4 GiB
+    workspace bound; the fused sweep for fewer columns (an STR factor), a
+    bfloat16 factor, or a covariance workspace past the bound."""
+    from paper_2604_02917_amd import api
+    lib = api._lib
+    F32, BF16, GEMV, SYRK = 0, 1, 1, 2
+    assert lib.npga_auto_path(5440, 48374, F32) == SYRK      # the full model, T >> n
+    assert lib.npga_auto_path(5440, 5440, F32) == SYRK       # T = n
+    assert lib.npga_auto_path(5440, 5439, F32) == GEMV       # T < n
+    assert lib.npga_auto_path(5440, 512, F32) == GEMV        # an STR factor (ell = 512)
+    assert lib.npga_auto_path(5440, 48374, BF16) == GEMV     # the covariance path needs float32
+    assert lib.npga_auto_path(64, 256, F32) == SYRK
+    assert lib.npga_auto_path(8192, 100000, F32) == GEMV     # Sigma + planes ~ 5.2 GB > 4 GiB
+    assert lib.npga_auto_path(0, 10, F32) == -1 and lib.npga_auto_path(10, 10, 7) == -1
+    # the workspace query sizes for the path AUTO takes
+    o = api._Options()
+    lib.npga_default_options(ctypes.byref(o))
+    assert o.path == 0
+    auto = lib.npga_solve_workspace_size(5440, 48374, ctypes.byref(o))
+    o.path = SYRK
+    assert auto == lib.npga_solve_workspace_size(5440, 48374, ctypes.byref(o))
+    o.path = 0
+    small = lib.npga_solve_workspace_size(5440, 512, ctypes.byref(o))
+    o.path = GEMV
+    assert small == lib.npga_solve_workspace_size(5440, 512, ctypes.byref(o)) < auto
+    assert api.auto_path(5440, 48374) == "syrk" and api.auto_path(5440, 48374, "bf16") == "gemv"
