@@ -49,10 +49,22 @@ def parse():
     return ap.parse_args()
 
 
+def _device_function_texts(src, names):
+    """Source text of the named device helpers (every definition, in order)."""
+    import re
+    out = []
+    for name in names:
+        pat = (r"(?:template <[^>]*>\n)?__device__ __forceinline__ [^\n]*\b" + re.escape(name) +
+               r"\b[^\n;]*\{.*?\n\}\n")
+        out.extend(m.group(0) for m in re.finditer(pat, src, re.S))
+    return out
+
+
 def sweep_traffic(path_used):
     """HBM bytes per sweep launch from the committed counter passes
-    (profiles/k_sweep_c2_traffic.json), or None when the fused sweep's
-    source has changed since they were taken (or another path ran)."""
+    (profiles/k_sweep_c2_traffic.json), or None when the fused sweep or the
+    device helpers it calls have changed since they were taken (or another
+    path ran)."""
     import hashlib
     import re
     if path_used != 1:
@@ -67,13 +79,17 @@ def sweep_traffic(path_used):
                   r"\{.*?\n\}\n", src, re.S)
     if not m:
         return None
-    # the kernel's text and the device helpers it calls (wave sums, loads)
     h = hashlib.sha256(m.group(0).encode())
     for extra in doc.get("helper_files", []):
         try:
-            h.update(open(os.path.join(ROOT, extra)).read().encode())
-        except OSError:
+            text = open(os.path.join(ROOT, extra["file"])).read()
+        except (OSError, TypeError, KeyError):
             return None
+        parts = _device_function_texts(text, extra.get("functions", []))
+        if len(parts) < len(extra.get("functions", [])):
+            return None
+        for t in parts:
+            h.update(t.encode())
     if h.hexdigest() != doc["source_sha256"]:
         return None
     return doc["traffic_bytes_per_launch"]
