@@ -7,10 +7,14 @@ returns with Student-t(4) idiosyncratic noise (gen.SPECS["c2"]), target
 r = 60th percentile of the asset means.
 
 One step = npga_build_factor (mu, L from the float32 returns already in
-HBM) + npga_solve (power-method step size, NPGA to residual 1e-6, float64
-refinement).  ``value`` is the median over the timed steps of the GPU time
-from npga_solve entry until the stopping test first passed (residual
-<= 1e-6), in seconds; ``ms_per_step`` is the wall time of a whole step.
+HBM) + npga_solve on the fused-sweep path (Lanczos step size, NPGA to
+residual 1e-6, float64 refinement).  ``value`` is the median over the
+timed steps of the GPU time from npga_solve entry until the stopping test
+first passed (residual <= 1e-6), in seconds; ``ms_per_step`` is the wall
+time of a whole step.  Beside it: the path AUTO would take, the covariance
+path, bfloat16 storage, STR, the adjoint and the C4 frontier, each with
+its error against the stored oracle solutions, and the float64 oracle
+timed on the host cores (``cpu_baseline``).
 
 Prints ONE JSON line.  --gpus N with N > 1 exits: the solver runs on one GPU.
 """
