@@ -276,16 +276,15 @@ def frontier_section(npga, gen, torch, dev, n_seq):
     if ref4 is not None:
         sec["targets"] = "the stored oracle frontier's (its r_mv); the GPU's r_mv differs by %.1e relative" % (
             abs(rs_gpu_mv[0] - rs[0]) / abs(rs[0]))
-    for name, Lx in (("f32", L4), ("bf16", npga.to_bf16(L4))):
-        best, cfg_ms = npga.batched_tune(Lx, m)
+    def run(Lx, path, config):
         runs = []
         for _ in range(2):
-            X, infos = npga.solve_batched(Lx, mu4, rs, batch_config=best)
+            X, infos = npga.solve_batched(Lx, mu4, rs, batch_config=config, path=path)
             runs.append(infos)
         infos = runs[-1]
         t_all = max(i["time_to_tol_ms"] for i in infos) / 1e3
-        gemm_ms = infos[0]["sweep_ms"]
-        sec[name] = {
+        out = {
+            "path_used": {1: "gemv", 2: "syrk"}[infos[0]["path_used"]],
             "frontier_solves_per_s": m / t_all,
             "time_to_tol_all_s": t_all,
             "solve_ms_incl_refinement": infos[0]["time_ms"],
@@ -295,13 +294,25 @@ def frontier_section(npga, gen, torch, dev, n_seq):
             "refine_iters_max": max(i["refine_iters"] for i in infos),
             "all_ok": all(i["status"] == 0 for i in infos),
             "all_refined": all(i["refined"] == 1 for i in infos),
-            "config": best,
-            "config_ms": cfg_ms,
-            "gemm_pair_ms": gemm_ms,
-            "gemm_TFLOPs": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms else None,
+            "gemm_ms": infos[0]["sweep_ms"],
             "objectives_nondecreasing": all(infos[j + 1]["objective"] >= infos[j]["objective"] * (1 - 1e-6)
                                             for j in range(m - 1)),
         }
+        return out, X, infos
+
+    # AUTO: the covariance form (T = 10 n): Sigma = L L^T once, then one
+    # GEMM 2 Sigma X per iteration; beside it the factor form's GEMM pair
+    # (U = L^T X, G = 2 L U) with the tuned tile configuration
+    sec["factor_form"] = {}
+    for name, Lx in (("f32", L4), ("bf16", npga.to_bf16(L4))):
+        sec[name], X, infos = run(Lx, "auto", -1)
+        best, cfg_ms = npga.batched_tune(Lx, m)
+        ff, _, _ = run(Lx, "gemv", best)
+        ff["config"] = best
+        ff["config_ms"] = cfg_ms
+        ff["gemm_TFLOPs"] = flops / (ff["gemm_ms"] * 1e-3) / 1e12 if ff["gemm_ms"] else None
+        sec["factor_form"][name] = ff
+        sec[name]["gemm_TFLOPs"] = (2.0 * n * n * m) / (sec[name]["gemm_ms"] * 1e-3) / 1e12 if sec[name]["gemm_ms"] else None
         ref4 = _golden("c4_frontier.json" if name == "f32" else "c4_frontier_bf16.json")
         if ref4 is not None and len(ref4["points"]) == m:
             import numpy as np
@@ -313,10 +324,9 @@ def frontier_section(npga, gen, torch, dev, n_seq):
                 "x_max_abs_sampled": max(float(np.abs(Xh[p["j"]] - np.asarray(p["x"])).max())
                                          for p in ref4["points"] if "x" in p)}
     # adaptive momentum restart (an option; Algorithm 1 itself has none)
-    best16 = sec["bf16"]["config"]
     Lb16 = npga.to_bf16(L4)
-    npga.solve_batched(Lb16, mu4, rs, batch_config=best16, restart=True)
-    _, inf_r = npga.solve_batched(Lb16, mu4, rs, batch_config=best16, restart=True)
+    npga.solve_batched(Lb16, mu4, rs, restart=True)
+    _, inf_r = npga.solve_batched(Lb16, mu4, rs, restart=True)
     t_r = max(i["time_to_tol_ms"] for i in inf_r) / 1e3
     sec["bf16_restart"] = {"frontier_solves_per_s": m / t_r, "time_to_tol_all_s": t_r,
                            "iters_max": max(i["iters"] for i in inf_r),

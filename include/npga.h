@@ -408,11 +408,17 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
  * target return r_j per solve (points of the efficient frontier, Sec. 5).
  * Every target runs Algorithm 1 with its own iterate, momentum, projection
  * and stopping test (Sec. 3.1), the shared step alpha = 1/(safety L_f_hat)
- * of one power method, and the same float64 face refinement as npga_solve.
- * The gradients of all targets come from two matrix-core GEMMs per
- * iteration, U^T = X^T L and G = 2 L U, so L is read twice per iteration for
- * all m targets; a target that has stopped keeps its x and is skipped by the
- * tails.
+ * of one step estimate, and a float64 face refinement (face CG with
+ * blocking steps).  The gradients of all targets come from matrix-core
+ * GEMMs on the targets still running: in the factor form (opt->path GEMV)
+ * two per iteration, U^T = X^T L and G = 2 L U, so L is read twice per
+ * iteration for all m targets; in the covariance form (opt->path SYRK, or
+ * AUTO with the single solve's rule: cols >= n and Sigma plus the SYRK
+ * planes within 4 GiB) Sigma = L L^T is formed once (split-plane SYRK on
+ * the float32 values of L, also for a bfloat16 factor) and each iteration
+ * takes G = 2 Sigma X from one GEMM split over the contraction (Sec. 3.1,
+ * explicit covariance).  A target that has stopped keeps its x and is
+ * skipped by the tails.
  *   f          factor (float32 or bfloat16), gamma >= 0
  *   r_targets  host, m target returns, each <= max(mu) (else
  *              NPGA_ERR_INFEASIBLE before any iteration)
@@ -422,11 +428,15 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
  *   res        host, m results (may be NULL); time_to_tol_ms of target j is
  *              the GPU time from entry to the end of the chunk of
  *              check_every iterations in which its stopping test passed;
- *              sweep_ms is the mean time of one U+G GEMM pair
- *   ws         npga_batched_workspace_size(n, cols, m, opt) bytes
+ *              sweep_ms is the mean time of one iteration's gradient GEMMs
+ *              over the full batch (the U+G pair, or the Sigma X GEMM)
+ *   ws         npga_batched_workspace_size(n, cols, m, opt) bytes (with the
+ *              covariance form: Sigma, the SYRK's bfloat16 planes of L and a
+ *              float32 copy of a bfloat16 factor; never less than the factor
+ *              form needs)
  * Returns NPGA_OK when every target returned NPGA_OK, else the status of the
- * first target that did not.  opt->path must be AUTO or GEMV.  Synchronises
- * `stream`.
+ * first target that did not; res[j].path_used reports the form (GEMV or
+ * SYRK).  Synchronises `stream`.
  *
  * npga_gradient_batched - G[:, j] = 2 L (L^T X[:, j]) + 2 gamma X[:, j] and
  * f_out[j] = ||L^T X[:, j]||^2 + gamma ||X[:, j]||^2 (float64 sums) for

@@ -1008,15 +1008,20 @@ namespace {
 // anchors), then the per-target states and vectors and the GEMM buffers.
 struct BatchLayout {
   SolveLayout single;
-  size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, off_act, off_U16, off_Lt, total;
-  int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt;
+  size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, off_act, off_U16, off_Lt, off_sigma,
+      off_planes, off_l32, total;
+  int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt, lds, ld32;
+  bool cov;
 };
 
 constexpr int kMaxSplits = 64;
 constexpr int kNumVec = 9;  // xbuf0, xbuf1, gbuf0, gbuf1, pvec, fvec, gvec, xa, ga
 
-BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m) {
+// cov: the covariance form (Sigma, the bfloat16 planes the SYRK reads, and a
+// float32 copy for a bfloat16 factor) instead of the factor form's buffers.
+BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m, bool cov = false) {
   BatchLayout l{};
+  l.cov = cov;
   l.single = npga::solve_layout(n, cols, NPGA_PATH_GEMV);
   l.npad = (int64_t)256 * l.single.slots;
   l.ldx = l.npad;
@@ -1038,18 +1043,50 @@ BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m) {
   l.off_usq = take(sizeof(double) * (size_t)utiles_max * (size_t)l.ldq);
   l.off_status = take(sizeof(int32_t) * (size_t)(2 * (m + 1)));
   l.off_act = take(sizeof(int32_t) * (size_t)(m + 1));
-  // bfloat16 factors: U planes and the row-major copy of L
   l.ldu16 = (cols + 7) / 8 * 8;
   l.ldlt = l.ldu16;
-  l.off_U16 = take(sizeof(uint16_t) * 3 * (size_t)m * (size_t)l.ldu16);
-  l.off_Lt = take(sizeof(uint16_t) * (size_t)n * (size_t)l.ldlt);
+  l.lds = (n + 3) / 4 * 4;
+  l.ld32 = l.lds;
+  if (cov) {
+    l.off_U16 = l.off_Lt = 0;
+    l.off_sigma = take(sizeof(float) * (size_t)l.lds * (size_t)n);
+    l.off_planes = take(npga::syrk_split_bytes(n, cols));
+    l.off_l32 = take(sizeof(float) * (size_t)l.ld32 * (size_t)cols);
+  } else {
+    // bfloat16 factors: U planes and the row-major copy of L
+    l.off_U16 = take(sizeof(uint16_t) * 3 * (size_t)m * (size_t)l.ldu16);
+    l.off_Lt = take(sizeof(uint16_t) * (size_t)n * (size_t)l.ldlt);
+    l.off_sigma = l.off_planes = l.off_l32 = 0;
+  }
   l.total = off;
   return l;
+}
+
+// The covariance form for a batch: asked for, or AUTO with the single
+// solve's rule on the shape (cols >= n, Sigma and the SYRK planes within
+// 4 GiB), for a float32 or a bfloat16 factor (Sigma is formed from its
+// float32 values, which takes a float32 copy of a bfloat16 factor).
+bool batch_uses_covariance(int requested, int64_t n, int64_t cols) {
+  if (requested == NPGA_PATH_SYRK) return true;
+  return requested == NPGA_PATH_AUTO && resolve_path(NPGA_PATH_AUTO, n, cols, NPGA_F32) == NPGA_PATH_SYRK;
 }
 
 // Split and tile counts of a configuration for this factor.
 npga::BatchArgs with_config(npga::BatchArgs b, const npga::BatchConfig &cfg) {
   const int64_t cols = b.base.cols;
+  if (b.covariance) {
+    // Sigma X split over the contraction so that a launch has a few
+    // hundred workgroups (chunks of whole 32-row stages)
+    const int64_t n = b.base.n;
+    const int64_t tiles = ((n + cfg.u_bm - 1) / cfg.u_bm) * ((b.m + cfg.u_bn - 1) / cfg.u_bn);
+    int64_t want = std::max<int64_t>(1, std::min<int64_t>((384 + tiles - 1) / tiles, kMaxSplits));
+    want = std::min<int64_t>(want, (n + 31) / 32);
+    const int64_t kc = ((n + want - 1) / want + 31) / 32 * 32;
+    b.kchunk = kc;
+    b.splits = (int32_t)((n + kc - 1) / kc);
+    b.utiles = 0;
+    return b;
+  }
   const int64_t kc = ((cols + cfg.splits - 1) / cfg.splits + 31) / 32 * 32;
   b.kchunk = kc;
   b.splits = (int32_t)((cols + kc - 1) / kc);
@@ -1254,9 +1291,14 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
 extern "C" {
 
 size_t npga_batched_workspace_size(int64_t n, int64_t cols, int32_t m, const npga_options *opt) {
-  (void)opt;
   if (n < 1 || n > NPGA_MAX_N || cols < 1 || m < 1 || m > NPGA_MAX_BATCH) return 0;
-  return batch_layout(n, cols, m).total;
+  npga_options o;
+  npga_default_options(&o);
+  if (opt) o = *opt;
+  const size_t fac = batch_layout(n, cols, m).total;
+  // the covariance form's buffers when that form would run; never less than
+  // the factor form's (npga_gradient_batched and npga_batched_tune use it)
+  return batch_uses_covariance(o.path, n, cols) ? std::max(fac, batch_layout(n, cols, m, true).total) : fac;
 }
 
 int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m, const npga_options *opt,
@@ -1271,16 +1313,19 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   if (!factor_valid(f) || !r_targets || !X || m < 1 || m > NPGA_MAX_BATCH || ldx < f->n ||
       !options_valid(o) || !aligned(X, 4))
     return NPGA_ERR_INVALID;
-  if (o.path == NPGA_PATH_SYRK) return NPGA_ERR_UNSUPPORTED;
   if (o.momentum == 1 && !(f->gamma > 0.0)) return NPGA_ERR_INVALID;
   for (int32_t j = 0; j < m; ++j)
     if (!is_fin(r_targets[j])) return NPGA_ERR_INVALID;
-  const BatchLayout lay = batch_layout(f->n, f->cols, m);
+  const bool cov = batch_uses_covariance(o.path, f->n, f->cols);
+  const BatchLayout lay = batch_layout(f->n, f->cols, m, cov);
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   DevState *pin = pinned_status();
   BatchPinned *bp = batch_pinned(m);
   if (!pin || !bp) return NPGA_ERR_HIP;
-  const npga::BatchConfig &cfg = batch_config_of(o.batch_config, f->n, f->cols, m);
+  // the covariance form tiles by the batch width (batch_config tunes the
+  // factor form's GEMM pair)
+  const npga::BatchConfig &cfg = cov ? npga::kBatchConfigTable[npga::batch_default_config(f->n, f->n, m)]
+                                     : batch_config_of(o.batch_config, f->n, f->cols, m);
   Carved c = carve(f, lay.single, ws, NPGA_PATH_GEMV);
   npga::BatchArgs b = carve_batch(f, lay, ws, m, cfg);
   const int slots = lay.single.slots;
@@ -1325,6 +1370,31 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   }
   HIPCHK(hipMemcpyAsync(b.base.st, bp->states, sizeof(DevState) * (size_t)m, hipMemcpyHostToDevice, stream));
   LAUNCHCHK(npga::launch_bcopy_step(b, c.st, stream));
+  if (cov) {
+    // Sigma = L L^T once (split-plane SYRK on the float32 values of L);
+    // every iteration then takes 2 Sigma X from one GEMM
+    char *base = static_cast<char *>(ws);
+    float *sigma = reinterpret_cast<float *>(base + lay.off_sigma);
+    const float *L32 = static_cast<const float *>(f->L);
+    int64_t ld32 = f->ld;
+    if (f->dtype == NPGA_BF16) {
+      float *w = reinterpret_cast<float *>(base + lay.off_l32);
+      LAUNCHCHK(npga::launch_widen_bf16(static_cast<const uint16_t *>(f->L), f->ld, f->n, f->cols, w, lay.ld32,
+                                        stream));
+      L32 = w;
+      ld32 = lay.ld32;
+    }
+    LAUNCHCHK(npga::launch_syrk_split(L32, f->n, f->cols, ld32, reinterpret_cast<uint16_t *>(base + lay.off_planes),
+                                      sigma, lay.lds, stream));
+    b.base.L = sigma;
+    b.base.ld = lay.lds;
+    b.base.cols = f->n;
+    b.base.dtype = NPGA_F32;
+    b.Lt = nullptr;
+    b.U16 = nullptr;
+    b.covariance = 1;
+    b = with_config(b, cfg);
+  }
   LAUNCHCHK(batch_prepare_b16(b, lay, stream));
   LAUNCHCHK(npga::launch_bset_x0(b, o.warm_start ? X : nullptr, ldx, stream));
   LAUNCHCHK(npga::launch_bproject_init(b, slots, stream));
@@ -1401,7 +1471,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
     rj.support = fin.support;
     rj.return_active = fin.nu_c > 0.0 ? 1 : 0;
     rj.refined = refined[j];
-    rj.path_used = NPGA_PATH_GEMV;
+    rj.path_used = cov ? NPGA_PATH_SYRK : NPGA_PATH_GEMV;
     rj.step_sweeps = o.alpha > 0.0 ? 0 : (o.step_estimator == 0 ? after_main[j].lz_m : o.power_iters);
     rj.residual = am.stop_residual;
     rj.final_residual = fin.residual;

@@ -107,7 +107,11 @@ constexpr int LDK = KB + 4;  // row length (floats) of contraction-contiguous LD
 // step s pairs k = s (lanes 0-31) with k = 16 + s (lanes 32-63) on both
 // operands.  Epilogue: U^T and per-tile column sums of U^2 (float64).
 // --------------------------------------------------------------------------
-template <typename TL, int BM, int BN, int WM, int WN>
+// KSPLIT (covariance form, L := Sigma): the contraction is split over
+// grid.z in ranges of b.kchunk rows, and each split writes its partial
+// product into P[(z n + t) ldpm + j] (the layout k_breduce sums) instead
+// of U^T; no column sums.
+template <typename TL, int BM, int BN, int WM, int WN, bool KSPLIT = false>
 __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
   constexpr int PM = BM / (32 * WM), PN = BN / (32 * WN);
   constexpr int QA = BM / 32, QB = BN / 32;
@@ -130,6 +134,8 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
   const int ma = *b.mact;
   if (j0 >= ma) return;
   (void)m;
+  const int64_t kbeg = KSPLIT ? (int64_t)blockIdx.z * b.kchunk : 0;
+  const int64_t kend = KSPLIT ? (kbeg + b.kchunk < n ? kbeg + b.kchunk : n) : n;
   // targets of this thread's X columns (column c -> target act[c])
   const float *xcol[QB];
 #pragma unroll
@@ -140,16 +146,18 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
 
   typename R::type ra[QA];
   f4 rb[QB];
+  // (a split's range starts and, except at n, ends on a multiple of 32, so
+  // a float4 never straddles kend below n)
   auto gload = [&](int64_t k0) {
     const int64_t k = k0 + kq;
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int64_t t = t0 + (tid >> 3) + 32 * q;
-      ra[q] = (t < T && k < n) ? R::load(L + t * ld + k) : R::zero();
+      ra[q] = (t < T && k < kend) ? R::load(L + t * ld + k) : R::zero();
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q)
-      rb[q] = (xcol[q] && k < n) ? *reinterpret_cast<const f4 *>(xcol[q] + k) : f4{0.f, 0.f, 0.f, 0.f};
+      rb[q] = (xcol[q] && k < kend) ? *reinterpret_cast<const f4 *>(xcol[q] + k) : f4{0.f, 0.f, 0.f, 0.f};
   };
   auto sstore = [&](int buf, int64_t k0) {
     const int64_t k = k0 + kq;
@@ -158,9 +166,9 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
       f4 v = R::widen(ra[q]);
       // rows past n inside the float4 (ld may exceed n): the contraction
       // must not see them
-      if (k + 1 >= n) v.y = 0.f;
-      if (k + 2 >= n) v.z = 0.f;
-      if (k + 3 >= n) v.w = 0.f;
+      if (k + 1 >= kend) v.y = 0.f;
+      if (k + 2 >= kend) v.z = 0.f;
+      if (k + 3 >= kend) v.w = 0.f;
       *reinterpret_cast<f4 *>(&As[buf][((tid >> 3) + 32 * q) * LDK + kq]) = v;
     }
 #pragma unroll
@@ -175,13 +183,13 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[p][q][v] = 0.f;
 
-  const int64_t nk = (n + KB - 1) / KB;
-  gload(0);
-  sstore(0, 0);
+  const int64_t nk = (kend - kbeg + KB - 1) / KB;
+  gload(kbeg);
+  sstore(0, kbeg);
   __syncthreads();
   for (int64_t s = 0; s < nk; ++s) {
     const int buf = (int)(s & 1);
-    if (s + 1 < nk) gload((s + 1) * KB);
+    if (s + 1 < nk) gload(kbeg + (s + 1) * KB);
     float av[PM][16], bv[PN][16];
 #pragma unroll
     for (int p = 0; p < PM; ++p) {
@@ -214,8 +222,24 @@ __global__ __launch_bounds__(256) void k_bgemm_u(BatchArgs b) {
 #pragma unroll
         for (int q = 0; q < PN; ++q)
           acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[p][kk], bv[q][kk], acc[p][q], 0, 0, 0);
-    if (s + 1 < nk) sstore(buf ^ 1, (s + 1) * KB);
+    if (s + 1 < nk) sstore(buf ^ 1, kbeg + (s + 1) * KB);
     __syncthreads();
+  }
+
+  if constexpr (KSPLIT) {
+    float *Pz = b.P + (int64_t)blockIdx.z * n * b.ldpm;
+#pragma unroll
+    for (int p = 0; p < PM; ++p)
+#pragma unroll
+      for (int q = 0; q < PN; ++q) {
+        const int64_t j = j0 + wc * 32 * PN + 32 * q + r;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t t = t0 + wr * 32 * PM + 32 * p + 8 * (v >> 2) + 4 * h + (v & 3);
+          if (t < T && j < ma) Pz[t * b.ldpm + j] = acc[p][q][v];
+        }
+      }
+    return;
   }
 
   // epilogue: U^T (coalesced along j) and column sums of U^2 over this tile
@@ -437,8 +461,8 @@ __global__ __launch_bounds__(256) void k_btail(BatchArgs b) {
   __shared__ double redbuf[64];
   __shared__ double mbuf[8];
   __shared__ int64_t ibuf[8];
-  double usq = -1.0;
-  if (a.mode == kTailNpga || a.mode == kTailGrad) {
+  double usq = -1.0;  // covariance form: f = x^T g / 2 in the tails
+  if (!b.covariance && (a.mode == kTailNpga || a.mode == kTailGrad)) {
     BlockReducer<5> red5{redbuf, 0};
     double acc[5] = {0, 0, 0, 0, 0};
     for (int w = threadIdx.x; w < b.utiles; w += 256) acc[0] += b.usq_part[(int64_t)w * b.ldq + blockIdx.x];
@@ -581,6 +605,22 @@ __global__ __launch_bounds__(256) void k_bact_all(int32_t m, int32_t *act, int32
   if (threadIdx.x == 0) *mact = m;
 }
 
+// L32 = float32 values of a bfloat16 factor (the covariance form's SYRK
+// reads float32); rows n..ld32-1 are written as zeros.
+__global__ __launch_bounds__(256) void k_widen_bf16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, float *L32,
+                                                    int64_t ld32) {
+  const int64_t total = ld32 * T;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t t = e / ld32, i = e - t * ld32;
+    L32[e] = (i < n) ? __uint_as_float((uint32_t)L[i + t * ld] << 16) : 0.f;
+  }
+}
+
+int launch_widen_bf16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, float *L32, int64_t ld32, hipStream_t s) {
+  hipLaunchKernelGGL(k_widen_bf16, dim3(2048), dim3(256), 0, s, L, ld, n, T, L32, ld32);
+  return (int)hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_zero_f32(float *p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
     p[i] = 0.0f;
@@ -636,7 +676,29 @@ static int launch_bgemm_t(const BatchArgs &b, const BatchConfig &c, hipStream_t 
   return (int)hipGetLastError();
 }
 
+// Covariance form: G = Sigma X by the U GEMM on L := Sigma (symmetric),
+// split over the contraction; k_breduce sums the splits.
+static int launch_bcov(const BatchArgs &b, const BatchConfig &c, hipStream_t s) {
+  const int64_t n = b.base.n;
+  const unsigned gy = (unsigned)((b.m + c.u_bn - 1) / c.u_bn);
+  const dim3 g((unsigned)((n + c.u_bm - 1) / c.u_bm), gy, (unsigned)b.splits);
+  if (c.u_bm == 128 && c.u_bn == 128)
+    hipLaunchKernelGGL((k_bgemm_u<float, 128, 128, 2, 2, true>), g, dim3(256), 0, s, b);
+  else if (c.u_bm == 128 && c.u_bn == 64)
+    hipLaunchKernelGGL((k_bgemm_u<float, 128, 64, 2, 2, true>), g, dim3(256), 0, s, b);
+  else if (c.u_bm == 128 && c.u_bn == 32)
+    hipLaunchKernelGGL((k_bgemm_u<float, 128, 32, 4, 1, true>), g, dim3(256), 0, s, b);
+  else if (c.u_bm == 64 && c.u_bn == 64)
+    hipLaunchKernelGGL((k_bgemm_u<float, 64, 64, 2, 2, true>), g, dim3(256), 0, s, b);
+  else if (c.u_bm == 64 && c.u_bn == 128)
+    hipLaunchKernelGGL((k_bgemm_u<float, 64, 128, 1, 4, true>), g, dim3(256), 0, s, b);
+  else
+    return (int)hipErrorInvalidValue;
+  return (int)hipGetLastError();
+}
+
 int launch_bgemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s) {
+  if (b.covariance) return launch_bcov(b, c, s);
   if (b.Lt) return launch_b16_gemm(b, c, s);
   if (b.base.dtype == NPGA_BF16) return launch_bgemm_t<bf16_t>(b, c, s);
   return launch_bgemm_t<float>(b, c, s);

@@ -191,6 +191,10 @@ struct BatchArgs {
   uint16_t *U16;
   int64_t ldu16;
   int64_t u16plane;
+  // covariance form (base.L = Sigma, n x n float32, base.cols = n): the
+  // gradient is 2 Sigma X by one GEMM split over the contraction into
+  // `splits` ranges of `kchunk` rows; the tails take f = x^T g / 2
+  int32_t covariance;
 };
 
 // Tile configuration of the two batched GEMMs.
@@ -279,6 +283,7 @@ int launch_zero_f32(float *p, int64_t count, hipStream_t s);
 int launch_b16_gemm(const BatchArgs &b, const BatchConfig &c, hipStream_t s);
 int launch_transpose16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, uint16_t *Lt, int64_t ldlt,
                        hipStream_t s);
+int launch_widen_bf16(const uint16_t *L, int64_t ld, int64_t n, int64_t T, float *L32, int64_t ld32, hipStream_t s);
 
 // Adjoint (npga_adjoint.hip).  Vectors: x* in xbuf1, the face gradient
 // 2 L L^T x* in ga, the loss gradient rhs in xa, the CG iterate in xbuf0.

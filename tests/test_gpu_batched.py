@@ -79,13 +79,19 @@ def _frontier_case(n, T, m, seed, gamma, dtype, npga):
     return L, mu, L_o, mu_o, rs
 
 
+@pytest.mark.parametrize("path", ["gemv", "syrk"])
 @pytest.mark.parametrize("n,T,m,gamma,dtype", [(64, 256, 8, 0.0, "f32"), (200, 2000, 16, 0.0, "f32"),
                                                (300, 1000, 12, 1e-4, "f32"), (150, 1500, 10, 0.0, "bf16"),
-                                               (97, 800, 3, 0.0, "f32")])
-def test_solve_batched_vs_oracle(npga, n, T, m, gamma, dtype):
-    banner(f"batched solve n={n} T={T} m={m} gamma={gamma} {dtype}")
+                                               (97, 800, 3, 0.0, "f32"), (70, 3000, 150, 0.0, "bf16")])
+def test_solve_batched_vs_oracle(npga, n, T, m, gamma, dtype, path):
+    """Both forms of the batched gradient: the factor form's GEMM pair
+    (gemv) and the covariance form's one GEMM on Sigma (syrk, also AUTO's
+    choice for T >= n), the latter with a bfloat16 factor through Sigma of
+    its float32 values."""
+    banner(f"batched solve n={n} T={T} m={m} gamma={gamma} {dtype} {path}")
     L, mu, L_o, mu_o, rs = _frontier_case(n, T, m, 200 + n, gamma, dtype, npga)
-    X, infos = npga.solve_batched(L, mu, rs, gamma=gamma)
+    X, infos = npga.solve_batched(L, mu, rs, gamma=gamma, path=path)
+    assert all(i["path_used"] == {"gemv": 1, "syrk": 2}[path] for i in infos)
     ref = frontier(L_o, gamma, mu_o, rs)
     Xh = X.cpu().numpy()
     for j in range(m):

@@ -24,7 +24,10 @@ GOLDEN_BF16 = os.path.join(os.path.dirname(__file__), "golden", "c4_frontier_bf1
 
 
 @pytest.mark.skipif(not (os.path.exists(GOLDEN) and os.path.exists(GOLDEN_BF16)), reason="c4 goldens not generated")
-def test_c4_frontier_parity():
+@pytest.mark.parametrize("path", ["auto", "gemv"])
+def test_c4_frontier_parity(path):
+    """AUTO (the covariance form, T = 10 n: what the benchmark times) and the
+    factor form's tuned GEMM pair."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2604_02917_amd as npga
@@ -37,9 +40,11 @@ def test_c4_frontier_parity():
     mu_o, L_o = ofactor.build_factor(Rt.T)
     L, mu = npga.build_factor(to_dev(Rt))
     rs = ref["targets"]
-    best, _ = npga.batched_tune(L, len(rs))
-    banner(f"c4: batched solve of {len(rs)} targets (config {best})")
-    X, infos = npga.solve_batched(L, mu, rs, batch_config=best)
+    best = -1
+    if path == "gemv":
+        best, _ = npga.batched_tune(L, len(rs))
+    banner(f"c4 {path}: batched solve of {len(rs)} targets (config {best})")
+    X, infos = npga.solve_batched(L, mu, rs, batch_config=best, path=path)
     Xh = X.cpu().numpy().astype(np.float64)
     worst = 0.0
     for p in ref["points"]:
@@ -61,9 +66,11 @@ def test_c4_frontier_parity():
     # bfloat16 values (tests/golden/c4_frontier_bf16.json) at every target,
     # and the quantisation gap against the float32 frontier
     Lb = npga.to_bf16(L)
-    best16, _ = npga.batched_tune(Lb, len(rs))
-    banner(f"c4 bf16: batched solve (config {best16})")
-    Xb, infos_b = npga.solve_batched(Lb, mu, rs, batch_config=best16)
+    best16 = -1
+    if path == "gemv":
+        best16, _ = npga.batched_tune(Lb, len(rs))
+    banner(f"c4 bf16 {path}: batched solve (config {best16})")
+    Xb, infos_b = npga.solve_batched(Lb, mu, rs, batch_config=best16, path=path)
     Xbh = Xb.cpu().numpy().astype(np.float64)
     with open(GOLDEN_BF16) as fh:
         refq = json.load(fh)

@@ -62,19 +62,21 @@ def test_trajectory_matches_oracle(npga, n, T, q, path):
     banner(f"trajectory n={n} T={T} {path}: max |x_gpu^k - x_oracle^k| over k in {KS} = {worst:.2e}")
 
 
-def test_batched_trajectory_matches_oracle(npga):
-    """The batched solver shares the step: each target's x^k is the oracle's."""
+@pytest.mark.parametrize("path", ["gemv", "syrk"])
+def test_batched_trajectory_matches_oracle(npga, path):
+    """The batched solver shares the step: each target's x^k is the oracle's
+    (factor form and covariance form)."""
     n, T = 120, 600
     Rt, mu, L, r, model, alpha = _setup(n, T, 950, 0.5)
     rs = [float(np.quantile(mu, 0.3)), float(np.quantile(mu, 0.7)), float(np.quantile(mu, 0.9))]
     Ld, mud = npga.build_factor(to_dev(Rt))
     k = 20
-    X, infos = npga.solve_batched(Ld, mud, rs, alpha=alpha, max_iter=k, refine=False, tol=1e-300)
+    X, infos = npga.solve_batched(Ld, mud, rs, alpha=alpha, max_iter=k, refine=False, tol=1e-300, path=path)
     for j, rj in enumerate(rs):
         ref = onpga.npga(model, mu, rj, alpha, np.full(n, 1.0 / n), tol=0.0, check_every=5, max_iter=k)
         assert infos[j]["iters"] == k and infos[j]["alpha"] == alpha
         err = float(np.abs(X[j].cpu().numpy().astype(np.float64) - ref["x"]).max())
-        banner(f"batched trajectory target {j}: max |x_gpu^k - x_oracle^k| = {err:.2e}")
+        banner(f"batched trajectory ({path}) target {j}: max |x_gpu^k - x_oracle^k| = {err:.2e}")
         assert err <= 1e-6, (j, err)
 
 
