@@ -1009,7 +1009,7 @@ namespace {
 struct BatchLayout {
   SolveLayout single;
   size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, off_act, off_U16, off_Lt, off_sigma,
-      off_planes, off_l32, total;
+      off_planes, off_l32, off_prec, total;
   int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt, lds, ld32;
   bool cov;
 };
@@ -1043,6 +1043,8 @@ BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m, bool cov = false) {
   l.off_usq = take(sizeof(double) * (size_t)utiles_max * (size_t)l.ldq);
   l.off_status = take(sizeof(int32_t) * (size_t)(2 * (m + 1)));
   l.off_act = take(sizeof(int32_t) * (size_t)(m + 1));
+  // the refinement's batched float64 anchor gradients (U^T and the split partials)
+  l.off_prec = take(npga::precise_batch_bytes(n, cols, m, l.npad));
   l.ldu16 = (cols + 7) / 8 * 8;
   l.ldlt = l.ldu16;
   l.lds = (n + 3) / 4 * 4;
@@ -1418,17 +1420,13 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
     br.base.mode = npga::kTailCG;
     std::vector<double> t_unused(m, 0.0);
     for (int round = 0; round < 2; ++round) {
-      // float64 anchor gradients of every target still converged
+      // float64 anchor gradients of every target still converged (the
+      // device's done flags are the ones copied to the host above)
       LAUNCHCHK(npga::launch_bcopy_anchor(br, stream));
-      for (int32_t j = 0; j < m; ++j) {
-        const int32_t dj = round == 0 ? after_main[j].done : ref_done[j];
-        if (dj != npga::kConverged) continue;
-        LAUNCHCHK(npga::launch_precise_gradient(c.a, br.base.xa + (int64_t)j * br.vstride,
-                                                reinterpret_cast<double *>(static_cast<char *>(ws) +
-                                                                           lay.single.off_ua),
-                                                const_cast<double *>(br.base.ga) + (int64_t)j * br.vstride,
-                                                reinterpret_cast<double *>(c.a.partials), slots, stream));
-      }
+      LAUNCHCHK(npga::launch_precise_gradient_batched(
+          f->L, f->dtype, f->ld, f->n, f->cols, br.base.xa, br.vstride, m, br.base.st,
+          reinterpret_cast<double *>(static_cast<char *>(ws) + lay.off_prec), lay.npad,
+          const_cast<double *>(br.base.ga), br.vstride, stream));
       LAUNCHCHK(npga::launch_bphase_reset(br, o.refine_tol, o.refine_max_iter, stream));
       LAUNCHCHK(npga::launch_bcg_init(br, slots, stream));
       const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;

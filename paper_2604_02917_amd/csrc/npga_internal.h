@@ -262,6 +262,20 @@ int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
                             double *part, int slots, hipStream_t s);
+// The same for a batch: G[j ldg + i] = 2 (L L^T x_j)_i for every target j
+// with st[j].done == kConverged (X[j ldxv + i]), 0 for the others; scratch:
+// precise_batch_bytes(n, T, m, npad) bytes (256-byte aligned), npad >= n.
+struct PreciseBatchPlan {
+  int64_t kc;       // periods per range of the split G GEMM (a multiple of 16)
+  int32_t splits;   // number of ranges
+  int64_t ldu;      // leading dimension of U^T (float64, m x T)
+  size_t u_bytes;
+};
+PreciseBatchPlan precise_batch_plan(int64_t n, int64_t T, int32_t m);
+size_t precise_batch_bytes(int64_t n, int64_t T, int32_t m, int64_t npad);
+int launch_precise_gradient_batched(const void *L, int32_t dtype, int64_t ld, int64_t n, int64_t T,
+                                    const double *X, int64_t ldxv, int32_t m, const DevState *st, double *scratch,
+                                    int64_t npad, double *G, int64_t ldg, hipStream_t s);
 int launch_phase_reset(DevState *st, double tol, int32_t max_iter, int32_t window, hipStream_t s);
 int launch_cg_init(const SolveArgs &a, int slots, hipStream_t s);
 int launch_add_ridge(const SolveArgs &a, hipStream_t s);  // gbuf0 += 2 gamma pvec

@@ -171,4 +171,246 @@ int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, 
   return (int)hipGetLastError();
 }
 
+
+// --------------------------------------------------------------------------
+// Batched float64 anchor gradients: G_j = 2 L (L^T x_j) for every target j
+// whose last phase converged (the others get G_j = 0), two float64 matrix-core
+// GEMMs for the whole batch instead of two streaming passes over L per
+// target.  Each product of a float32 (or bfloat16) entry of L with a float64
+// entry is formed in float64 by v_mfma_f64_16x16x4f64, as in the per-target
+// kernels above; only the order of the float64 sums differs.
+//   U^T (m x T)  = X^T L      contraction over the n assets
+//   G^T (m x n)  = U^T L^T    contraction over the T periods, split in
+//                             ranges of kc periods, one float64 partial
+//                             G^T per range, summed in range order
+// Tiles of 64 targets x 64 periods (or assets), four wavefronts of 32 x 32
+// (2 x 2 blocks of 16 x 16), 16-deep stages double-buffered in LDS.
+// --------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int PT = 64;
+constexpr int PK = 16;
+
+// Four entries of column col of L from row i (i % 4 == 0), zero past n.
+// i < n <= ld and ld % 4 == 0 keep the 16-byte (8-byte for bfloat16) load
+// inside the column.
+template <typename TL>
+__device__ __forceinline__ f4 load_l4(const TL *L, int64_t ld, int64_t n, int64_t col, int64_t i) {
+  f4 v = f4{0.f, 0.f, 0.f, 0.f};
+  if (i < n) {
+    v = load4_nt<TL>(L + col * ld + i);
+    if (i + 1 >= n) v.y = 0.f;
+    if (i + 2 >= n) v.z = 0.f;
+    if (i + 3 >= n) v.w = 0.f;
+  }
+  return v;
+}
+
+// The 4 x 16 x 16 MFMA steps of one stage for a 32 x 32 wavefront tile:
+// A rows (targets) from As, B columns from Bs, lane l supplying row or
+// column l % 16 at contraction index kk + l / 16.
+__device__ __forceinline__ void prec_stage(const double (*As)[PT + 1], const double (*Bs)[PT + 1], int lane,
+                                           int wr, int wc, d4 (&acc)[2][2]) {
+#pragma unroll
+  for (int kk = 0; kk < PK; kk += 4) {
+    const int kr = kk + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) av[p] = As[kr][wr * 32 + p * 16 + (lane & 15)];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) bv[q] = Bs[kr][wc * 32 + q * 16 + (lane & 15)];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
+  }
+}
+
+// U^T = X^T L.  Grid: (period tiles, target tiles).  Target j's column of X
+// is read only when st[j].done == kConverged.
+template <typename TL>
+__global__ __launch_bounds__(256) void k_bprec_u(const TL *L, int64_t ld, int64_t n, int64_t T, const double *X,
+                                                 int64_t ldxv, int32_t m, const DevState *st, double *Ut,
+                                                 int64_t ldu) {
+  __shared__ double Xs[2][PK][PT + 1];
+  __shared__ double Ls[2][PK][PT + 1];
+  const int j0 = blockIdx.y * PT;
+  const int64_t t0 = (int64_t)blockIdx.x * PT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  // loader: column tid / 4 of each panel, rows 4 (tid % 4) .. +3 of a stage
+  const int col = tid >> 2, fi = tid & 3;
+  const int jl = j0 + col;
+  const bool live = jl < m && st[jl].done == kConverged;
+  const double *xc = X + (int64_t)jl * ldxv;
+  const int64_t tl = t0 + col;
+  double xr[4];
+  f4 lr;
+  auto gload = [&](int64_t i0) {
+    const int64_t i = i0 + 4 * fi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xr[e] = (live && i + e < n) ? xc[i + e] : 0.0;
+    lr = (tl < T) ? load_l4<TL>(L, ld, n, tl, i) : f4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Xs[buf][4 * fi + e][col] = xr[e];
+    Ls[buf][4 * fi + 0][col] = (double)lr.x;
+    Ls[buf][4 * fi + 1][col] = (double)lr.y;
+    Ls[buf][4 * fi + 2][col] = (double)lr.z;
+    Ls[buf][4 * fi + 3][col] = (double)lr.w;
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t nst = (n + PK - 1) / PK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t s = 0; s < nst; ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < nst) gload((s + 1) * PK);
+    prec_stage(Xs[buf], Ls[buf], lane, wr, wc, acc);
+    if (s + 1 < nst) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // float64 16 x 16 output: lane l, register v -> row l / 16 + 4 v, column l % 16
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + wr * 32 + p * 16 + (lane >> 4) + 4 * v;
+        const int64_t t = t0 + wc * 32 + q * 16 + (lane & 15);
+        if (j < m && t < T) Ut[(int64_t)j * ldu + t] = acc[p][q][v];
+      }
+}
+
+// Partial G^T over periods [z kc, min(T, (z + 1) kc)).  Grid: (target tiles,
+// asset tiles, period ranges).  Out: P[(z m + j) npad + i].
+template <typename TL>
+__global__ __launch_bounds__(256) void k_bprec_g(const TL *L, int64_t ld, int64_t n, int64_t T, const double *Ut,
+                                                 int64_t ldu, int32_t m, int64_t kc, double *P, int64_t npad) {
+  __shared__ double Us[2][PK][PT + 1];
+  __shared__ double Ls[2][PK][PT + 1];
+  const int j0 = blockIdx.x * PT;
+  const int64_t i0 = (int64_t)blockIdx.y * PT;
+  const int64_t tb = (int64_t)blockIdx.z * kc;
+  const int64_t te = (tb + kc < T) ? tb + kc : T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  // U loader: target tid / 4, periods 4 (tid % 4) .. +3 of a stage;
+  // L loader: period tid / 16 of a stage, assets 4 (tid % 16) .. +3
+  const int col = tid >> 2, fi = tid & 3;
+  const int ju = j0 + col;
+  const double *uc = Ut + (int64_t)ju * ldu;
+  const int kt = tid >> 4, i4 = 4 * (tid & 15);
+  double ur[4];
+  f4 lr;
+  auto gload = [&](int64_t t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t te4 = t + 4 * fi + e;
+      ur[e] = (ju < m && te4 < te) ? uc[te4] : 0.0;
+    }
+    const int64_t tt = t + kt;
+    lr = (tt < te) ? load_l4<TL>(L, ld, n, tt, i0 + i4) : f4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Us[buf][4 * fi + e][col] = ur[e];
+    Ls[buf][kt][i4 + 0] = (double)lr.x;
+    Ls[buf][kt][i4 + 1] = (double)lr.y;
+    Ls[buf][kt][i4 + 2] = (double)lr.z;
+    Ls[buf][kt][i4 + 3] = (double)lr.w;
+  };
+  d4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t nst = (te - tb + PK - 1) / PK;
+  if (nst > 0) {
+    gload(tb);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int64_t s = 0; s < nst; ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < nst) gload(tb + (s + 1) * PK);
+    prec_stage(Us[buf], Ls[buf], lane, wr, wc, acc);
+    if (s + 1 < nst) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  double *out = P + (int64_t)blockIdx.z * m * npad;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = j0 + wr * 32 + p * 16 + (lane >> 4) + 4 * v;
+        const int64_t i = i0 + wc * 32 + q * 16 + (lane & 15);
+        if (j < m && i < n) out[(int64_t)j * npad + i] = acc[p][q][v];
+      }
+}
+
+// G[j ldg + i] = 2 sum_z P[(z m + j) npad + i], ranges added in order.
+__global__ __launch_bounds__(256) void k_bprec_reduce(const double *P, int32_t splits, int32_t m, int64_t npad,
+                                                      int64_t n, double *G, int64_t ldg) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += P[((int64_t)z * m + j) * npad + i];
+  G[(int64_t)j * ldg + i] = 2.0 * s;
+}
+
+PreciseBatchPlan precise_batch_plan(int64_t n, int64_t T, int32_t m) {
+  PreciseBatchPlan p{};
+  const int64_t tiles = ((m + PT - 1) / PT) * ((n + PT - 1) / PT);
+  int64_t want = (512 + tiles - 1) / tiles;
+  if (want > 32) want = 32;
+  const int64_t cap = (T + 8 * PK - 1) / (8 * PK);  // ranges of at least 8 stages
+  if (want > cap) want = cap;
+  if (want < 1) want = 1;
+  p.kc = ((T + want - 1) / want + PK - 1) / PK * PK;
+  p.splits = (int32_t)((T + p.kc - 1) / p.kc);
+  p.ldu = (T + 1) / 2 * 2;
+  p.u_bytes = sizeof(double) * (size_t)m * (size_t)p.ldu;
+  return p;
+}
+
+size_t precise_batch_bytes(int64_t n, int64_t T, int32_t m, int64_t npad) {
+  const PreciseBatchPlan p = precise_batch_plan(n, T, m);
+  return (p.u_bytes + 255) / 256 * 256 + sizeof(double) * (size_t)p.splits * (size_t)m * (size_t)npad;
+}
+
+int launch_precise_gradient_batched(const void *L, int32_t dtype, int64_t ld, int64_t n, int64_t T,
+                                    const double *X, int64_t ldxv, int32_t m, const DevState *st, double *scratch,
+                                    int64_t npad, double *G, int64_t ldg, hipStream_t s) {
+  if (m < 1 || n < 1 || T < 1 || npad < n || ld < n || (ld % 4) != 0) return (int)hipErrorInvalidValue;
+  const PreciseBatchPlan p = precise_batch_plan(n, T, m);
+  double *Ut = scratch;
+  double *P = scratch + (p.u_bytes + 255) / 256 * 256 / sizeof(double);
+  if ((T + PT - 1) / PT > 0x7fffffffLL) return (int)hipErrorInvalidValue;
+  const dim3 gu((unsigned)((T + PT - 1) / PT), (unsigned)((m + PT - 1) / PT));
+  const dim3 gg((unsigned)((m + PT - 1) / PT), (unsigned)((n + PT - 1) / PT), (unsigned)p.splits);
+  if (dtype == NPGA_BF16) {
+    const bf16_t *Lb = static_cast<const bf16_t *>(L);
+    hipLaunchKernelGGL(k_bprec_u<bf16_t>, gu, dim3(256), 0, s, Lb, ld, n, T, X, ldxv, m, st, Ut, p.ldu);
+    hipLaunchKernelGGL(k_bprec_g<bf16_t>, gg, dim3(256), 0, s, Lb, ld, n, T, Ut, p.ldu, m, p.kc, P, npad);
+  } else {
+    const float *Lf = static_cast<const float *>(L);
+    hipLaunchKernelGGL(k_bprec_u<float>, gu, dim3(256), 0, s, Lf, ld, n, T, X, ldxv, m, st, Ut, p.ldu);
+    hipLaunchKernelGGL(k_bprec_g<float>, gg, dim3(256), 0, s, Lf, ld, n, T, Ut, p.ldu, m, p.kc, P, npad);
+  }
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  hipLaunchKernelGGL(k_bprec_reduce, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, s, P, p.splits, m,
+                     npad, n, G, ldg);
+  return (int)hipGetLastError();
+}
+
 }  // namespace npga
