@@ -35,15 +35,27 @@ bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 // Pinned host mirrors of the device state, one set per host thread.  They
 // are allocated on first use and kept for the life of the process.
 constexpr int kStatusSlots = 4;
+thread_local char *g_pin_dev = nullptr;  // device address of the pinned mirrors
 DevState *pinned_status() {
   thread_local DevState *buf = nullptr;
   if (!buf) {
-    void *p = nullptr;
+    void *p = nullptr, *d = nullptr;
     if (hipHostMalloc(&p, sizeof(DevState) * kStatusSlots, hipHostMallocDefault) != hipSuccess)
       return nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess || !d) {
+      (void)hipHostFree(p);
+      return nullptr;
+    }
     buf = static_cast<DevState *>(p);
+    g_pin_dev = static_cast<char *>(d);
   }
   return buf;
+}
+
+// Device address of a word inside the pinned mirrors.
+int32_t *pinned_dev(const DevState *pin, const int32_t *host_word) {
+  return reinterpret_cast<int32_t *>(g_pin_dev + (reinterpret_cast<const char *>(host_word) -
+                                                  reinterpret_cast<const char *>(pin)));
 }
 
 #define HIPCHK(expr)                                   \
@@ -331,8 +343,8 @@ int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max
       }
       if (step(c, path, slots, s)) return NPGA_ERR_HIP;
     }
-    if (hipMemcpyAsync(&pin[slot], c.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return NPGA_ERR_HIP;
+    // the chunk's done word, stored by the device into the pinned slot
+    if (npga::launch_status(c.st, pinned_dev(pin, &pin[slot].done), s)) return NPGA_ERR_HIP;
     if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
     return NPGA_OK;
   };
@@ -511,10 +523,9 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
   int e = run_phase(c, path, slots, o.check_every, main_chunks, stream, pin, evs, ev0, &done, &tol_ms, &tm);
   if (e) return e;
   const int main_done = done;
-  DevState after_main = pin[0].done != npga::kRunning ? pin[0] : pin[1];
   HIPCHK(hipMemcpyAsync(&pin[2], c.st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  after_main = pin[2];
+  const DevState after_main = pin[2];
   const double host_tol_ms = ms_since(t0);
   (void)host_tol_ms;
 
@@ -1174,7 +1185,8 @@ void batch_refine_vectors(npga::BatchArgs &b, const BatchLayout &l, void *ws) {
 // Pinned host buffers of a batched call: m states and two status slots.
 struct BatchPinned {
   DevState *states = nullptr;
-  int32_t *status = nullptr;  // 2 slots of (m + 1)
+  int32_t *status = nullptr;      // 2 slots of (m + 1)
+  int32_t *status_dev = nullptr;  // its device address (written by k_bstatus)
   int32_t cap = 0;
 };
 
@@ -1185,15 +1197,22 @@ BatchPinned *batch_pinned(int32_t m) {
     if (p.status) (void)hipHostFree(p.status);
     p.states = nullptr;
     p.status = nullptr;
+    p.status_dev = nullptr;
     p.cap = 0;
-    void *a = nullptr, *c = nullptr;
+    void *a = nullptr, *c = nullptr, *d = nullptr;
     if (hipHostMalloc(&a, sizeof(DevState) * (size_t)m, hipHostMallocDefault) != hipSuccess) return nullptr;
     if (hipHostMalloc(&c, sizeof(int32_t) * (size_t)(2 * (m + 1)), hipHostMallocDefault) != hipSuccess) {
       (void)hipHostFree(a);
       return nullptr;
     }
+    if (hipHostGetDevicePointer(&d, c, 0) != hipSuccess || !d) {
+      (void)hipHostFree(a);
+      (void)hipHostFree(c);
+      return nullptr;
+    }
     p.states = static_cast<DevState *>(a);
     p.status = static_cast<int32_t *>(c);
+    p.status_dev = static_cast<int32_t *>(d);
     p.cap = m;
   }
   return &p;
@@ -1220,7 +1239,8 @@ const npga::BatchConfig &config_for_running(const npga::BatchConfig &req, int64_
 // t_done[j] receives the GPU time from ev0 to the end of the chunk in which
 // target j stopped (unchanged for targets that stopped before the phase).
 int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int slots, int check_every,
-                    int64_t max_chunks, hipStream_t s, int32_t *dev_status, int32_t *pin_status, hipEvent_t *evs,
+                    int64_t max_chunks, hipStream_t s, int32_t *dev_status, int32_t *pin_status,
+                    int32_t *pin_status_dev, hipEvent_t *evs,
                     hipEvent_t ev0, double *t_done, SweepTimer *tm) {
   const int32_t m = b0.m;
   int32_t running = m;  // last count read back (an upper bound of the device's)
@@ -1237,11 +1257,8 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
       if (i == 0 && tm && hipEventRecord(tm->b[slot], s) != hipSuccess) return NPGA_ERR_HIP;
       if (npga::launch_breduce_tail(b, slots, s)) return NPGA_ERR_HIP;
     }
-    int32_t *ds = dev_status + (size_t)slot * (m + 1);
-    int32_t *hs = pin_status + (size_t)slot * (m + 1);
-    if (npga::launch_bstatus(b, ds, act, mact, s)) return NPGA_ERR_HIP;
-    if (hipMemcpyAsync(hs, ds, sizeof(int32_t) * (size_t)(m + 1), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return NPGA_ERR_HIP;
+    // running count and done codes, stored by the device into the pinned slot
+    if (npga::launch_bstatus(b, pin_status_dev + (size_t)slot * (m + 1), act, mact, s)) return NPGA_ERR_HIP;
     if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
     return NPGA_OK;
   };
@@ -1404,7 +1421,8 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
 
   std::vector<double> t_done(m, -1.0);
   const int64_t main_chunks = (int64_t)o.max_iter / o.check_every + 4;
-  int e = run_batch_phase(b, cfg, slots, o.check_every, main_chunks, stream, dev_status, bp->status, evs, ev0,
+  int e = run_batch_phase(b, cfg, slots, o.check_every, main_chunks, stream, dev_status, bp->status,
+                          bp->status_dev, evs, ev0,
                           t_done.data(), &tm);
   if (e) return e;
   HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost, stream));
@@ -1430,7 +1448,8 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
       LAUNCHCHK(npga::launch_bphase_reset(br, o.refine_tol, o.refine_max_iter, stream));
       LAUNCHCHK(npga::launch_bcg_init(br, slots, stream));
       const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
-      e = run_batch_phase(br, cfg, slots, o.check_every, ref_chunks, stream, dev_status, bp->status, evs, ev0,
+      e = run_batch_phase(br, cfg, slots, o.check_every, ref_chunks, stream, dev_status, bp->status,
+                          bp->status_dev, evs, ev0,
                           t_unused.data(), nullptr);
       if (e) return e;
       HIPCHK(hipMemcpyAsync(bp->states, b.base.st, sizeof(DevState) * (size_t)m, hipMemcpyDeviceToHost,

@@ -239,6 +239,8 @@ int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
 int launch_set_alpha(DevState *st, double step_safety, hipStream_t s, double alpha_fixed = 0.0);  // also beta_const
+// *host_done = st->done, host_done in pinned host memory (device-accessible)
+int launch_status(const DevState *st, int32_t *host_done, hipStream_t s);
 int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s);
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.

@@ -879,6 +879,18 @@ int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
+// The stopping state of a chunk for the host: the done word stored by the
+// device into pinned host memory (visible to the host once the stream has
+// passed this launch), in place of a copy command in the stream.
+__global__ void k_status(const DevState *st, int32_t *host_done) {
+  if (threadIdx.x == 0) *host_done = st->done;
+}
+
+int launch_status(const DevState *st, int32_t *host_done, hipStream_t s) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, st, host_done);
+  return (int)hipGetLastError();
+}
+
 int launch_set_alpha(DevState *st, double step_safety, hipStream_t s, double alpha_fixed) {
   hipLaunchKernelGGL(k_set_alpha, dim3(1), dim3(64), 0, s, st, step_safety, alpha_fixed);
   return (int)hipGetLastError();
