@@ -441,10 +441,8 @@ __global__ __launch_bounds__(256) void k_breduce(BatchArgs b) {
     if (st->done != kRunning) continue;
     const double tot = tile[il][cl];
     if (a.mode == kTailNpga) {
-      const int cur = st->iter & 1;
-      const double *xk = cur ? a.xbuf1 : a.xbuf0;
-      double *gk = cur ? a.gbuf1 : a.gbuf0;
-      gk[i] = 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i];
+      const double *xk = (st->iter & 1) ? a.xbuf1 : a.xbuf0;
+      npga_store_grad_step(a, st, i, 2.0 * tot + (a.ga ? a.ga[i] : 0.0) + 2.0 * st->gamma * xk[i]);
     } else if (a.mode == kTailGrad) {
       a.gbuf0[i] = 2.0 * tot + 2.0 * st->gamma * a.xbuf0[i];
     } else if (a.mode == kTailCG) {

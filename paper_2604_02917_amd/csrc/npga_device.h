@@ -511,4 +511,23 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
   return out;
 }
 
+// The element-wise part of an NPGA iteration at row i, done by the launch
+// that produces the gradient: g_k into its slot and, without backtracking,
+// the step input v = y - alpha grad f(y) with y = x_k + beta (x_k - x_{k-1})
+// and grad f(y) = g_k + beta (g_k - g_{k-1}) (grad f is affine) into the
+// g_{k-1} slot, which the serial tail reads instead of forming the step.
+__device__ __forceinline__ void npga_store_grad_step(const SolveArgs &a, const DevState *st, int64_t i, double gi) {
+  const int cur = st->iter & 1;
+  const double *xk = cur ? a.xbuf1 : a.xbuf0;
+  const double *xp = cur ? a.xbuf0 : a.xbuf1;
+  double *gk = cur ? a.gbuf1 : a.gbuf0;
+  double *gp = cur ? a.gbuf0 : a.gbuf1;
+  gk[i] = gi;
+  if (a.backtrack) return;
+  const double x = xk[i];
+  const double y = fma(st->beta, x - xp[i], x);
+  const double gy = fma(st->beta, gi - gp[i], gi);
+  gp[i] = fma(-st->alpha, gy, y);
+}
+
 }  // namespace npga

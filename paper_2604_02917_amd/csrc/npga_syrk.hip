@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256) void k_symv(SolveArgs a, const float *__restri
       else if (a.mode == kTailCG || a.mode == kTailPdas || a.mode == kTailAdj)
         gk[col] = 2.0 * (double)d + 2.0 * st->gamma * pv[col];
       else
-        gk[col] = 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col];
+        npga_store_grad_step(a, st, col, 2.0 * (double)d + (a.ga ? a.ga[col] : 0.0) + 2.0 * st->gamma * xk[col]);
     }
   };
   f4 c0[E], c1[E];

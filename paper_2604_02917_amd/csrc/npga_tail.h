@@ -37,13 +37,26 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   const double alpha = st->alpha, r = st->r, tolphi = st->tolphi, beta = st->beta;
   BlockReducer<5, NW> red{redbuf, 0};
 
-  // every vector the iteration reads is loaded up front, so the loads of
-  // all five overlap; the step input v = y - alpha grad f(y) and the
-  // momentum direction dx = x_k - x_{k-1} are formed at once, after which
-  // x_{k-1} and g_{k-1} are dead (fewer live vectors in the projections).
-  // With backtracking the step is formed after the test of the pending
-  // trial, which reads that trial's y and grad f(y) from ybt and gybt.
+  // Without backtracking the gradient launch has already formed the step
+  // input v = y - alpha grad f(y) in the g_{k-1} slot (an element-wise
+  // update of its rows), so an iteration loads only mu and v here; x_k and
+  // g_k are loaded for the stopping test and x_{k-1} for the restart test.
+  // With backtracking the step is formed here, after the test of the
+  // pending trial, which reads that trial's y and grad f(y) from ybt and
+  // gybt; every vector it reads is then loaded up front.
   double mu[E], xk[E], gk[E], v[E], dx[E];
+  bool have_xg = false;
+  auto load_xg = [&]() {
+    if (have_xg) return;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      const bool ok = i < n;
+      xk[j] = ok ? xk_p[i] : 0.0;
+      gk[j] = ok ? gk_p[i] : 0.0;
+    }
+    have_xg = true;
+  };
   auto form_step = [&](int j) {
     const int64_t i = tid + NT * j;
     const bool ok = i < n;
@@ -60,14 +73,21 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
       }
     }
   };
+  if constexpr (!BT) {
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + NT * j;
-    const bool ok = i < n;
-    mu[j] = ok ? a.mu[i] : 0.0;
-    xk[j] = ok ? xk_p[i] : 0.0;
-    gk[j] = ok ? gk_p[i] : 0.0;
-    if constexpr (!BT) form_step(j);
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      const bool ok = i < n;
+      mu[j] = ok ? a.mu[i] : 0.0;
+      v[j] = ok ? gp_p[i] : -1.0e300;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int64_t i = tid + NT * j;
+      mu[j] = (i < n) ? a.mu[i] : 0.0;
+    }
+    load_xg();
   }
   if constexpr (BT) {
     if (st->bt_pending) {
@@ -126,6 +146,7 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   }
 
   if (k % st->check_every == 0) {
+    load_xg();
     double w[E];
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
@@ -176,6 +197,14 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
   if (st->restart) {
     // gradient restart test (y - x_{k+1})^T (x_{k+1} - x_k) > 0 with
     // y - x_k = beta dx
+    load_xg();
+    if constexpr (!BT) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t i = tid + NT * j;
+        dx[j] = (i < n) ? xk[j] - xn_p[i] : 0.0;
+      }
+    }
     double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
