@@ -255,6 +255,18 @@ __device__ __forceinline__ double simplex_tau(const double (&v)[E], const double
 
 // One pass that also counts membership changes against the previous pass
 // (per-thread bit masks, E <= 32).
+// Whether the support {j : v_j + nu mu_j > tau} differs from mask in any
+// thread (every thread gets the answer): one barrier and no sums, for the
+// test that a Newton point keeps the support it was computed on.
+template <int E>
+__device__ __forceinline__ bool support_changes(const double (&v)[E], const double (&mu)[E], double nu, double tau,
+                                                uint32_t mask) {
+  uint32_t nm = 0u;
+#pragma unroll
+  for (int j = 0; j < E; ++j) nm |= ((fma(nu, mu[j], v[j]) > tau) ? 1u : 0u) << j;
+  return __syncthreads_or(nm != mask ? 1 : 0) != 0;
+}
+
 template <int E, int NW>
 __device__ __forceinline__ PassSums proj_pass_masked(const double (&v)[E], const double (&mu)[E], double nu,
                                                      double tau, uint32_t &mask, double &changed,
@@ -413,10 +425,8 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
       const double tn = (b1 * s.smm - s.sm * b2) / det;
       const double nn = (s.sm * b1 - s.c * b2) / det;
       if (!(nn > 0.0) || !isfinite(tn)) break;
-      s = proj_pass_masked<E, NW>(v, mu, nn, tn, mask, changed, red.buf);
       ++passes;
-      __syncthreads();
-      if (changed == 0.0) {
+      if (!support_changes<E>(v, mu, nn, tn, mask)) {
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] = fmax(fma(nn, mu[j], v[j]) - tn, 0.0);
         out.nu = nn;
@@ -425,6 +435,9 @@ __device__ ProjResult project_F(double (&v)[E], const double (&mu)[E], double r,
         out.flags = flags;
         return out;
       }
+      // the support moved: its sums for the next Newton step
+      s = proj_pass_masked<E, NW>(v, mu, nn, tn, mask, changed, red.buf);
+      __syncthreads();
     }
   }
   const double INF = 1.0e308;
