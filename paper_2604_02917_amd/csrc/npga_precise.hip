@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_precise_u(const TL *L, int64_t ld, int6
       d = fma((double)c[j].w, xr[4 * j + 3], d);
     }
     d = wave_sum_f64(d);
-    if (lane == 0) u[col] = d;
+    if (lane == 0 && u) u[col] = d;
   }
 }
 
@@ -100,6 +100,87 @@ __global__ __launch_bounds__(256) void k_precise_g(const TL *L, int64_t ld, int6
   }
   double *out = part + (int64_t)blockIdx.x * ldp;
   for (int idx = threadIdx.x; idx < 256 * E; idx += 256) out[idx] = sh[idx];
+}
+
+// Both products in one pass over L, the order of the fused float32 sweep:
+// per column t, u_t = L_t . x (float64 products and sums, all lanes hold it
+// after the wave sum) and then g += L_t u_t (float64).  x lives in LDS
+// (float64, 8 KB per slot), so g and two column buffers fit the registers
+// and the next column loads while this one is used.  Per-workgroup float64
+// partials of g as in k_precise_g.  Up to 22 slots (n <= 5632).
+template <int E, typename TL>
+__global__ __launch_bounds__(256) void k_precise_sweep(const TL *L, int64_t ld, int64_t n, int64_t cols,
+                                                       const double *x, double *u, double *part,
+                                                       int64_t ldp) {
+  __shared__ double xsh[256 * E];  // x; after the sweep, the combine buffer
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t W = (int64_t)gridDim.x * 4;
+  // entry 4 lane + 256 j + e of x at xsh[(4 j + e) 64 + lane]: a wavefront
+  // reads 64 consecutive doubles per (j, e)
+  for (int q = threadIdx.x; q < 256 * E; q += 256) {
+    const int l = q & 63, je = q >> 6, j = je >> 2, e = je & 3;
+    const int64_t i = 4 * l + 256 * j + e;
+    xsh[q] = (i < n) ? x[i] : 0.0;
+  }
+  double g[4 * E];
+#pragma unroll
+  for (int j = 0; j < 4 * E; ++j) g[j] = 0.0;
+  __syncthreads();
+  // zero the compiler cannot see through (n < 2^62): the update below
+  // widens the column again instead of keeping the float64 values of the
+  // dot product live across its wave sum
+  const unsigned int z = (unsigned int)((uint64_t)n >> 62);
+  auto wide = [&](float v) { return (double)__uint_as_float(__float_as_uint(v) ^ z); };
+  auto process = [&](const f4(&c)[E], int64_t col) {
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      d = fma((double)c[j].x, xsh[(4 * j + 0) * 64 + lane], d);
+      d = fma((double)c[j].y, xsh[(4 * j + 1) * 64 + lane], d);
+      d = fma((double)c[j].z, xsh[(4 * j + 2) * 64 + lane], d);
+      d = fma((double)c[j].w, xsh[(4 * j + 3) * 64 + lane], d);
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads of x next to their use
+    }
+    d = wave_sum_f64(d);
+    if (lane == 0 && u) u[col] = d;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      g[4 * j + 0] = fma(wide(c[j].x), d, g[4 * j + 0]);
+      g[4 * j + 1] = fma(wide(c[j].y), d, g[4 * j + 1]);
+      g[4 * j + 2] = fma(wide(c[j].z), d, g[4 * j + 2]);
+      g[4 * j + 3] = fma(wide(c[j].w), d, g[4 * j + 3]);
+    }
+  };
+  f4 c0[E], c1[E];
+  int64_t col = (int64_t)blockIdx.x * 4 + wave;
+  if (col < cols) load_col_masked<E, TL>(L, ld, n, col, lane, c0);
+  while (col < cols) {
+    const int64_t col1 = col + W;
+    if (col1 < cols) load_col_masked<E, TL>(L, ld, n, col1, lane, c1);
+    process(c0, col);
+    if (col1 >= cols) break;
+    const int64_t col2 = col1 + W;
+    if (col2 < cols) load_col_masked<E, TL>(L, ld, n, col2, lane, c0);
+    process(c1, col1);
+    col = col2;
+  }
+  // combine wavefronts 0..3 in a fixed order (x is no longer needed)
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int idx = 4 * lane + 256 * j + e;
+          xsh[idx] = (w == 0) ? g[4 * j + e] : xsh[idx] + g[4 * j + e];
+        }
+    }
+    __syncthreads();
+  }
+  double *out = part + (int64_t)blockIdx.x * ldp;
+  for (int idx = threadIdx.x; idx < 256 * E; idx += 256) out[idx] = xsh[idx];
 }
 
 __global__ __launch_bounds__(256) void k_precise_reduce(const double *part, int G, int64_t ldp, int64_t n,
@@ -146,7 +227,30 @@ int launch_add_ridge(const SolveArgs &a, hipStream_t s) {
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,
                             double *part, int slots, hipStream_t s) {
   const int G = sweep_grid_for(a.cols);
-  if (a.dtype == NPGA_BF16) {
+  if (slots <= 22) {
+    // one pass over L
+#define ONEPASS(E, TL)                                                                                       \
+  hipLaunchKernelGGL((k_precise_sweep<E, TL>), dim3(G), dim3(256), 0, s, static_cast<const TL *>(a.L), a.ld, \
+                     a.n, a.cols, x, u_out, part, a.ldp)
+#define ONEPASS_SWITCH(TL)                     \
+  switch (slots) {                             \
+    case 1: ONEPASS(1, TL); break;             \
+    case 2: ONEPASS(2, TL); break;             \
+    case 4: ONEPASS(4, TL); break;             \
+    case 8: ONEPASS(8, TL); break;             \
+    case 12: ONEPASS(12, TL); break;           \
+    case 16: ONEPASS(16, TL); break;           \
+    case 22: ONEPASS(22, TL); break;           \
+    default: return (int)hipErrorInvalidValue; \
+  }
+    if (a.dtype == NPGA_BF16) {
+      ONEPASS_SWITCH(bf16_t)
+    } else {
+      ONEPASS_SWITCH(float)
+    }
+#undef ONEPASS_SWITCH
+#undef ONEPASS
+  } else if (a.dtype == NPGA_BF16) {
     const bf16_t *L = static_cast<const bf16_t *>(a.L);
 #define CALL(E) hipLaunchKernelGGL((k_precise_u<E, bf16_t>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, x, u_out)
     PRECISE_SLOT_SWITCH(slots, CALL)
