@@ -327,24 +327,26 @@ int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max
               DevState *pin, hipEvent_t *evs, hipEvent_t ev0, int *done_out, double *phase_ms,
               SweepTimer *tm) {
   int64_t issued = 0, consumed = 0;
+  // the last tail of a chunk stores the chunk's done word into its pinned slot
+  Carved last = c;
   auto issue = [&](int slot) -> int {
+    last.a.host_done = pinned_dev(pin, &pin[slot].done);
     for (int i = 0; i < check_every; ++i) {
+      const Carved &ci = (i == check_every - 1) ? last : c;
       if (i == 0 && tm) {
         // time the first gradient launch of every chunk on this stream
         if (hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
-        const int e = (path == NPGA_PATH_SYRK) ? npga::launch_symv(c.a, c.sigma, c.lds, slots, s)
-                                               : npga::launch_sweep(c.a, slots, s);
+        const int e = (path == NPGA_PATH_SYRK) ? npga::launch_symv(ci.a, ci.sigma, ci.lds, slots, s)
+                                               : npga::launch_sweep(ci.a, slots, s);
         if (e) return NPGA_ERR_HIP;
         if (hipEventRecord(tm->b[slot], s) != hipSuccess) return NPGA_ERR_HIP;
-        const int e2 = (path == NPGA_PATH_SYRK) ? npga::launch_tail(c.a, slots, 1, s)
-                                                : npga::launch_reduce_tail(c.a, slots, s);
+        const int e2 = (path == NPGA_PATH_SYRK) ? npga::launch_tail(ci.a, slots, 1, s)
+                                                : npga::launch_reduce_tail(ci.a, slots, s);
         if (e2) return NPGA_ERR_HIP;
         continue;
       }
-      if (step(c, path, slots, s)) return NPGA_ERR_HIP;
+      if (step(ci, path, slots, s)) return NPGA_ERR_HIP;
     }
-    // the chunk's done word, stored by the device into the pinned slot
-    if (npga::launch_status(c.st, pinned_dev(pin, &pin[slot].done), s)) return NPGA_ERR_HIP;
     if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
     return NPGA_OK;
   };

@@ -156,6 +156,10 @@ struct SolveArgs {
   double *pvec;        // search direction p
   double *fvec;        // 1 where x_i is free on the face, 0 where x_i is fixed at 0
   double *gvec;        // gradient maintained by linearity
+  // when set (the last iteration of a chunk), the one-workgroup tail stores
+  // st->done here at its end: a word of pinned host memory the host reads
+  // once the chunk's event has passed
+  int32_t *host_done;
 };
 
 // m independent solves sharing L (one target return per solve).  Target j
@@ -239,8 +243,7 @@ int launch_phase(DevState *st, int32_t phase_kind, double tol, int32_t max_iter,
                  hipStream_t s);
 int launch_set_tolphi(DevState *st, double proj_tol, hipStream_t s);
 int launch_set_alpha(DevState *st, double step_safety, hipStream_t s, double alpha_fixed = 0.0);  // also beta_const
-// *host_done = st->done, host_done in pinned host memory (device-accessible)
-int launch_status(const DevState *st, int32_t *host_done, hipStream_t s);
+
 int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s);
 
 // Symmetric rank-T update Sigma = L L^T (MFMA) and the covariance-path kernels.

@@ -474,69 +474,76 @@ __global__ __launch_bounds__(1024) void k_reduce(SolveArgs a) {
 // The serial tails of one iteration, one kernel per mode (one workgroup
 // each), so that each carries only its own mode's registers.  `covariance`
 // selects the objective source: the sweep's ||L^T x||^2 partials on the
-// factor path, 1/2 x^T g on the covariance path.
+// factor path, 1/2 x^T g on the covariance path.  At the end of a chunk
+// (a.host_done set) every tail stores the done word for the host.
+__device__ __forceinline__ void store_host_done(const SolveArgs &a) {
+  if (!a.host_done) return;
+  __syncthreads();  // the tail's last state writes, by any thread
+  if (threadIdx.x == 0) *a.host_done = a.st->done;
+}
+
 template <int E, int NW>
 __global__ __launch_bounds__(64 * NW) void k_tail_npga(SolveArgs a, int covariance) {
-  DevState *st = a.st;
-  if (st->done != kRunning) return;
   __shared__ double redbuf[red_buf_doubles<NW>()];
-  tail_npga<E, false, false, NW>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  DevState *st = a.st;
+  if (st->done == kRunning) tail_npga<E, false, false, NW>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  store_host_done(a);
 }
 
 template <int E, int NW>
 __global__ __launch_bounds__(64 * NW) void k_tail_cg(SolveArgs a) {
-  if (a.st->done != kRunning) return;
   __shared__ double redbuf[red_buf_doubles<NW>()];
   __shared__ double mbuf[2 * NW];
   __shared__ int64_t ibuf[2 * NW];
-  tail_cg<E, NW>(a, redbuf, mbuf, ibuf);
+  if (a.st->done == kRunning) tail_cg<E, NW>(a, redbuf, mbuf, ibuf);
+  store_host_done(a);
 }
 
 template <int E, int NW>
 __global__ __launch_bounds__(64 * NW) void k_tail_pdas(SolveArgs a) {
-  if (a.st->done != kRunning) return;
   __shared__ double redbuf[red_buf_doubles<NW>()];
-  tail_pdas<E, NW>(a, redbuf);
+  if (a.st->done == kRunning) tail_pdas<E, NW>(a, redbuf);
+  store_host_done(a);
 }
 
 template <int E>
 __global__ __launch_bounds__(256) void k_tail_adj(SolveArgs a) {
-  if (a.st->done != kRunning) return;
   __shared__ double redbuf[64];
-  tail_adj<E>(a, redbuf);
+  if (a.st->done == kRunning) tail_adj<E>(a, redbuf);
+  store_host_done(a);
 }
 
 template <int E>
 __global__ __launch_bounds__(256) void k_tail_power(SolveArgs a, int covariance) {
-  DevState *st = a.st;
-  if (st->done != kRunning) return;
   __shared__ double redbuf[64];
-  tail_power<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  DevState *st = a.st;
+  if (st->done == kRunning) tail_power<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  store_host_done(a);
 }
 
 template <int E>
 __global__ __launch_bounds__(256) void k_tail_lanczos(SolveArgs a) {
-  if (a.st->done != kRunning) return;
   __shared__ double redbuf[64];
-  tail_lanczos<E>(a, redbuf);
+  if (a.st->done == kRunning) tail_lanczos<E>(a, redbuf);
+  store_host_done(a);
 }
 
 template <int E>
 __global__ __launch_bounds__(256) void k_tail_grad(SolveArgs a, int covariance) {
-  DevState *st = a.st;
-  if (st->done != kRunning) return;
   __shared__ double redbuf[64];
-  tail_grad<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  DevState *st = a.st;
+  if (st->done == kRunning) tail_grad<E>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  store_host_done(a);
 }
 
 // The NPGA tail with Dykstra's projections (options.projection = 1) and/or
 // adaptive backtracking (options.backtrack_rho > 0).
 template <int E, bool DYK, bool BT>
 __global__ __launch_bounds__(256) void k_tail_var(SolveArgs a, int covariance) {
-  DevState *st = a.st;
-  if (st->done != kRunning) return;
   __shared__ double redbuf[64];
-  tail_npga<E, DYK, BT>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  DevState *st = a.st;
+  if (st->done == kRunning) tail_npga<E, DYK, BT>(a, covariance ? -1.0 : st->usq_sweep, redbuf);
+  store_host_done(a);
 }
 
 template <int E>
@@ -874,18 +881,6 @@ __global__ __launch_bounds__(256) void k_lanczos_init(SolveArgs a, double tol) {
 
 int launch_lanczos_init(const SolveArgs &a, double tol, hipStream_t s) {
   hipLaunchKernelGGL(k_lanczos_init, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, tol);
-  return (int)hipGetLastError();
-}
-
-// The stopping state of a chunk for the host: the done word stored by the
-// device into pinned host memory (visible to the host once the stream has
-// passed this launch), in place of a copy command in the stream.
-__global__ void k_status(const DevState *st, int32_t *host_done) {
-  if (threadIdx.x == 0) *host_done = st->done;
-}
-
-int launch_status(const DevState *st, int32_t *host_done, hipStream_t s) {
-  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, s, st, host_done);
   return (int)hipGetLastError();
 }
 

@@ -156,7 +156,9 @@ __device__ void tail_npga(const SolveArgs &a, double usq_total, double *redbuf) 
       acc[2] += (xk[j] > 0.0) ? 1.0 : 0.0;
       acc[3] = fma(xk[j], gk[j], acc[3]);
     }
-    const ProjResult pr = project_F<E, DYK, NW>(w, mu, r, tolphi, st->nu_c, st->tau_c, red, st->dykstra_iters);
+    // warm start from the last step's projection (one iteration old, where
+    // the last test's multipliers are check_every iterations old)
+    const ProjResult pr = project_F<E, DYK, NW>(w, mu, r, tolphi, st->nu, st->tau, red, st->dykstra_iters);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const double d = w[j] - xk[j];
