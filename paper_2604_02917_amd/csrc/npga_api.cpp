@@ -1028,6 +1028,10 @@ struct BatchLayout {
 };
 
 constexpr int kMaxSplits = 64;
+// Tile of the covariance form's GEMM 2 Sigma X whatever the number of running
+// targets: 64 x 64 (the table's 64 x 64 entry; measured at C4 against the
+// factor form's choice of 128 x m-wide tiles: 6535 vs 5304 solves/s)
+constexpr int kCovConfig = 6;
 constexpr int kNumVec = 9;  // xbuf0, xbuf1, gbuf0, gbuf1, pvec, fvec, gvec, xa, ga
 
 // cov: the covariance form (Sigma, the bfloat16 planes the SYRK reads, and a
@@ -1090,11 +1094,13 @@ bool batch_uses_covariance(int requested, int64_t n, int64_t cols) {
 npga::BatchArgs with_config(npga::BatchArgs b, const npga::BatchConfig &cfg) {
   const int64_t cols = b.base.cols;
   if (b.covariance) {
-    // Sigma X split over the contraction so that a launch has a few
-    // hundred workgroups (chunks of whole 32-row stages)
+    // Sigma X split over the contraction so that a launch has about 512
+    // workgroups (chunks of whole 32-row stages; measured at n = 2000 with
+    // 64 x 64 tiles: 4, 6, 8, 11 and 16 ranges gave 5892, 5536, 6535, 5917
+    // and 6336 frontier solves/s)
     const int64_t n = b.base.n;
     const int64_t tiles = ((n + cfg.u_bm - 1) / cfg.u_bm) * ((b.m + cfg.u_bn - 1) / cfg.u_bn);
-    int64_t want = std::max<int64_t>(1, std::min<int64_t>((384 + tiles - 1) / tiles, kMaxSplits));
+    int64_t want = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, kMaxSplits));
     want = std::min<int64_t>(want, (n + 31) / 32);
     const int64_t kc = ((n + want - 1) / want + 31) / 32 * 32;
     b.kchunk = kc;
@@ -1251,7 +1257,8 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
   // GEMM columns = targets running at the start of the phase
   if (npga::launch_bstatus(b0, dev_status, act, mact, s)) return NPGA_ERR_HIP;
   auto issue = [&](int slot) -> int {
-    const npga::BatchConfig &cfg = config_for_running(req, b0.base.n, b0.base.cols, running);
+    const npga::BatchConfig &cfg =
+        b0.covariance ? req : config_for_running(req, b0.base.n, b0.base.cols, running);
     const npga::BatchArgs b = with_config(b0, cfg);
     for (int i = 0; i < check_every; ++i) {
       if (i == 0 && tm && hipEventRecord(tm->a[slot], s) != hipSuccess) return NPGA_ERR_HIP;
@@ -1345,7 +1352,7 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
   if (!pin || !bp) return NPGA_ERR_HIP;
   // the covariance form tiles by the batch width (batch_config tunes the
   // factor form's GEMM pair)
-  const npga::BatchConfig &cfg = cov ? npga::kBatchConfigTable[npga::batch_default_config(f->n, f->n, m)]
+  const npga::BatchConfig &cfg = cov ? npga::kBatchConfigTable[kCovConfig]
                                      : batch_config_of(o.batch_config, f->n, f->cols, m);
   Carved c = carve(f, lay.single, ws, NPGA_PATH_GEMV);
   npga::BatchArgs b = carve_batch(f, lay, ws, m, cfg);
