@@ -170,3 +170,37 @@ def test_auto_path_parity(npga, n, T, want):
     x, info = npga.solve(L, mu, r, gamma=gamma)
     assert info["status"] == 0 and info["path_used"] == want, info
     _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, gamma, ref, f"auto {n}x{T}")
+
+
+@pytest.mark.parametrize("path", ["gemv", "syrk"])
+@pytest.mark.parametrize("check_every", [1, 3, 7])
+def test_check_every(npga, check_every, path):
+    """The stopping test every check_every iterations (Algorithm 1's KKT check):
+    the iteration count is a multiple of it, the last tail of each chunk of
+    check_every launches reports the chunk's state to the host, and the
+    refined solution is the oracle's."""
+    spec = spec_with("c2", 300, 2500, seed=33)
+    banner(f"check_every={check_every} {path}")
+    Rt, r, mu_ref, L_ref, ref = _case(spec)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, check_every=check_every, path=path)
+    assert info["status"] == 0 and info["refined"] == 1, info
+    assert info["iters"] % check_every == 0, info["iters"]
+    assert info["residual"] <= 1e-6
+    _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, 0.0, ref, f"check_every={check_every}")
+
+
+def test_batched_deterministic(npga):
+    """Fixed launch shapes and fixed summation orders: two batched solves
+    (main phase, float64 anchors of the refinement, face steps) give the
+    same bits."""
+    spec = spec_with("c4", 400, 3000, seed=34)
+    Rt = gen.returns_TxN(spec)
+    L, mu = npga.build_factor(to_dev(Rt))
+    mu_h = mu.cpu().numpy()
+    rs = list(np.linspace(float(np.quantile(mu_h, 0.5)), 0.9 * float(mu_h.max()), 70))
+    for path in ("gemv", "syrk"):
+        Xa, ia = npga.solve_batched(L, mu, rs, path=path)
+        Xb, ib = npga.solve_batched(L, mu, rs, path=path)
+        assert torch.equal(Xa, Xb), path
+        assert [i["objective"] for i in ia] == [i["objective"] for i in ib], path
