@@ -58,6 +58,27 @@ int32_t *pinned_dev(const DevState *pin, const int32_t *host_word) {
                                                   reinterpret_cast<const char *>(pin)));
 }
 
+// A status word the device stores into pinned host memory is set to
+// kStatusUnset by the host before the chunk is issued.  Once the chunk's
+// event has completed the device's store is visible; should it not be
+// (a platform that delays the store past the event), the host waits up to
+// a millisecond for it and otherwise reports an error instead of reading
+// a stale word.
+constexpr int32_t kStatusUnset = -0x5eed;
+
+bool read_status(const int32_t *word, int32_t *out) {
+  const volatile int32_t *w = word;
+  int32_t v = *w;
+  if (v == kStatusUnset) {
+    const auto t0 = std::chrono::steady_clock::now();
+    while ((v = *w) == kStatusUnset &&
+           std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(1)) {
+    }
+  }
+  *out = v;
+  return v != kStatusUnset;
+}
+
 #define HIPCHK(expr)                                   \
   do {                                                 \
     if ((expr) != hipSuccess) return NPGA_ERR_HIP;     \
@@ -330,6 +351,7 @@ int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max
   // the last tail of a chunk stores the chunk's done word into its pinned slot
   Carved last = c;
   auto issue = [&](int slot) -> int {
+    pin[slot].done = kStatusUnset;
     last.a.host_done = pinned_dev(pin, &pin[slot].done);
     for (int i = 0; i < check_every; ++i) {
       const Carved &ci = (i == check_every - 1) ? last : c;
@@ -360,7 +382,8 @@ int run_phase(const Carved &c, int path, int slots, int check_every, int64_t max
     const int slot = consumed & 1;
     if (hipEventSynchronize(evs[slot]) != hipSuccess) return NPGA_ERR_HIP;
     ++consumed;
-    const int done = pin[slot].done;
+    int32_t done = 0;
+    if (!read_status(&pin[slot].done, &done)) return NPGA_ERR_HIP;
     if (tm && done == npga::kRunning) {  // only chunks that ran every launch in full
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, tm->a[slot], tm->b[slot]) == hipSuccess) {
@@ -1267,6 +1290,7 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
       if (npga::launch_breduce_tail(b, slots, s)) return NPGA_ERR_HIP;
     }
     // running count and done codes, stored by the device into the pinned slot
+    pin_status[(size_t)slot * (m + 1)] = kStatusUnset;
     if (npga::launch_bstatus(b, pin_status_dev + (size_t)slot * (m + 1), act, mact, s)) return NPGA_ERR_HIP;
     if (hipEventRecord(evs[slot], s) != hipSuccess) return NPGA_ERR_HIP;
     return NPGA_OK;
@@ -1284,6 +1308,8 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
     if (hipEventSynchronize(evs[slot]) != hipSuccess) return NPGA_ERR_HIP;
     ++consumed;
     const int32_t *hs = pin_status + (size_t)slot * (m + 1);
+    int32_t nrun = 0;
+    if (!read_status(hs, &nrun)) return NPGA_ERR_HIP;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, evs[slot]);
     for (int32_t j = 0; j < m; ++j) {
@@ -1292,15 +1318,15 @@ int run_batch_phase(const npga::BatchArgs &b0, const npga::BatchConfig &req, int
         if (t_done[j] < 0) t_done[j] = ms;
       }
     }
-    running = hs[0];
-    if (tm && hs[0] == m) {  // pairs over the full batch only
+    running = nrun;
+    if (tm && nrun == m) {  // pairs over the full batch only
       float g = 0.f;
       if (hipEventElapsedTime(&g, tm->a[slot], tm->b[slot]) == hipSuccess) {
         tm->total_ms += g;
         tm->samples += 1;
       }
     }
-    if (hs[0] == 0) {
+    if (nrun == 0) {
       if (hipStreamSynchronize(s) != hipSuccess) return NPGA_ERR_HIP;
       return NPGA_OK;
     }
