@@ -233,12 +233,15 @@ int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb,
  * beta_k = (t_k - 1)/t_{k+1}, and x^{k+1} = Pi_F(y^k - alpha grad f(y^k)).
  * Pi_F is computed exactly by the scalar dual search of eq. projF-dualpath
  * (Sec. 3.1).  The stopping rule is checked every check_every iterations.
- * With refine = 1 the iteration then continues (momentum restarted,
- * adaptive restart on) until the residual reaches refine_tol, using
- * mixed-precision iterative refinement: the gradient at the stopping point
- * x_a is recomputed with float64 products, and later gradients are
+ * With refine = 1 a float64 KKT refinement follows (mixed-precision
+ * iterative refinement): the gradient at the stopping point x_a is
+ * recomputed with float64 products, later gradients are
  * g_a + 2 L L^T (x - x_a) + 2 gamma x with the float32 sweep applied to the
- * small correction x - x_a.
+ * small correction x - x_a, and the face of the active set is solved by an
+ * inexact primal-dual active-set method (CG on the face, the KKT sign rules
+ * move the face) or, per refine_method, by face CG with blocking steps; the
+ * result is re-anchored in float64 once and the refinement ends on the KKT
+ * test (res->refined = 1).
  *   f      (host) effective factor and ridge; n <= NPGA_MAX_N
  *   r      target return R_target; r > max mu gives NPGA_ERR_INFEASIBLE
  *   opt    (host) options, or NULL for the defaults
@@ -409,8 +412,9 @@ int npga_sketch_str(const float *L, int64_t n, int64_t T, int64_t ldl, int64_t k
  * Every target runs Algorithm 1 with its own iterate, momentum, projection
  * and stopping test (Sec. 3.1), the shared step alpha = 1/(safety L_f_hat)
  * of one step estimate, and a float64 face refinement (face CG with
- * blocking steps).  The gradients of all targets come from matrix-core
- * GEMMs on the targets still running: in the factor form (opt->path GEMV)
+ * blocking steps; the float64 anchor gradients of all targets come from
+ * two float64 matrix-core GEMMs with L).  The gradients of all targets
+ * come from matrix-core GEMMs on the targets still running: in the factor form (opt->path GEMV)
  * two per iteration, U^T = X^T L and G = 2 L U, so L is read twice per
  * iteration for all m targets; in the covariance form (opt->path SYRK, or
  * AUTO with the single solve's rule: cols >= n and Sigma plus the SYRK
