@@ -1046,14 +1046,15 @@ struct BatchLayout {
   SolveLayout single;
   size_t off_states, off_X, off_vec, off_Ut, off_P, off_usq, off_status, off_act, off_U16, off_Lt, off_sigma,
       off_planes, off_l32, off_prec, total;
-  int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt, lds, ld32;
+  int64_t npad, ldx, ldut, ldpm, ldq, ldu16, ldlt, lds, ld32, ldsp;
   bool cov;
 };
 
 constexpr int kMaxSplits = 64;
 // Tile of the covariance form's GEMM 2 Sigma X whatever the number of running
-// targets: 64 x 64 (the table's 64 x 64 entry; measured at C4 against the
-// factor form's choice of 128 x m-wide tiles: 6535 vs 5304 solves/s)
+// targets: 64 x 64 (the table's 64 x 64 entry; measured at C4 with the
+// float32 GEMM against the factor form's choice of 128 x m-wide tiles: 6535
+// vs 5304 solves/s; the bfloat16 split-plane GEMM takes the same tile)
 constexpr int kCovConfig = 6;
 constexpr int kNumVec = 9;  // xbuf0, xbuf1, gbuf0, gbuf1, pvec, fvec, gvec, xa, ga
 
@@ -1092,7 +1093,10 @@ BatchLayout batch_layout(int64_t n, int64_t cols, int32_t m, bool cov = false) {
   if (cov) {
     l.off_U16 = l.off_Lt = 0;
     l.off_sigma = take(sizeof(float) * (size_t)l.lds * (size_t)n);
-    l.off_planes = take(npga::syrk_split_bytes(n, cols));
+    // the SYRK's planes of L, then (once Sigma is formed) Sigma's three
+    // bfloat16 planes for the iteration GEMM
+    l.ldsp = (n + 63) / 64 * 64;
+    l.off_planes = take(std::max(npga::syrk_split_bytes(n, cols), sizeof(uint16_t) * 3 * (size_t)n * (size_t)l.ldsp));
     l.off_l32 = take(sizeof(float) * (size_t)l.ld32 * (size_t)cols);
   } else {
     // bfloat16 factors: U planes and the row-major copy of L
@@ -1119,8 +1123,8 @@ npga::BatchArgs with_config(npga::BatchArgs b, const npga::BatchConfig &cfg) {
   if (b.covariance) {
     // Sigma X split over the contraction so that a launch has about 512
     // workgroups (chunks of whole 32-row stages; measured at n = 2000 with
-    // 64 x 64 tiles: 4, 6, 8, 11 and 16 ranges gave 5892, 5536, 6535, 5917
-    // and 6336 frontier solves/s)
+    // 64 x 64 tiles and the split-plane GEMM: 256, 384, 512, 768 and 1024
+    // workgroups took 20.5, 18.4, 16.0, 20.0 and 18.2 us per iteration)
     const int64_t n = b.base.n;
     const int64_t tiles = ((n + cfg.u_bm - 1) / cfg.u_bm) * ((b.m + cfg.u_bn - 1) / cfg.u_bn);
     int64_t want = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, kMaxSplits));
@@ -1438,8 +1442,14 @@ int npga_solve_batched(const npga_factor *f, const double *r_targets, int32_t m,
       L32 = w;
       ld32 = lay.ld32;
     }
-    LAUNCHCHK(npga::launch_syrk_split(L32, f->n, f->cols, ld32, reinterpret_cast<uint16_t *>(base + lay.off_planes),
-                                      sigma, lay.lds, stream));
+    uint16_t *planes = reinterpret_cast<uint16_t *>(base + lay.off_planes);
+    LAUNCHCHK(npga::launch_syrk_split(L32, f->n, f->cols, ld32, planes, sigma, lay.lds, stream));
+    // Sigma's bfloat16 planes over the SYRK's (the SYRK is done with them
+    // in stream order): the iteration GEMM runs on the bfloat16 matrix cores
+    LAUNCHCHK(npga::launch_split_rows(sigma, f->n, f->n, lay.lds, planes, lay.ldsp, f->n * lay.ldsp, stream));
+    b.Sp = planes;
+    b.ldsp = lay.ldsp;
+    b.spplane = f->n * lay.ldsp;
     b.base.L = sigma;
     b.base.ld = lay.lds;
     b.base.cols = f->n;

@@ -14,6 +14,8 @@
 //               (stopping test, momentum, projection; or a face-CG step).
 // L is read twice per iteration for all m targets instead of once per
 // target, and the arithmetic moves from the vector ALUs to the matrix cores.
+// The covariance form (Sigma = L L^T formed once) replaces the GEMM pair by
+// one GEMM P[s] = Sigma[:, K_s] X[K_s, :] (k_cov16).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -26,6 +28,8 @@ namespace npga {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 const BatchConfig kBatchConfigTable[kBatchConfigs] = {
     {128, 128, 128, 128, 16}, {128, 128, 128, 128, 32}, {64, 128, 128, 128, 32}, {64, 128, 64, 128, 32},
@@ -674,12 +678,130 @@ static int launch_bgemm_t(const BatchArgs &b, const BatchConfig &c, hipStream_t 
   return (int)hipGetLastError();
 }
 
-// Covariance form: G = Sigma X by the U GEMM on L := Sigma (symmetric),
-// split over the contraction; k_breduce sums the splits.
+// Covariance form on the bfloat16 matrix cores: P_z = Sigma[:, K_z] X[K_z, :]
+// (the split-partial layout k_breduce sums) with Sigma given as three
+// bfloat16 planes (split once per call) and each float32 column of X split
+// into three planes as it is staged, v = v_h + v_m + v_l exactly; the six
+// largest plane products (h h, h m, m h, h l, m m, l h: the dropped m l,
+// l m and l l are below 2^-24 of the leading one) on
+// v_mfma_f32_32x32x16_bf16 with float32 accumulation over the range, as the
+// split SYRK does.  Tile: 64 rows of Sigma x 64 GEMM columns,
+// four wavefronts of 32 x 32; 32-deep stages of both panels, double
+// buffered.  Grid: (row tiles, column tiles, ranges).
+constexpr int C16K = 32;            // contraction depth of one stage
+constexpr int C16LD = C16K + 8;     // LDS row length in bfloat16 (80 bytes)
+
+__global__ __launch_bounds__(256) void k_cov16(BatchArgs b) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][3][64 * C16LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][3][64 * C16LD];
+  const int64_t n = b.base.n;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t j0 = (int64_t)blockIdx.y * 64;
+  const int ma = *b.mact;
+  if (j0 >= ma) return;
+  const int64_t kbeg = (int64_t)blockIdx.z * b.kchunk;
+  const int64_t kend = (kbeg + b.kchunk < n) ? kbeg + b.kchunk : n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int h = lane >> 5, r = lane & 31;
+  // staging: row tid / 4 of each panel, contraction entries 8 (tid % 4) .. +7
+  // of a stage
+  const int prow = tid >> 2, pseg = 8 * (tid & 3);
+  const bool oka = i0 + prow < n;
+  const uint16_t *pa = b.Sp + (i0 + prow) * b.ldsp + pseg;
+  const int64_t cb = j0 + prow;
+  const float *xc = (cb < ma) ? b.base.xs + (int64_t)b.act[cb] * b.ldx + pseg : nullptr;
+  u4v ra[3];
+  f4 rx[2];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl)
+      ra[pl] = oka ? *reinterpret_cast<const u4v *>(pa + pl * b.spplane + k0) : u4v{0u, 0u, 0u, 0u};
+    // k0 + pseg + 8 <= ldx (X columns are padded to a multiple of 256), so
+    // both loads stay in the column; entries at or past kend are masked at
+    // the split
+    rx[0] = xc ? *reinterpret_cast<const f4 *>(xc + k0) : f4{0.f, 0.f, 0.f, 0.f};
+    rx[1] = xc ? *reinterpret_cast<const f4 *>(xc + k0 + 4) : f4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto sstore = [&](int buf, int64_t k0) {
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) *reinterpret_cast<u4v *>(&As[buf][pl][prow * C16LD + pseg]) = ra[pl];
+    const float v[8] = {rx[0].x, rx[0].y, rx[0].z, rx[0].w, rx[1].x, rx[1].y, rx[1].z, rx[1].w};
+    uint32_t hw[4], mw[4], lw[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t h2[2], m2[2], l2[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float x = (k0 + pseg + 2 * w + e < kend) ? v[2 * w + e] : 0.f;
+        const uint32_t hb = (__float_as_uint(x) + 0x7fffu + ((__float_as_uint(x) >> 16) & 1u)) >> 16;
+        const float r1 = x - __uint_as_float(hb << 16);
+        const uint32_t mb = (__float_as_uint(r1) + 0x7fffu + ((__float_as_uint(r1) >> 16) & 1u)) >> 16;
+        const float r2 = r1 - __uint_as_float(mb << 16);
+        h2[e] = hb;
+        m2[e] = mb;
+        l2[e] = (__float_as_uint(r2) + 0x7fffu + ((__float_as_uint(r2) >> 16) & 1u)) >> 16;
+      }
+      hw[w] = h2[0] | (h2[1] << 16);
+      mw[w] = m2[0] | (m2[1] << 16);
+      lw[w] = l2[0] | (l2[1] << 16);
+    }
+    *reinterpret_cast<u4v *>(&Bs[buf][0][prow * C16LD + pseg]) = u4v{hw[0], hw[1], hw[2], hw[3]};
+    *reinterpret_cast<u4v *>(&Bs[buf][1][prow * C16LD + pseg]) = u4v{mw[0], mw[1], mw[2], mw[3]};
+    *reinterpret_cast<u4v *>(&Bs[buf][2][prow * C16LD + pseg]) = u4v{lw[0], lw[1], lw[2], lw[3]};
+  };
+  v16f acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  const int64_t nk = (kend - kbeg + C16K - 1) / C16K;
+  gload(kbeg);
+  sstore(0, kbeg);
+  __syncthreads();
+  for (int64_t st = 0; st < nk; ++st) {
+    const int buf = (int)(st & 1);
+    if (st + 1 < nk) gload(kbeg + (st + 1) * C16K);
+#pragma unroll
+    for (int ks = 0; ks < C16K / 16; ++ks) {
+      const int koff = 16 * ks + 8 * h;
+      bf16x8_t a[3], bb[3];
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) {
+        a[pl] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u4v *>(&As[buf][pl][(wr * 32 + r) * C16LD + koff]));
+        bb[pl] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u4v *>(&Bs[buf][pl][(wc * 32 + r) * C16LD + koff]));
+      }
+      // smallest terms first
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], bb[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[2], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], bb[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], bb[0], acc, 0, 0, 0);
+    }
+    if (st + 1 < nk) sstore(buf ^ 1, kbeg + (st + 1) * C16K);
+    __syncthreads();
+  }
+  // 32 x 32 output layout: lane (h, r), register v -> row 8 (v / 4) + 4 h + v % 4, column r
+  float *out = b.P + (int64_t)blockIdx.z * n * b.ldpm;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t row = i0 + wr * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+    const int64_t col = j0 + wc * 32 + r;
+    if (row < n && col < ma) out[row * b.ldpm + col] = acc[v];
+  }
+}
+
+// Covariance form: G = Sigma X split over the contraction (k_breduce sums
+// the splits), by k_cov16 on Sigma's bfloat16 planes when they are given,
+// else by the float32 U GEMM on L := Sigma (symmetric).
 static int launch_bcov(const BatchArgs &b, const BatchConfig &c, hipStream_t s) {
   const int64_t n = b.base.n;
   const unsigned gy = (unsigned)((b.m + c.u_bn - 1) / c.u_bn);
   const dim3 g((unsigned)((n + c.u_bm - 1) / c.u_bm), gy, (unsigned)b.splits);
+  if (b.Sp) {
+    if (c.u_bm != 64 || c.u_bn != 64 || (b.kchunk % C16K) != 0) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cov16, g, dim3(256), 0, s, b);
+    return (int)hipGetLastError();
+  }
   if (c.u_bm == 128 && c.u_bn == 128)
     hipLaunchKernelGGL((k_bgemm_u<float, 128, 128, 2, 2, true>), g, dim3(256), 0, s, b);
   else if (c.u_bm == 128 && c.u_bn == 64)

@@ -199,6 +199,12 @@ struct BatchArgs {
   // gradient is 2 Sigma X by one GEMM split over the contraction into
   // `splits` ranges of `kchunk` rows; the tails take f = x^T g / 2
   int32_t covariance;
+  // when set, Sigma as three bfloat16 planes (row i of plane p at
+  // Sp + p spplane + i ldsp, zeros past n): the GEMM runs on the bfloat16
+  // matrix cores with X split into planes as it is staged
+  const uint16_t *Sp;
+  int64_t ldsp;
+  int64_t spplane;
 };
 
 // Tile configuration of the two batched GEMMs.
@@ -263,6 +269,10 @@ int launch_syrk_split(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t
 size_t gemm_split_bytes(int64_t m, int64_t ncols, int64_t K);
 int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc, int64_t M,
                       int64_t N, int64_t K, uint16_t *planes, hipStream_t s);
+// Three bfloat16 planes of `rows` float32 rows contiguous along T (row j at
+// X + j ldx): P[p plane + j ldt + t], zeros for t in [T, ldt), ldt % 8 == 0.
+int launch_split_rows(const float *X, int64_t rows, int64_t T, int64_t ldx, uint16_t *P, int64_t ldt,
+                      int64_t plane, hipStream_t s);
 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,

@@ -420,6 +420,15 @@ size_t gemm_split_bytes(int64_t m, int64_t ncols, int64_t K) {
   return (size_t)3 * (size_t)(m + ncols) * (size_t)split_ldt(K) * 2;
 }
 
+int launch_split_rows(const float *X, int64_t rows, int64_t T, int64_t ldx, uint16_t *P, int64_t ldt,
+                      int64_t plane, hipStream_t s) {
+  if (ldt % 8 != 0 || ldt < T) return (int)hipErrorInvalidValue;
+  const int64_t groups = rows * (ldt / 8);
+  const int sgrid = (int)std::min<int64_t>((groups + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_split_rows, dim3(sgrid), dim3(256), 0, s, X, rows, T, ldx, P, ldt, plane);
+  return (int)hipGetLastError();
+}
+
 int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc, int64_t M,
                       int64_t N, int64_t K, uint16_t *planes, hipStream_t s) {
   const int64_t ldt = split_ldt(K);
