@@ -152,7 +152,12 @@ typedef struct npga_options {
                             the KKT sign rules, several indices at once (falls back to 2
                             when the face does not settle); 2 = face CG with blocking
                             steps (one index fixed per block)                        */
-  int32_t reserved_opt;
+  int32_t refine_plain_cg; /* 0 (default): the active-set refinement's face CG is
+                            preconditioned on the factor path for n >= 2048 by a
+                            rank-32 randomized Nystrom approximation of H (one
+                            multi-vector product per refinement; the path of the
+                            face solves changes, not the KKT test that ends them);
+                            1: plain face CG                                      */
 } npga_options;
 
 /* Result of a solve (host). */

@@ -47,7 +47,7 @@ class _Options(ctypes.Structure):
                 ("batch_config", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("projection", ctypes.c_int32), ("dykstra_iters", ctypes.c_int32),
                 ("backtrack_rho", ctypes.c_double), ("refine_method", ctypes.c_int32),
-                ("reserved_opt", ctypes.c_int32)]
+                ("refine_plain_cg", ctypes.c_int32)]
 
 
 class _StrOptions(ctypes.Structure):
@@ -167,6 +167,7 @@ class Options:
     dykstra_iters: int = 5000
     backtrack_rho: float = 0.0   # in (0, 1): adaptive backtracking from the trial step
     refine_method: str = "auto"   # "auto", "pdas" (primal-dual active set) or "cg" (blocking face CG)
+    refine_precond: bool = True   # Nystrom-preconditioned face CG of the active-set method (n >= 2048)
 
     def _c(self):
         o = _Options()
@@ -184,6 +185,7 @@ class Options:
         o.dykstra_iters = self.dykstra_iters
         o.backtrack_rho = self.backtrack_rho
         o.refine_method = {"auto": 0, "pdas": 1, "cg": 2}[self.refine_method]
+        o.refine_plain_cg = 0 if self.refine_precond else 1
         return o
 
 

@@ -100,7 +100,7 @@ int sweep_grid_for(int64_t cols) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
 }
 
-SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
+SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg) {
   SolveLayout l{};
   l.slots = slots_for(n);
   const int64_t npad = (int64_t)256 * std::max(l.slots, 1);
@@ -136,6 +136,18 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path) {
   l.off_xa = take(sizeof(double) * npad);
   l.off_ga = take(sizeof(double) * npad);
   l.off_ua = take(sizeof(double) * (size_t)cols);
+  l.pcg = pcg;
+  if (pcg) {
+    l.off_pre_y = take(sizeof(float) * (size_t)npad * kPreK);
+    l.off_pre_mat = take(sizeof(double) * (size_t)kPreMatDoubles);
+    l.off_pre_a1 = take(sizeof(double) * (size_t)npad);
+    l.off_pre_a2 = take(sizeof(double) * (size_t)npad);
+    l.off_pre_x = take(sizeof(float) * (size_t)npad * kPreK);
+    l.off_pre_ut = take(sizeof(float) * (size_t)kPreK * (size_t)cols);
+    l.off_pre_p = take(sizeof(float) * (size_t)kPreMaxSplits * (size_t)n * kPreK);
+    l.off_pre_usq = take(sizeof(double) * (size_t)((cols + 31) / 32) * kPreK);
+    l.off_pre_act = take(sizeof(int32_t) * (size_t)(kPreK + 1));
+  }
   l.total = off;
   return l;
 }
@@ -171,7 +183,8 @@ bool options_valid(const npga_options &o) {
          o.batch_config < npga::kBatchConfigs && (o.momentum == 0 || o.momentum == 1) &&
          (o.step_estimator == 0 || o.step_estimator == 1) && is_fin(o.alpha) && o.alpha >= 0.0 &&
          (o.projection == 0 || o.projection == 1) && o.dykstra_iters >= 1 && is_fin(o.backtrack_rho) &&
-         o.backtrack_rho >= 0.0 && o.backtrack_rho < 1.0 && o.refine_method >= 0 && o.refine_method <= 2;
+         o.backtrack_rho >= 0.0 && o.backtrack_rho < 1.0 && o.refine_method >= 0 && o.refine_method <= 2 &&
+         (o.refine_plain_cg == 0 || o.refine_plain_cg == 1);
 }
 
 bool factor_valid(const npga_factor *f) {
@@ -204,6 +217,20 @@ struct Carved {
 // vs 101, T = 5440 35 vs 133), cols < n the blocking CG (STR with ell = 512:
 // 8.8 vs 27.8; n = 1000, T = 500: 86 vs 141).
 bool pdas_suits(int64_t n, int64_t cols) { return cols >= n; }
+
+// The active-set method's face solves preconditioned by a rank-32 Nystrom
+// sketch of H (npga_pcg.h) on the factor path from n = 2048 (a round then
+// starts with one multi-vector product of 32 columns; on a 10-factor model
+// the face Hessian has 10 outliers above a bulk of condition ~5, and a CPU
+// simulation of the refinement from the C2 stopping point took 38 face
+// products instead of 84).
+bool pcg_applies(const npga_options &o, int64_t n, int64_t cols, int path) {
+  if (path != NPGA_PATH_GEMV || !o.refine || o.refine_max_iter <= 0 || o.refine_plain_cg) return false;
+  if (n < 2048 || n > NPGA_MAX_N) return false;
+  return o.refine_method == 1 || (o.refine_method == 0 && pdas_suits(n, cols));
+}
+
+int pcg_build(const npga_factor *f, const SolveLayout &l, char *base, hipStream_t s);
 
 Carved carve(const npga_factor *f, const SolveLayout &l, void *ws, int path) {
   char *base = static_cast<char *>(ws);
@@ -441,7 +468,7 @@ void npga_default_options(npga_options *o) {
   o->dykstra_iters = 5000;
   o->backtrack_rho = 0.0;
   o->refine_method = 0;
-  o->reserved_opt = 0;
+  o->refine_plain_cg = 0;
 }
 
 size_t npga_struct_size(int32_t which) {
@@ -481,7 +508,11 @@ size_t npga_solve_workspace_size(int64_t n, int64_t cols, const npga_options *op
   npga_default_options(&o);
   if (opt) o = *opt;
   const int path = resolve_path(o.path, n, cols);
-  return npga::solve_layout(n, cols, path).total;
+  size_t t = npga::solve_layout(n, cols, path, pcg_applies(o, n, cols, path)).total;
+  // AUTO: a bfloat16 factor takes the factor path
+  if (o.path == NPGA_PATH_AUTO)
+    t = std::max(t, npga::solve_layout(n, cols, NPGA_PATH_GEMV, pcg_applies(o, n, cols, NPGA_PATH_GEMV)).total);
+  return t;
 }
 
 static int solve_once(const npga_factor *f, double r, const npga_options *opt, float *x, npga_result *res,
@@ -494,7 +525,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
   if (o.momentum == 1 && !(f->gamma > 0.0)) return NPGA_ERR_INVALID;
   const int path = resolve_path(o.path, f->n, f->cols, f->dtype);
   if (path == NPGA_PATH_SYRK && f->dtype != NPGA_F32) return NPGA_ERR_UNSUPPORTED;
-  const SolveLayout lay = npga::solve_layout(f->n, f->cols, path);
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, path, pcg_applies(o, f->n, f->cols, path));
   if (!ws || !aligned(ws, 256) || ws_bytes < lay.total) return NPGA_ERR_WORKSPACE;
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
@@ -576,6 +607,15 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
     c.a.pvec = vecs;
     c.a.fvec = vecs + npad;
     c.a.gvec = vecs + 2 * npad;
+    if (lay.pcg) {
+      // Y = H Omega for the preconditioner of the face solves (one
+      // multi-vector product, then set up per face on the device)
+      LAUNCHCHK(pcg_build(f, lay, base, stream));
+      c.a.pre_y = reinterpret_cast<const float *>(base + lay.off_pre_y);
+      c.a.pre_mat = reinterpret_cast<double *>(base + lay.off_pre_mat);
+      c.a.pre_a1 = reinterpret_cast<double *>(base + lay.off_pre_a1);
+      c.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
+    }
     // rounds re-anchored in float64 at the previous round's result (removes
     // the drift of the gradient carried by linearity).  A round that ends
     // without the KKT test (stagnation of the float32 products, e.g. on a
@@ -584,6 +624,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
     // onto F) switches them to the face CG with blocking steps.
     bool precise = false;
     bool blocking = o.refine_method == 2 || (o.refine_method == 0 && !pdas_suits(f->n, f->cols));
+    bool pcg_ready = false;  // S and sigma formed (the first preconditioned round)
     for (int round = 0; round < 4; ++round) {
       if (round > 0) {
         HIPCHK(hipMemcpyAsync(xa, xk, sizeof(double) * f->n, hipMemcpyDeviceToDevice, stream));
@@ -595,6 +636,8 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
       // badly conditioned face, so those rounds wait longer
       LAUNCHCHK(npga::launch_phase_reset(c.st, o.refine_tol, o.refine_max_iter, precise ? 1000 : 60, stream));
       LAUNCHCHK(npga::launch_cg_init(c.a, slots, stream));
+      if (c.a.pre_y && !blocking) LAUNCHCHK(npga::launch_pcg_init(c.a, slots, !pcg_ready, stream));
+      pcg_ready = pcg_ready || (c.a.pre_y && !blocking);
       double rms = 0.0;
       const int64_t ref_chunks = (int64_t)o.refine_max_iter / o.check_every + 4;
       Carved cr = c;
@@ -1257,6 +1300,40 @@ const npga::BatchConfig &batch_config_of(int32_t requested, int64_t n, int64_t c
   const int id = (requested >= 0 && requested < npga::kBatchConfigs) ? requested
                                                                       : npga::batch_default_config(n, cols, m);
   return npga::kBatchConfigTable[id];
+}
+
+// Y = 2 L (L^T Omega) row-major in float32 for the refinement's
+// preconditioner: Omega's signs as the 32 columns of the batched GEMM pair
+// (the factor form, float32 matrix cores), then the split partials summed.
+int pcg_build(const npga_factor *f, const SolveLayout &l, char *base, hipStream_t s) {
+  npga::BatchArgs b{};
+  SolveArgs &a = b.base;
+  a.L = f->L;
+  a.dtype = f->dtype;
+  a.ld = f->ld;
+  a.n = f->n;
+  a.cols = f->cols;
+  a.mu = f->mu;
+  a.mode = npga::kTailGrad;
+  a.xs = reinterpret_cast<float *>(base + l.off_pre_x);
+  b.m = npga::kPreK;
+  b.ldx = l.ldp;
+  b.Ut = reinterpret_cast<float *>(base + l.off_pre_ut);
+  b.ldut = npga::kPreK;
+  b.P = reinterpret_cast<float *>(base + l.off_pre_p);
+  b.ldpm = npga::kPreK;
+  b.usq_part = reinterpret_cast<double *>(base + l.off_pre_usq);
+  b.ldq = npga::kPreK;
+  int32_t *act = reinterpret_cast<int32_t *>(base + l.off_pre_act);
+  b.act = act;
+  b.mact = act + npga::kPreK;
+  const npga::BatchConfig &cfg = batch_config_of(-1, f->n, f->cols, npga::kPreK);
+  b = with_config(b, cfg);
+  if (b.splits > npga::kPreMaxSplits || b.utiles > (f->cols + 31) / 32) return 1;
+  if (npga::launch_pre_omega(a.xs, l.ldp, f->n, s)) return 1;
+  if (npga::launch_bact_all(b, act, act + npga::kPreK, s)) return 1;
+  if (npga::launch_bgemm(b, cfg, s)) return 1;
+  return npga::launch_pre_reduce(b.P, b.ldpm, b.splits, f->n, reinterpret_cast<float *>(base + l.off_pre_y), s);
 }
 
 // Configuration for the chunk about to run: the requested one while it is

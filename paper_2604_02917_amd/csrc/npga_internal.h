@@ -106,6 +106,9 @@ struct alignas(256) DevState {
   int32_t pdas_failed;             // 1: the round hit kPdasMaxOuter (x was projected onto F)
   int32_t pdas_moved;              // indices moved by face updates in the current round
   double pdas_eta2;                // inner CG tolerance ||r||^2 <= eta2 ||r_0||^2
+  double pcg_rz;                   // preconditioned face CG: g^T z of the current direction
+  int32_t pcg_todo;                // after the tail: 0 nothing, 1 next direction, 2 new face
+  double pcg_lam0, pcg_nu0;        // the tail's least-squares multipliers of the current g
   // adjoint results
   double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
   double adj_dgamma;         // dl/dgamma
@@ -160,7 +163,21 @@ struct SolveArgs {
   // st->done here at its end: a word of pinned host memory the host reads
   // once the chunk's event has passed
   int32_t *host_done;
+  // preconditioned face solves of the active-set refinement (null: plain CG):
+  // Y = H Omega row-major (n x kPreK float32), pre_mat = S, the Cholesky
+  // factor of K and scalars, a1 / a2 = M_F^{-1} 1_F / M_F^{-1} mu_F (n)
+  const float *pre_y;
+  double *pre_mat;
+  double *pre_a1;
+  double *pre_a2;
 };
+
+// Rank of the Nystrom sketch of the refinement's preconditioner, the
+// per-thread rows of its 512-thread kernel, and the doubles of pre_mat.
+constexpr int kPreK = 32;
+constexpr int kPcgMaxE = 16;
+constexpr int kPreMatDoubles = 2 * kPreK * kPreK + 8;
+constexpr int kPreMaxSplits = 64;  // period ranges of the multi-vector product's G GEMM
 
 // m independent solves sharing L (one target return per solve).  Target j
 // uses the SolveArgs of target 0 with every per-target pointer advanced by
@@ -222,13 +239,19 @@ int batch_default_config(int64_t n, int64_t cols, int32_t m);
 struct SolveLayout {
   size_t off_state, off_status_dev, off_xs, off_x0, off_x1, off_g0, off_g1, off_part, off_usq,
       off_sigma, off_planes, off_vecs, off_bt, off_xa, off_ga, off_ua, total;
+  // the refinement's preconditioner (pcg): Y, pre_mat, a1, a2, and the
+  // multi-vector product's GEMM buffers (Omega, U^T, split partials, column
+  // sums, active list)
+  size_t off_pre_y, off_pre_mat, off_pre_a1, off_pre_a2, off_pre_x, off_pre_ut, off_pre_p, off_pre_usq,
+      off_pre_act;
+  bool pcg;
   int32_t slots;
   int32_t sweep_grid;
   int64_t ldp;
 };
 
 int slots_for(int64_t n);
-SolveLayout solve_layout(int64_t n, int64_t cols, int path);
+SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg = false);
 int sweep_grid_for(int64_t cols);
 
 // ---- launchers (defined in the .hip files; return hipError_t as int) ----
@@ -273,6 +296,15 @@ int launch_gemm_split(const float *A, int64_t lda, const float *B, int64_t ldb, 
 // X + j ldx): P[p plane + j ldt + t], zeros for t in [T, ldt), ldt % 8 == 0.
 int launch_split_rows(const float *X, int64_t rows, int64_t T, int64_t ldx, uint16_t *P, int64_t ldt,
                       int64_t plane, hipStream_t s);
+
+// Preconditioner set-up of the refinement: Omega (signs) into the batched
+// GEMM input X (column c at X + c ldx), and Y[i][c] = 2 sum_s P[s][i][c]
+// (the split partials of the GEMM pair, fixed order) row-major in float32.
+int launch_pre_omega(float *X, int64_t ldx, int64_t n, hipStream_t s);
+int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, hipStream_t s);
+// Preconditioned start of a refinement round (after launch_cg_init): the
+// first round forms S and estimates sigma, later rounds reuse them.
+int launch_pcg_init(const SolveArgs &a, int slots, bool first, hipStream_t s);
 
 // Float64 anchor gradient for the refinement phase.
 int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, double *g_out,

@@ -506,6 +506,85 @@ __global__ __launch_bounds__(64 * NW) void k_tail_pdas(SolveArgs a) {
   store_host_done(a);
 }
 
+// Preconditioned direction of the active-set refinement, launched after the
+// tail (which left p alone and said in pcg_todo what follows): 1, the next
+// CG direction p = -z + (g^T z / pcg_rz) p; 2, the first direction on the
+// face the tail has just moved to (the face's factor first).  force = 2:
+// the same at the start of a later round (after k_cg_init).  INIT (the
+// start of the first round): S = Omega^T Y and sigma on the round's first
+// face, its factor, p = -z.  Eight wavefronts.
+template <int E, bool INIT>
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force) {
+  __shared__ double redbuf[red_buf_doubles<kPcgWaves>()];
+  __shared__ PcgShared sh;
+  DevState *st = a.st;
+  if (st->done != kRunning) return;
+  const int todo = INIT ? 3 : (force ? force : st->pcg_todo);
+  if (todo == 0) return;
+  const int tid = threadIdx.x;
+  const int64_t n = a.n;
+  BlockReducer<5, kPcgWaves> red{redbuf, 0};
+  double g[E], mu[E], fr[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + kPcgThreads * j;
+    const bool ok = i < n;
+    mu[j] = ok ? a.mu[i] : 0.0;
+    fr[j] = ok ? a.fvec[i] : 0.0;
+  }
+  const bool active = st->cg_active != 0;
+  if (INIT) pcg_face<E, true>(a, fr, mu, sh, red);
+  else if (todo == 2) pcg_face<E, false>(a, fr, mu, sh, red);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + kPcgThreads * j;
+    g[j] = (i < n) ? a.gvec[i] : 0.0;
+  }
+  double z[E], rz;
+  // the tail's least-squares multipliers (none at a round's start)
+  const bool lsq = force == 0 && !INIT;
+  pcg_direction<E>(a, g, fr, mu, active, todo != 1, lsq, lsq ? st->pcg_lam0 : 0.0, lsq ? st->pcg_nu0 : 0.0, sh,
+                   red, z, rz);
+  const double beta = (todo == 1 && st->pcg_rz > 0.0) ? rz / st->pcg_rz : 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int64_t i = tid + kPcgThreads * j;
+    if (i < n) {
+      const double p = (todo == 1) ? fma(beta, a.pvec[i], -z[j]) : -z[j];
+      a.pvec[i] = p;
+      a.xs[i] = (float)p;
+    }
+  }
+  __syncthreads();  // every thread has read pcg_rz
+  if (tid == 0) {
+    st->pcg_rz = rz;
+    st->pcg_todo = 0;
+    if (!isfinite(rz)) st->done = kNumeric;
+  }
+}
+
+// Omega's signs into the batched GEMM input (column c at X + c ldx, zeros
+// past n up to ldx).
+__global__ __launch_bounds__(256) void k_pre_omega(float *X, int64_t ldx, int64_t n) {
+  const int64_t total = ldx * kPreK;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t c = e / ldx, i = e % ldx;
+    X[e] = (i < n) ? pre_omega(i, (int)c) : 0.f;
+  }
+}
+
+// Y[i][c] = 2 sum_s P[(s n + i) ldpm + c], the splits in order.
+__global__ __launch_bounds__(256) void k_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n,
+                                                    float *Y) {
+  const int64_t total = n * kPreK;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / kPreK, c = e % kPreK;
+    double acc = 0.0;
+    for (int32_t sp = 0; sp < splits; ++sp) acc += (double)P[((int64_t)sp * n + i) * ldpm + c];
+    Y[e] = (float)(2.0 * acc);
+  }
+}
+
 template <int E>
 __global__ __launch_bounds__(256) void k_tail_adj(SolveArgs a) {
   __shared__ double redbuf[64];
@@ -745,6 +824,46 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
     default: return (int)hipErrorInvalidValue;                                                 \
   }
 
+// Per-thread rows of the 512-thread preconditioner kernel (n >= 2048).
+#define NPGA_PCG_SLOT_SWITCH(slots, CALL)                     \
+  switch (slots) {                                            \
+    case 8: CALL(4); break;                                   \
+    case 12: CALL(6); break;                                  \
+    case 16: CALL(8); break;                                  \
+    case 22: CALL(11); break;                                 \
+    case 28: CALL(14); break;                                 \
+    case 32: CALL(16); break;                                 \
+    default: return (int)hipErrorInvalidValue;                \
+  }
+
+int launch_pcg_init(const SolveArgs &a, int slots, bool first, hipStream_t s) {
+  if (!a.pre_y || !a.pre_mat || !a.pre_a1 || !a.pre_a2) return (int)hipErrorInvalidValue;
+  if (first) {
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, true>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
+    NPGA_PCG_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  } else {
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 2)
+    NPGA_PCG_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_pre_omega(float *X, int64_t ldx, int64_t n, hipStream_t s) {
+  const int64_t total = ldx * kPreK;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pre_omega, dim3(grid), dim3(256), 0, s, X, ldx, n);
+  return (int)hipGetLastError();
+}
+
+int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, hipStream_t s) {
+  const int64_t total = n * kPreK;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pre_reduce, dim3(grid), dim3(256), 0, s, P, ldpm, splits, n, Y);
+  return (int)hipGetLastError();
+}
+
 int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
   if ((a.dykstra || a.backtrack) && a.mode == kTailNpga) {
     // the NPGA tail with Dykstra's projections and/or backtracking: own
@@ -796,6 +915,12 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
       } else {
 #define CALL(E) hipLaunchKernelGGL((k_tail_pdas<E, 4>), dim3(1), dim3(256), 0, s, a)
         NPGA_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      }
+      if (a.pre_y) {
+        if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
+        NPGA_PCG_SLOT_SWITCH(slots, CALL)
 #undef CALL
       }
       break;

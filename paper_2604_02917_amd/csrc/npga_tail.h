@@ -10,6 +10,7 @@
 
 #include "npga_device.h"
 #include "npga_internal.h"
+#include "npga_pcg.h"
 
 namespace npga {
 
@@ -802,6 +803,11 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 // gradient is below 1e-10 of the gradient on S (KKT to rounding), or on
 // stagnation of the float32 products; after kPdasMaxOuter updates it
 // projects x onto F and reports the fallback (pdas_failed).
+// With the preconditioner set (a.pre_y), the search directions come from
+// k_pcg_step, launched after this tail (npga_pcg.h): the tail then leaves
+// p alone, takes its step length from pcg_rz = g^T z and tells k_pcg_step
+// in pcg_todo what follows (1: next direction, 2: the first direction on a
+// new face); the tests keep using the plain projected gradient.
 // ---------------------------------------------------------------------------
 template <int E, int NW = 4>
 __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
@@ -844,17 +850,23 @@ __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
       acc[0] = fma(p[j], p[j], acc[0]);
     }
     red.sum(acc);
+    const bool pre = a.pre_y != nullptr;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int64_t i = tid + NT * j;
       if (i < n) {
         x_p[i] = x[j];
         a.gvec[i] = g[j];
-        a.pvec[i] = p[j];
-        a.xs[i] = (float)p[j];
+        if (!pre) {
+          a.pvec[i] = p[j];
+          a.xs[i] = (float)p[j];
+        }
       }
     }
     if (tid == 0) {
+      st->pcg_todo = 2;
+      st->pcg_lam0 = lam;
+      st->pcg_nu0 = nu;
       st->cg_pg = 0;
       st->cg_rr = acc[0];
       st->cg_rr0 = acc[0];
@@ -867,7 +879,7 @@ __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
   }
 
   // (1) CG step on the face, not limited by x >= 0
-  const double rr = st->cg_rr;
+  const double rr = a.pre_y ? st->pcg_rz : st->cg_rr;
   double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < E; ++j) acc[0] = fma(fr[j] * p[j], hp[j], acc[0]);
@@ -965,6 +977,7 @@ __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
         }
       }
       if (tid == 0) {
+        st->pcg_todo = 0;
         st->cg_pg = 1;
         st->cg_active = act_new ? 1 : 0;
         st->pdas_outer += 1;
@@ -1065,7 +1078,8 @@ __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
   }
   if (inner_done && tid == 0) st->pdas_final = 1;  // settled face: solve it to the KKT tolerance
 
-  // (6) next direction
+  // (6) next direction (by k_pcg_step when preconditioned)
+  const bool pre = a.pre_y != nullptr;
   const double beta = (rr > 0.0) ? rr_new / rr : 0.0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -1074,11 +1088,16 @@ __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
     if (i < n) {
       x_p[i] = x[j];
       a.gvec[i] = g[j];
-      a.pvec[i] = p[j];
-      a.xs[i] = (float)p[j];
+      if (!pre) {
+        a.pvec[i] = p[j];
+        a.xs[i] = (float)p[j];
+      }
     }
   }
   if (tid == 0) {
+    st->pcg_todo = 1;
+    st->pcg_lam0 = lam;
+    st->pcg_nu0 = nu;
     st->cg_iter = it;
     st->cg_rr = rr_new;
     st->cg_best_rr = best;

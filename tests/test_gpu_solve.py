@@ -204,3 +204,26 @@ def test_batched_deterministic(npga):
         Xb, ib = npga.solve_batched(L, mu, rs, path=path)
         assert torch.equal(Xa, Xb), path
         assert [i["objective"] for i in ia] == [i["objective"] for i in ib], path
+
+
+@pytest.mark.parametrize("n,T,q,precond", [
+    (2048, 6000, 0.6, True),
+    (2048, 6000, 0.6, False),
+    (2600, 7800, 0.3, True),
+    (2600, 7800, 0.0, True),   # return constraint slack
+    (2100, 4200, 1.0, True),   # r = max mu: a single feasible vertex
+])
+def test_refine_preconditioned(npga, n, T, q, precond):
+    """Face solves of the active-set refinement with the Nystrom
+    preconditioner (n >= 2048 on the factor path) and without it: the same
+    parity bar against the oracle's minimiser, and bitwise-repeatable."""
+    banner(f"preconditioned refinement n={n} T={T} q={q} precond={precond}")
+    spec = spec_with("c2", n, T, seed=71 + n)
+    Rt, r, mu_ref, L_ref, ref = _case(spec, q=q)
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, path="gemv", refine_precond=precond)
+    assert info["status"] == 0 and info["refined"] == 1, info
+    _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, 0.0, ref, f"pcg {n}x{T} q={q}")
+    x2, info2 = npga.solve(L, mu, r, path="gemv", refine_precond=precond)
+    assert torch.equal(x, x2) and info2["refine_iters"] == info["refine_iters"]
+    banner(f"refine_iters {info['refine_iters']}")
