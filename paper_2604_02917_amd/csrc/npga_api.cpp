@@ -139,6 +139,7 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg) {
   l.pcg = pcg;
   if (pcg) {
     l.off_pre_y = take(sizeof(float) * (size_t)npad * kPreK);
+    l.off_pre_yt = take(sizeof(float) * (size_t)npad * kPreK);
     l.off_pre_mat = take(sizeof(double) * (size_t)kPreMatDoubles);
     l.off_pre_a1 = take(sizeof(double) * (size_t)npad);
     l.off_pre_a2 = take(sizeof(double) * (size_t)npad);
@@ -612,6 +613,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
       // multi-vector product, then set up per face on the device)
       LAUNCHCHK(pcg_build(f, lay, base, stream));
       c.a.pre_y = reinterpret_cast<const float *>(base + lay.off_pre_y);
+      c.a.pre_yt = reinterpret_cast<const float *>(base + lay.off_pre_yt);
       c.a.pre_mat = reinterpret_cast<double *>(base + lay.off_pre_mat);
       c.a.pre_a1 = reinterpret_cast<double *>(base + lay.off_pre_a1);
       c.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
@@ -1333,7 +1335,8 @@ int pcg_build(const npga_factor *f, const SolveLayout &l, char *base, hipStream_
   if (npga::launch_pre_omega(a.xs, l.ldp, f->n, s)) return 1;
   if (npga::launch_bact_all(b, act, act + npga::kPreK, s)) return 1;
   if (npga::launch_bgemm(b, cfg, s)) return 1;
-  return npga::launch_pre_reduce(b.P, b.ldpm, b.splits, f->n, reinterpret_cast<float *>(base + l.off_pre_y), s);
+  return npga::launch_pre_reduce(b.P, b.ldpm, b.splits, f->n, reinterpret_cast<float *>(base + l.off_pre_y),
+                                 reinterpret_cast<float *>(base + l.off_pre_yt), l.ldp, s);
 }
 
 // Configuration for the chunk about to run: the requested one while it is

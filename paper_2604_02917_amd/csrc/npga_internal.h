@@ -164,9 +164,11 @@ struct SolveArgs {
   // once the chunk's event has passed
   int32_t *host_done;
   // preconditioned face solves of the active-set refinement (null: plain CG):
-  // Y = H Omega row-major (n x kPreK float32), pre_mat = S, the Cholesky
-  // factor of K and scalars, a1 / a2 = M_F^{-1} 1_F / M_F^{-1} mu_F (n)
+  // Y = H Omega row-major (n x kPreK float32) and column-major (column c at
+  // pre_yt + c ldp), pre_mat = S, the Cholesky factor of K and scalars,
+  // a1 / a2 = M_F^{-1} 1_F / M_F^{-1} mu_F (n)
   const float *pre_y;
+  const float *pre_yt;
   double *pre_mat;
   double *pre_a1;
   double *pre_a2;
@@ -242,7 +244,7 @@ struct SolveLayout {
   // the refinement's preconditioner (pcg): Y, pre_mat, a1, a2, and the
   // multi-vector product's GEMM buffers (Omega, U^T, split partials, column
   // sums, active list)
-  size_t off_pre_y, off_pre_mat, off_pre_a1, off_pre_a2, off_pre_x, off_pre_ut, off_pre_p, off_pre_usq,
+  size_t off_pre_y, off_pre_yt, off_pre_mat, off_pre_a1, off_pre_a2, off_pre_x, off_pre_ut, off_pre_p, off_pre_usq,
       off_pre_act;
   bool pcg;
   int32_t slots;
@@ -299,9 +301,11 @@ int launch_split_rows(const float *X, int64_t rows, int64_t T, int64_t ldx, uint
 
 // Preconditioner set-up of the refinement: Omega (signs) into the batched
 // GEMM input X (column c at X + c ldx), and Y[i][c] = 2 sum_s P[s][i][c]
-// (the split partials of the GEMM pair, fixed order) row-major in float32.
+// (the split partials of the GEMM pair, fixed order) in float32, row-major
+// into Y and column-major (column c at Yt + c ldyt) into Yt.
 int launch_pre_omega(float *X, int64_t ldx, int64_t n, hipStream_t s);
-int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, hipStream_t s);
+int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, float *Yt, int64_t ldyt,
+                      hipStream_t s);
 // Preconditioned start of a refinement round (after launch_cg_init): the
 // first round forms S and estimates sigma, later rounds reuse them.
 int launch_pcg_init(const SolveArgs &a, int slots, bool first, hipStream_t s);

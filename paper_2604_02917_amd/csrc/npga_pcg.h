@@ -19,9 +19,13 @@
 //
 // All routines run in one workgroup of 8 wavefronts (thread t owns rows
 // t + 512 j, j < E; with 256 registers per lane the per-row vectors stay in
-// registers).  Y is stored row-major in float32 (row i at
-// pre_y + 32 i); S, the Cholesky factor of K and the scalars live in
-// pre_mat (float64).
+// registers).  Y is stored in float32 twice: row-major (row i at pre_y +
+// 32 i) for the Gram products on the matrix cores, and column-major
+// (column c at pre_yt + c ldp) for the two passes of every application of
+// M_F^{-1}, in which a load instruction then reads 64 consecutive rows of
+// one column (with a row per thread and float4 loads, each instruction
+// touched 64 cache lines and the passes took 18 us each at n = 5440).
+// S, the Cholesky factor of K and the scalars live in pre_mat (float64).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -146,21 +150,33 @@ __device__ __forceinline__ void pcg_gram(const SolveArgs &a, PcgShared &sh, doub
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = pcg_d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t i0 = r0; i0 < r1; i0 += 4) {
-    const int64_t i = i0 + kq;
-    double yv[2] = {0.0, 0.0}, wv[2] = {0.0, 0.0};
-    if (i < r1) {
-      const bool keep = OMEGA || sh.mask[i] != 0;
+  // eight 4-row steps per batch, all loads issued before the products (a
+  // load-then-multiply step per iteration waits on memory every time)
+  constexpr int kB = 8;
+  for (int64_t b0 = r0; b0 < r1; b0 += 4 * kB) {
+    float yb[kB][2];
+    bool kb[kB];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        yv[p] = (double)a.pre_y[i * kPreK + 16 * p + c];
-        wv[p] = OMEGA ? (double)pre_omega(i, 16 * p + c) : (keep ? yv[p] : 0.0);
-      }
+    for (int u = 0; u < kB; ++u) {
+      const int64_t i = b0 + 4 * u + kq;
+      kb[u] = i < r1 && (OMEGA || sh.mask[i] != 0);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) yb[u][p] = (i < r1) ? a.pre_y[i * kPreK + 16 * p + c] : 0.f;
     }
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int u = 0; u < kB; ++u) {
+      const int64_t i = b0 + 4 * u + kq;
+      double yv[2], wv[2];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[p], yv[q], acc[p][q], 0, 0, 0);
+      for (int p = 0; p < 2; ++p) {
+        yv[p] = (double)yb[u][p];
+        wv[p] = OMEGA ? ((i < r1) ? (double)pre_omega(i, 16 * p + c) : 0.0) : (kb[u] ? yv[p] : 0.0);
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[p], yv[q], acc[p][q], 0, 0, 0);
+    }
   }
   // 16 x 16 output layout: lane (kq, c), register v -> row kq + 4 v, column c
 #pragma unroll
@@ -220,16 +236,10 @@ __device__ __forceinline__ void pcg_apply(const SolveArgs &a, const double (&v)[
       for (int j = 0; j < E; ++j) {
         const int64_t i = tid + kPcgThreads * j;
         if (i < n && fr[j] > 0.0) {
-          const f4 y0 = *reinterpret_cast<const f4 *>(a.pre_y + i * kPreK + 8 * q);
-          const f4 y1 = *reinterpret_cast<const f4 *>(a.pre_y + i * kPreK + 8 * q + 4);
-          t8[0] = fma((double)y0.x, v[j], t8[0]);
-          t8[1] = fma((double)y0.y, v[j], t8[1]);
-          t8[2] = fma((double)y0.z, v[j], t8[2]);
-          t8[3] = fma((double)y0.w, v[j], t8[3]);
-          t8[4] = fma((double)y1.x, v[j], t8[4]);
-          t8[5] = fma((double)y1.y, v[j], t8[5]);
-          t8[6] = fma((double)y1.z, v[j], t8[6]);
-          t8[7] = fma((double)y1.w, v[j], t8[7]);
+          // column-major Y: lanes read consecutive rows of one column
+          const float *yc = a.pre_yt + (int64_t)(8 * q) * a.ldp + i;
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) t8[cc] = fma((double)yc[cc * a.ldp], v[j], t8[cc]);
         }
       }
       const double r = wave_reduce8(t8, lane);
@@ -253,21 +263,22 @@ __device__ __forceinline__ void pcg_apply(const SolveArgs &a, const double (&v)[
     __syncthreads();
   }
   const double inv = 1.0 / sigma;
+  // K^{-1} Y^T v in registers while the rows' vectors leave room (n <= 6144)
+  constexpr bool kHoist = E <= 12;
+  double sv[kHoist ? kPreK : 1];
+  if constexpr (kHoist) {
+#pragma unroll
+    for (int c = 0; c < kPreK; ++c) sv[c] = lowrank ? sh.s[c] : 0.0;
+  }
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + kPcgThreads * j;
     double w = v[j];
     if (lowrank && i < n && fr[j] > 0.0) {
-      const f4 *yr = reinterpret_cast<const f4 *>(a.pre_y + i * kPreK);
+      const float *yc = a.pre_yt + i;
       double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < kPreK / 4; ++q) {
-        const f4 y = yr[q];
-        acc = fma((double)y.x, sh.s[4 * q], acc);
-        acc = fma((double)y.y, sh.s[4 * q + 1], acc);
-        acc = fma((double)y.z, sh.s[4 * q + 2], acc);
-        acc = fma((double)y.w, sh.s[4 * q + 3], acc);
-      }
+      for (int c = 0; c < kPreK; ++c) acc = fma((double)yc[c * a.ldp], kHoist ? sv[kHoist ? c : 0] : sh.s[c], acc);
       w -= acc;
     }
     z[j] = (i < n && fr[j] > 0.0) ? w * inv : 0.0;

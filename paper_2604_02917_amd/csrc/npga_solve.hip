@@ -573,15 +573,18 @@ __global__ __launch_bounds__(256) void k_pre_omega(float *X, int64_t ldx, int64_
   }
 }
 
-// Y[i][c] = 2 sum_s P[(s n + i) ldpm + c], the splits in order.
+// Y[i][c] = 2 sum_s P[(s n + i) ldpm + c], the splits in order, stored
+// row-major (Y) and column-major (Yt).
 __global__ __launch_bounds__(256) void k_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n,
-                                                    float *Y) {
+                                                    float *Y, float *Yt, int64_t ldyt) {
   const int64_t total = n * kPreK;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / kPreK, c = e % kPreK;
     double acc = 0.0;
     for (int32_t sp = 0; sp < splits; ++sp) acc += (double)P[((int64_t)sp * n + i) * ldpm + c];
-    Y[e] = (float)(2.0 * acc);
+    const float y = (float)(2.0 * acc);
+    Y[e] = y;
+    Yt[c * ldyt + i] = y;
   }
 }
 
@@ -837,7 +840,7 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
   }
 
 int launch_pcg_init(const SolveArgs &a, int slots, bool first, hipStream_t s) {
-  if (!a.pre_y || !a.pre_mat || !a.pre_a1 || !a.pre_a2) return (int)hipErrorInvalidValue;
+  if (!a.pre_y || !a.pre_yt || !a.pre_mat || !a.pre_a1 || !a.pre_a2) return (int)hipErrorInvalidValue;
   if (first) {
 #define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, true>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
     NPGA_PCG_SLOT_SWITCH(slots, CALL)
@@ -857,10 +860,12 @@ int launch_pre_omega(float *X, int64_t ldx, int64_t n, hipStream_t s) {
   return (int)hipGetLastError();
 }
 
-int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, hipStream_t s) {
+int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, float *Y, float *Yt, int64_t ldyt,
+                      hipStream_t s) {
+  if (ldyt < n) return (int)hipErrorInvalidValue;
   const int64_t total = n * kPreK;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_pre_reduce, dim3(grid), dim3(256), 0, s, P, ldpm, splits, n, Y);
+  hipLaunchKernelGGL(k_pre_reduce, dim3(grid), dim3(256), 0, s, P, ldpm, splits, n, Y, Yt, ldyt);
   return (int)hipGetLastError();
 }
 
