@@ -123,6 +123,10 @@ __global__ __launch_bounds__(256) void k_random_unit(double *u, float *xs, int64
     if (i < n) {
       u[i] = val[j] * inv;
       xs[i] = (float)(val[j] * inv);
+    } else {
+      // the padding up to 256 E entries is read by the sweeps; later
+      // writers of xs store only the first n entries
+      xs[i] = 0.0f;
     }
   }
 }

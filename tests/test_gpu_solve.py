@@ -225,5 +225,40 @@ def test_refine_preconditioned(npga, n, T, q, precond):
     assert info["status"] == 0 and info["refined"] == 1, info
     _check_parity(x.cpu().numpy(), info, L_ref, mu_ref, r, 0.0, ref, f"pcg {n}x{T} q={q}")
     x2, info2 = npga.solve(L, mu, r, path="gemv", refine_precond=precond)
-    assert torch.equal(x, x2) and info2["refine_iters"] == info["refine_iters"]
+    assert torch.equal(x, x2) and info2["refine_iters"] == info["refine_iters"], (
+        float((x - x2).abs().max()), info["refine_iters"], info2["refine_iters"], info["iters"], info2["iters"],
+        info["objective"], info2["objective"])
     banner(f"refine_iters {info['refine_iters']}")
+
+
+def test_solve_ignores_stale_workspace(npga):
+    """A solve reads nothing of its workspace before writing it: the same
+    solve on a zeroed workspace and on one holding finite junk (what earlier
+    calls leave behind) is bitwise identical.  Regression: the padding of
+    the float32 sweep input past n was left as found by the random start
+    vector of the step estimate, and shifted the step size."""
+    import ctypes
+    from paper_2604_02917_amd import api
+    spec = spec_with("c2", 2600, 7800, seed=71 + 2600)
+    Rt, r, mu_ref, L_ref, ref = _case(spec, q=0.3)
+    L, mu = npga.build_factor(to_dev(Rt))
+    co = api.Options(path="gemv")._c()
+    Lb, n, cols, ld = api._as_colmajor(L)
+    need = api._lib.npga_solve_workspace_size(n, cols, ctypes.byref(co))
+    mud = mu.to(torch.float64).contiguous()
+    outs = []
+    for fill in ("zero", "junk"):
+        ws = torch.zeros(need // 8 + 1, dtype=torch.float64, device="cuda:0")
+        if fill == "junk":
+            ws.uniform_(-1e-3, 1e-3)
+        x = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        res = api._Result()
+        f = api._factor(Lb, n, cols, ld, mud, 0.0)
+        code = api._lib.npga_solve(ctypes.byref(f), r, ctypes.byref(co), ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.byref(res), ctypes.c_void_p(ws.data_ptr()), need, api._stream())
+        torch.cuda.synchronize()
+        assert code == 0
+        outs.append((x, res.iters, res.refine_iters))
+    assert torch.equal(outs[0][0], outs[1][0]), float((outs[0][0] - outs[1][0]).abs().max())
+    assert outs[0][1:] == outs[1][1:], (outs[0][1:], outs[1][1:])
+    _check_parity(outs[1][0].cpu().numpy(), {"objective": ref["f"]}, L_ref, mu_ref, r, 0.0, ref, "stale workspace")
