@@ -244,9 +244,11 @@ int npga_to_bf16(const float *L, int64_t n, int64_t T, int64_t ld, uint16_t *Lb,
  * g_a + 2 L L^T (x - x_a) + 2 gamma x with the float32 sweep applied to the
  * small correction x - x_a, and the face of the active set is solved by an
  * inexact primal-dual active-set method (CG on the face, the KKT sign rules
- * move the face) or, per refine_method, by face CG with blocking steps; the
- * result is re-anchored in float64 once and the refinement ends on the KKT
- * test (res->refined = 1).
+ * move the face; on the factor path from n = 2048 the face CG is
+ * preconditioned by a rank-32 Nystrom approximation of H built from one
+ * multi-vector product, unless opt->refine_plain_cg) or, per refine_method,
+ * by face CG with blocking steps; the result is re-anchored in float64 once
+ * and the refinement ends on the KKT test (res->refined = 1).
  *   f      (host) effective factor and ridge; n <= NPGA_MAX_N
  *   r      target return R_target; r > max mu gives NPGA_ERR_INFEASIBLE
  *   opt    (host) options, or NULL for the defaults
