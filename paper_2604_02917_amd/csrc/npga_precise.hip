@@ -183,6 +183,112 @@ __global__ __launch_bounds__(256) void k_precise_sweep(const TL *L, int64_t ld, 
   for (int idx = threadIdx.x; idx < 256 * E; idx += 256) out[idx] = xsh[idx];
 }
 
+// The same pass with the rows of a column split over a pair of wavefronts
+// (eight per workgroup, four column streams): each lane then keeps 2 E
+// float64 accumulators instead of 4 E, which fit the vector registers (with
+// 4 E = 88 at n = 5440 they sat in accumulation registers, moved in and out
+// on every update, and the kernel was bound by its vector instructions).
+// The pair's two partial dot products meet in LDS, one barrier per column
+// step (slots alternate with the step's parity); every pair runs the step
+// count of the workgroup's first pair so that the barriers match.
+template <int E, typename TL>
+__global__ __launch_bounds__(512) void k_precise_pair(const TL *L, int64_t ld, int64_t n, int64_t cols,
+                                                      const double *x, double *u, double *part, int64_t ldp) {
+  constexpr int E2 = (E + 1) / 2;
+  __shared__ double xsh[256 * E];     // x; after the sweep, the combine buffer
+  __shared__ double dsh[2][4][2];     // [step parity][pair][half]
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int pr = wave >> 1, hf = wave & 1;
+  const int j0 = hf * E2;  // the half's first group of four rows
+  const int64_t W = (int64_t)gridDim.x * 4;
+  for (int q = threadIdx.x; q < 256 * E; q += 512) {
+    const int l = q & 63, je = q >> 6, j = je >> 2, e = je & 3;
+    const int64_t i = 4 * l + 256 * j + e;
+    xsh[q] = (i < n) ? x[i] : 0.0;
+  }
+  double g[4 * E2];
+#pragma unroll
+  for (int q = 0; q < 4 * E2; ++q) g[q] = 0.0;
+  __syncthreads();
+  const unsigned int z = (unsigned int)((uint64_t)n >> 62);
+  auto wide = [&](float v) { return (double)__uint_as_float(__float_as_uint(v) ^ z); };
+  auto load = [&](f4(&c)[E2], int64_t col) {
+    const TL *p = L + col * ld + 4 * lane;
+#pragma unroll
+    for (int jj = 0; jj < E2; ++jj) {
+      const int j = j0 + jj;
+      const int64_t row0 = 4 * lane + 256 * j;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (col < cols && j < E && row0 < n) {
+        v = load4_nt<TL>(p + 256 * j);
+        if (row0 + 1 >= n) v.y = 0.f;
+        if (row0 + 2 >= n) v.z = 0.f;
+        if (row0 + 3 >= n) v.w = 0.f;
+      }
+      c[jj] = v;
+    }
+  };
+  auto step = [&](const f4(&c)[E2], int64_t col, int64_t k) {
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < E2; ++jj) {
+      const int j = j0 + jj;
+      if (j < E) {
+        d0 = fma((double)c[jj].x, xsh[(4 * j + 0) * 64 + lane], d0);
+        d1 = fma((double)c[jj].y, xsh[(4 * j + 1) * 64 + lane], d1);
+        d2 = fma((double)c[jj].z, xsh[(4 * j + 2) * 64 + lane], d2);
+        d3 = fma((double)c[jj].w, xsh[(4 * j + 3) * 64 + lane], d3);
+      }
+    }
+    const double dp = wave_sum_f64((d0 + d1) + (d2 + d3));
+    const int par = (int)(k & 1);
+    if (lane == 0) dsh[par][pr][hf] = dp;
+    __syncthreads();
+    const double d = dsh[par][pr][0] + dsh[par][pr][1];
+    if (hf == 0 && lane == 0 && u && col < cols) u[col] = d;
+#pragma unroll
+    for (int jj = 0; jj < E2; ++jj) {
+      g[4 * jj + 0] = fma(wide(c[jj].x), d, g[4 * jj + 0]);
+      g[4 * jj + 1] = fma(wide(c[jj].y), d, g[4 * jj + 1]);
+      g[4 * jj + 2] = fma(wide(c[jj].z), d, g[4 * jj + 2]);
+      g[4 * jj + 3] = fma(wide(c[jj].w), d, g[4 * jj + 3]);
+    }
+  };
+  const int64_t c00 = (int64_t)blockIdx.x * 4;
+  const int64_t K = (c00 < cols) ? (cols - c00 + W - 1) / W : 0;  // steps of the first pair (the most)
+  f4 c0[E2], c1[E2];
+  if (K > 0) load(c0, c00 + pr);
+  for (int64_t k = 0; k < K; k += 2) {
+    const int64_t ca = c00 + pr + k * W;
+    if (k + 1 < K) load(c1, ca + W);
+    step(c0, ca, k);
+    if (k + 1 >= K) break;
+    if (k + 2 < K) load(c0, ca + 2 * W);
+    step(c1, ca + W, k + 1);
+  }
+  // combine the four pairs in a fixed order (x is no longer needed)
+  __syncthreads();
+  for (int p = 0; p < 4; ++p) {
+    if (pr == p) {
+#pragma unroll
+      for (int jj = 0; jj < E2; ++jj) {
+        const int j = j0 + jj;
+        if (j < E) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int idx = 4 * lane + 256 * j + e;
+            xsh[idx] = (p == 0) ? g[4 * jj + e] : xsh[idx] + g[4 * jj + e];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double *out = part + (int64_t)blockIdx.x * ldp;
+  for (int idx = threadIdx.x; idx < 256 * E; idx += 512) out[idx] = xsh[idx];
+}
+
 __global__ __launch_bounds__(256) void k_precise_reduce(const double *part, int G, int64_t ldp, int64_t n,
                                                         double *g) {
   __shared__ double red[4][64];
@@ -232,6 +338,9 @@ int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, 
 #define ONEPASS(E, TL)                                                                                       \
   hipLaunchKernelGGL((k_precise_sweep<E, TL>), dim3(G), dim3(256), 0, s, static_cast<const TL *>(a.L), a.ld, \
                      a.n, a.cols, x, u_out, part, a.ldp)
+#define PAIRPASS(E, TL)                                                                                     \
+  hipLaunchKernelGGL((k_precise_pair<E, TL>), dim3(G), dim3(512), 0, s, static_cast<const TL *>(a.L), a.ld, \
+                     a.n, a.cols, x, u_out, part, a.ldp)
 #define ONEPASS_SWITCH(TL)                     \
   switch (slots) {                             \
     case 1: ONEPASS(1, TL); break;             \
@@ -239,8 +348,8 @@ int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, 
     case 4: ONEPASS(4, TL); break;             \
     case 8: ONEPASS(8, TL); break;             \
     case 12: ONEPASS(12, TL); break;           \
-    case 16: ONEPASS(16, TL); break;           \
-    case 22: ONEPASS(22, TL); break;           \
+    case 16: PAIRPASS(16, TL); break;          \
+    case 22: PAIRPASS(22, TL); break;          \
     default: return (int)hipErrorInvalidValue; \
   }
     if (a.dtype == NPGA_BF16) {
@@ -250,6 +359,7 @@ int launch_precise_gradient(const SolveArgs &a, const double *x, double *u_out, 
     }
 #undef ONEPASS_SWITCH
 #undef ONEPASS
+#undef PAIRPASS
   } else if (a.dtype == NPGA_BF16) {
     const bf16_t *L = static_cast<const bf16_t *>(a.L);
 #define CALL(E) hipLaunchKernelGGL((k_precise_u<E, bf16_t>), dim3(G), dim3(256), 0, s, L, a.ld, a.n, a.cols, x, u_out)
