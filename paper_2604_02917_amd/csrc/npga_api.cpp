@@ -220,11 +220,11 @@ struct Carved {
 bool pdas_suits(int64_t n, int64_t cols) { return cols >= n; }
 
 // The active-set method's face solves preconditioned by a rank-32 Nystrom
-// sketch of H (npga_pcg.h) on the factor path from n = 2048 (a round then
-// starts with one multi-vector product of 32 columns; on a 10-factor model
-// the face Hessian has 10 outliers above a bulk of condition ~5, and a CPU
-// simulation of the refinement from the C2 stopping point took 38 face
-// products instead of 84).
+// sketch of H (npga_pcg.h) on the factor path from n = 2048 (the refinement
+// then starts with one multi-vector product of 32 columns; on a 10-factor
+// model the face Hessian has 10 outliers above a bulk of condition ~5, and
+// a CPU simulation of the refinement from the C2 stopping point took 38
+// face products instead of 84).
 bool pcg_applies(const npga_options &o, int64_t n, int64_t cols, int path) {
   if (path != NPGA_PATH_GEMV || !o.refine || o.refine_max_iter <= 0 || o.refine_plain_cg) return false;
   if (n < 2048 || n > NPGA_MAX_N) return false;

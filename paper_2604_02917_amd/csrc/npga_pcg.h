@@ -288,7 +288,8 @@ __device__ __forceinline__ void pcg_apply(const SolveArgs &a, const double (&v)[
 // Preconditioner for the face fr (LDS mask written here): K = sigma S +
 // Y_F^T Y_F and its Cholesky factor (into sh.kc and pre_mat), then a1, a2
 // and the 2 x 2 metric of the equality rows.  INIT: S = Omega^T Y is formed
-// and sigma estimated on this face (kept for the later faces of the round).
+// and sigma estimated on this face (kept for the later faces and rounds of
+// the solve).
 template <int E, bool INIT>
 __device__ __forceinline__ void pcg_face(const SolveArgs &a, const double (&fr)[E], const double (&mu)[E], PcgShared &sh,
                          BlockReducer<5, kPcgWaves> &red) {

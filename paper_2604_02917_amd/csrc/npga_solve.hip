@@ -12,6 +12,8 @@
 //               NPGA: stopping test, momentum extrapolation, gradient step
 //               and the exact projection).  The kernel boundaries order the
 //               writes; no workgroup waits on another.
+// In the refinement's active-set mode with the preconditioner set, a fourth
+// launch (k_pcg_step) forms the next search direction after the tail.
 //
 // The sweep evaluates the gradient at the iterate x_k rather than at the
 // extrapolated point y_k: the gradient is affine in x, so
