@@ -12,6 +12,7 @@ torch = pytest.importorskip("torch")
 
 import gen
 from oracle import factor as ofactor
+from oracle import qp
 from oracle.reference import exact_mv_factor
 from tests.golden.make_golden import panel_digest
 from tests.gpu_util import banner, spec_with, to_dev
@@ -141,3 +142,41 @@ def test_adjoint_degenerate_vertex(npga):
     dmu, dL, binfo = npga.backward(L, mu, r, x, to_dev(g))
     assert binfo["degenerate"] == 1 and binfo["support"] == 1
     assert torch.isfinite(dmu).all() and torch.isfinite(dL).all()
+
+
+class _FactorHessian:
+    """H = 2 L L^T applied in factor form (the oracle's KKT report only
+    forms H x)."""
+
+    def __init__(self, L):
+        self.L = L
+
+    def __matmul__(self, x):
+        return 2.0 * (self.L @ (self.L.T @ x))
+
+
+@pytest.mark.parametrize("n,T", [(7000, 7200), (8192, 8192)])
+def test_preconditioned_refinement_largest(npga, n, T):
+    """The preconditioned face CG at 14 and 16 rows per thread (n > 6144 with
+    cols >= n): the float64 KKT certificate of the returned x computed in
+    factor form (a dense oracle solve does not finish in seconds at this
+    size), at the bar of the other certificate test (float32 x: 1e-4 of the
+    gradient), and the same minimiser as the plain face CG."""
+    banner(f"preconditioned refinement n={n} T={T}")
+    Rt, mu_o, L_o = _factor(n, T, 900 + n, K=10)
+    r = float(np.quantile(mu_o, 0.6))
+    L, mu = npga.build_factor(to_dev(Rt))
+    x, info = npga.solve(L, mu, r, path="gemv")
+    assert info["status"] == 0 and info["refined"] == 1, info
+    xp, infop = npga.solve(L, mu, r, path="gemv", refine_precond=False)
+    assert infop["status"] == 0 and infop["refined"] == 1, infop
+    xh = x.cpu().numpy().astype(np.float64)
+    rep = qp.kkt_report(_FactorHessian(L_o), np.zeros(n), mu_o, r, xh,
+                        act_tol=1e-6 * max(abs(r), np.abs(mu_o).max()))
+    assert rep["min_x"] >= 0.0 and rep["budget"] <= 1e-6, rep
+    assert rep["ret_slack"] >= -1e-6 * max(1.0, abs(r)), rep
+    assert rep["stat_support"] <= 1e-4 and rep["dual_offsupport"] >= -1e-4, rep
+    assert np.abs(xh - xp.cpu().numpy()).max() <= 1e-5
+    assert abs(info["objective"] - infop["objective"]) <= 1e-8 * abs(infop["objective"])
+    banner(f"refine_iters {info['refine_iters']} (plain face CG {infop['refine_iters']}), "
+           f"stationarity {rep['stat_support']:.1e}")
