@@ -459,6 +459,17 @@ def main():
     ref2 = _golden("c2_solution.json")
     if ref2 is not None:
         out["solve"]["error_vs_fp64_oracle"] = errors_vs_golden(x, last["objective"], ref2)
+    if last["path_used"] == 1:
+        # the same solve with the refinement's plain face CG (no Nystrom
+        # preconditioner), outside the timed steps
+        Lp, mup = npga.build_factor(R)
+        plain = [npga.solve(Lp, mup, r, path=args.path, refine_precond=False)[1] for _ in range(3)]
+        out["solve"]["plain_face_cg"] = {
+            "solve_ms_incl_refinement": statistics.median(i["time_ms"] for i in plain),
+            "refine_iters": plain[-1]["refine_iters"],
+            "status": plain[-1]["status_name"],
+        }
+        del Lp, mup
     out["auto_path"] = {"choice": npga.auto_path(n, T),
                         "rule": "covariance path for a float32 factor with T >= n (workspace <= 4 GiB), "
                                 "fused sweep otherwise"}
