@@ -1702,9 +1702,14 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
   return NPGA_OK;
 }
 
+// The adjoint's face CG is preconditioned as the refinement's is (npga_pcg.h)
+// for n >= 2048 and cols >= n (the factor shapes whose face Hessian has a
+// few outliers above a narrow bulk).
+bool adj_pcg(int64_t n, int64_t cols) { return n >= 2048 && n <= NPGA_MAX_N && cols >= n; }
+
 size_t npga_backward_workspace_size(int64_t n, int64_t cols) {
   if (n < 1 || n > NPGA_MAX_N || cols < 1) return 0;
-  const SolveLayout l = npga::solve_layout(n, cols, NPGA_PATH_GEMV);
+  const SolveLayout l = npga::solve_layout(n, cols, NPGA_PATH_GEMV, adj_pcg(n, cols));
   const size_t npad = (size_t)256 * l.slots;
   return align_up(l.total, 256) + align_up(sizeof(double) * (3 * npad + (size_t)cols), 256);
 }
@@ -1715,7 +1720,7 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
   const auto t0 = Clock::now();
   if (!factor_valid(f) || !x_star || !dl_dx || !dl_dmu || !is_fin(r) || !aligned(dl_dmu, 8)) return NPGA_ERR_INVALID;
   if (dl_dL && ldg < f->n) return NPGA_ERR_INVALID;
-  const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV);
+  const SolveLayout lay = npga::solve_layout(f->n, f->cols, NPGA_PATH_GEMV, adj_pcg(f->n, f->cols));
   if (!ws || !aligned(ws, 256) || ws_bytes < npga_backward_workspace_size(f->n, f->cols)) return NPGA_ERR_WORKSPACE;
   DevState *pin = pinned_status();
   if (!pin) return NPGA_ERR_HIP;
@@ -1760,6 +1765,15 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
   Carved cg = c;
   cg.a.mode = npga::kTailAdj;
   cg.a.ga = nullptr;
+  if (lay.pcg) {
+    // the face CG preconditioned as in the refinement: Y = H Omega once
+    LAUNCHCHK(pcg_build(f, lay, base, stream));
+    cg.a.pre_y = reinterpret_cast<const float *>(base + lay.off_pre_y);
+    cg.a.pre_yt = reinterpret_cast<const float *>(base + lay.off_pre_yt);
+    cg.a.pre_mat = reinterpret_cast<double *>(base + lay.off_pre_mat);
+    cg.a.pre_a1 = reinterpret_cast<double *>(base + lay.off_pre_a1);
+    cg.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
+  }
   hipEvent_t evs[2], ev0;
   EventSet<3> events;
   HIPCHK(events.make(&ev0));
@@ -1776,6 +1790,9 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
     }
     LAUNCHCHK(npga::launch_phase(c.st, 0, 0.0, max_iter, 0, stream));
     LAUNCHCHK(npga::launch_adj_init(cg.a, rr, slots, stream));
+    // first direction: S and sigma on the face in the first round, the
+    // face's factor again in the second
+    if (cg.a.pre_y) LAUNCHCHK(npga::launch_pcg_init(cg.a, slots, round == 0, stream));
     double ms = 0.0;
     const int64_t chunks = (int64_t)max_iter / o.check_every + 4;
     int e = run_phase(cg, NPGA_PATH_GEMV, slots, o.check_every, chunks, stream, pin, evs, ev0, &done, &ms, nullptr);

@@ -12,8 +12,9 @@
 //               NPGA: stopping test, momentum extrapolation, gradient step
 //               and the exact projection).  The kernel boundaries order the
 //               writes; no workgroup waits on another.
-// In the refinement's active-set mode with the preconditioner set, a fourth
-// launch (k_pcg_step) forms the next search direction after the tail.
+// In the refinement's active-set mode and the adjoint's face CG with the
+// preconditioner set, a fourth launch (k_pcg_step) forms the next search
+// direction after the tail.
 //
 // The sweep evaluates the gradient at the iterate x_k rather than at the
 // extrapolated point y_k: the gradient is affine in x, so
@@ -939,6 +940,12 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
 #define CALL(E) hipLaunchKernelGGL(k_tail_adj<E>, dim3(1), dim3(256), 0, s, a)
       NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
+      if (a.pre_y) {
+        if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
+        NPGA_PCG_SLOT_SWITCH(slots, CALL)
+#undef CALL
+      }
       break;
     case kTailPower:
 #define CALL(E) hipLaunchKernelGGL(k_tail_power<E>, dim3(1), dim3(256), 0, s, a, covariance)

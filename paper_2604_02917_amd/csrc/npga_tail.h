@@ -1240,7 +1240,10 @@ __device__ void tail_adj(const SolveArgs &a, double *redbuf) {
     fr[j] = ok ? a.fvec[i] : 0.0;
   }
   const bool active = st->cg_active != 0;
-  const double rr = st->cg_rr;
+  // with the preconditioner set (a.pre_y) the directions come from
+  // k_pcg_step after this tail, and the step length from its g^T z
+  const bool pre = a.pre_y != nullptr;
+  const double rr = pre ? st->pcg_rz : st->cg_rr;
   double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < E; ++j) acc[0] = fma(fr[j] * p[j], hp[j], acc[0]);
@@ -1283,11 +1286,16 @@ __device__ void tail_adj(const SolveArgs &a, double *redbuf) {
     if (i < n) {
       a.xbuf0[i] = x[j];
       a.gvec[i] = q[j];
-      a.pvec[i] = p[j];
-      a.xs[i] = (float)p[j];
+      if (!pre) {
+        a.pvec[i] = p[j];
+        a.xs[i] = (float)p[j];
+      }
     }
   }
   if (tid == 0) {
+    st->pcg_todo = 1;
+    st->pcg_lam0 = lam;
+    st->pcg_nu0 = nu;
     st->cg_iter = it;
     st->cg_rr = rr_new;
     st->cg_best_rr = best;

@@ -8,6 +8,9 @@ a held-out block (same B and drift, fresh factor and noise draws, seed 105,
 5000 periods).  The GPU runs at the oracle's exact x* (float32), so the two
 sides differentiate at the same point.
 
+The n = 2048, T = 6000 case runs the face CG with the Nystrom
+preconditioner (n >= 2048 with at least as many columns as assets).
+
 Bar: the adjoint solve uses float32 products with one float64 correction
 round, so dl/dmu and dl/dL agree with the oracle to 1e-4 of their largest
 entry; dl/dr and dl/dgamma to 1e-4 relative."""
@@ -77,7 +80,7 @@ def _compare(npga, Rt, mu_o, L_o, r, s, grad, gamma, tag):
 
 @pytest.mark.parametrize("n,T,seed,q,gamma", [(200, 2000, 5, 0.6, 0.0), (200, 2000, 5, 0.9, 0.0),
                                               (131, 700, 7, 0.5, 1e-5), (150, 1200, 8, None, 0.0),
-                                              (300, 400, 9, 0.7, 2e-5)])
+                                              (300, 400, 9, 0.7, 2e-5), (2048, 6000, 12, 0.6, 1e-5)])
 def test_backward_vs_oracle(npga, n, T, seed, q, gamma):
     Rt, mu_o, L_o, r, s, grad = _case(n, T, seed, q, gamma)
     _compare(npga, Rt, mu_o, L_o, r, s, grad, gamma, f"adjoint n={n} T={T} q={q} gamma={gamma}")
