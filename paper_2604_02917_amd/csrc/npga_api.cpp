@@ -148,6 +148,8 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg) {
     l.off_pre_p = take(sizeof(float) * (size_t)kPreMaxSplits * (size_t)n * kPreK);
     l.off_pre_usq = take(sizeof(double) * (size_t)((cols + 31) / 32) * kPreK);
     l.off_pre_act = take(sizeof(int32_t) * (size_t)(kPreK + 1));
+    l.off_pre_z = take(sizeof(double) * (size_t)npad);
+    l.off_pre_part = take(sizeof(double) * (size_t)kPreMaxRowBlocks * (kPreK + 5));
   }
   l.total = off;
   return l;
@@ -617,6 +619,8 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
       c.a.pre_mat = reinterpret_cast<double *>(base + lay.off_pre_mat);
       c.a.pre_a1 = reinterpret_cast<double *>(base + lay.off_pre_a1);
       c.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
+      c.a.pre_z = reinterpret_cast<double *>(base + lay.off_pre_z);
+      c.a.pre_part = reinterpret_cast<double *>(base + lay.off_pre_part);
     }
     // rounds re-anchored in float64 at the previous round's result (removes
     // the drift of the gradient carried by linearity).  A round that ends
@@ -1773,6 +1777,8 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
     cg.a.pre_mat = reinterpret_cast<double *>(base + lay.off_pre_mat);
     cg.a.pre_a1 = reinterpret_cast<double *>(base + lay.off_pre_a1);
     cg.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
+    cg.a.pre_z = reinterpret_cast<double *>(base + lay.off_pre_z);
+    cg.a.pre_part = reinterpret_cast<double *>(base + lay.off_pre_part);
   }
   hipEvent_t evs[2], ev0;
   EventSet<3> events;

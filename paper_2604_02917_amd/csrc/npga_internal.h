@@ -108,6 +108,7 @@ struct alignas(256) DevState {
   double pdas_eta2;                // inner CG tolerance ||r||^2 <= eta2 ||r_0||^2
   double pcg_rz;                   // preconditioned face CG: g^T z of the current direction
   int32_t pcg_todo;                // after the tail: 0 nothing, 1 next direction, 2 new face
+  int32_t pcg_arrive;              // workgroups of the direction's last launch that have finished
   double pcg_lam0, pcg_nu0;        // the tail's least-squares multipliers of the current g
   // adjoint results
   double adj_alam, adj_anu;  // multipliers of the adjoint system (a_lam, a_nu)
@@ -172,6 +173,11 @@ struct SolveArgs {
   double *pre_mat;
   double *pre_a1;
   double *pre_a2;
+  // a direction on an unchanged face spread over one workgroup per 256
+  // rows: z = M_F^{-1} r before its projection (n) and the workgroups'
+  // partial sums (kPreMaxRowBlocks x (kPreK + 5))
+  double *pre_z;
+  double *pre_part;
 };
 
 // Rank of the Nystrom sketch of the refinement's preconditioner, the
@@ -180,6 +186,7 @@ constexpr int kPreK = 32;
 constexpr int kPcgMaxE = 16;
 constexpr int kPreMatDoubles = 2 * kPreK * kPreK + 8;
 constexpr int kPreMaxSplits = 64;  // period ranges of the multi-vector product's G GEMM
+constexpr int kPreMaxRowBlocks = 32;  // 256-row blocks of the spread direction (n <= 8192)
 
 // m independent solves sharing L (one target return per solve).  Target j
 // uses the SolveArgs of target 0 with every per-target pointer advanced by
@@ -245,7 +252,7 @@ struct SolveLayout {
   // multi-vector product's GEMM buffers (Omega, U^T, split partials, column
   // sums, active list)
   size_t off_pre_y, off_pre_yt, off_pre_mat, off_pre_a1, off_pre_a2, off_pre_x, off_pre_ut, off_pre_p, off_pre_usq,
-      off_pre_act;
+      off_pre_act, off_pre_z, off_pre_part;
   bool pcg;
   int32_t slots;
   int32_t sweep_grid;

@@ -520,6 +520,58 @@ __global__ __launch_bounds__(64 * NW) void k_tail_pdas(SolveArgs a) {
 // the same at the start of a later round (after k_cg_init).  INIT (the
 // start of the first round): S = Omega^T Y and sigma on the round's first
 // face, its factor, p = -z.  Eight wavefronts.
+// The next direction on an unchanged face (pcg_todo = 1) in three launches
+// spread over row blocks, one row per thread, where k_pcg_step's single
+// workgroup reads Y alone.  The arithmetic is pcg_direction's with
+// r = g - lam0 1 - nu0 mu from the tail's multipliers:
+//   k_pcg_step (one 512-thread workgroup per 512 rows): partial sums of
+//     t = Y_F^T r per row block;
+//   k_pcg_dir_z (one 256-thread workgroup per 256 rows): every workgroup
+//     adds the partials in block order and solves K s = t (the same s in
+//     each), z = (r - Y_F s) / sigma, and partial sums of 1^T z, mu^T z,
+//     r^T z, r^T a1, r^T a2;
+//   k_pcg_dir_p: every workgroup adds those in block order, projects z in
+//     the M metric and writes p = -z + beta p; the last workgroup to
+//     finish stores r^T z for the next step.
+__device__ __forceinline__ bool pcg_dir_runs(const SolveArgs &a) {
+  return a.st->done == kRunning && a.st->pcg_todo == 1;
+}
+
+__device__ __forceinline__ double pcg_dir_residual(const SolveArgs &a, int64_t i) {
+  const DevState *st = a.st;
+  return (i < a.n && a.fvec[i] > 0.0) ? a.gvec[i] - st->pcg_lam0 - st->pcg_nu0 * a.mu[i] : 0.0;
+}
+
+// Partial sums of Y_F^T r over this workgroup's kPcgThreads rows into
+// pre_part (kPreK per block); tw: kPcgWaves x kPreK doubles of LDS.
+__device__ __forceinline__ void pcg_dir_t(const SolveArgs &a, double *tw) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kPcgThreads + tid;
+  const double r = pcg_dir_residual(a, i);
+#pragma unroll
+  for (int q = 0; q < kPreK / 8; ++q) {
+    double t8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r != 0.0) {
+      // column-major Y: lanes read consecutive rows of one column
+      const float *yc = a.pre_yt + (int64_t)(8 * q) * a.ldp + i;
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) t8[cc] = (double)yc[cc * a.ldp] * r;
+    }
+    const double v = wave_reduce8(t8, lane);
+    if ((lane & 7) == 0) tw[wave * kPreK + 8 * q + 4 * (lane >> 5) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1)] = v;
+  }
+  __syncthreads();
+  if (tid < kPreK) {
+    double e = 0.0, o = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPcgWaves; w += 2) {
+      e += tw[w * kPreK + tid];
+      o += tw[(w + 1) * kPreK + tid];
+    }
+    a.pre_part[(int64_t)blockIdx.x * kPreK + tid] = e + o;
+  }
+}
+
 template <int E, bool INIT>
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force) {
   __shared__ double redbuf[red_buf_doubles<kPcgWaves>()];
@@ -528,6 +580,13 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force
   if (st->done != kRunning) return;
   const int todo = INIT ? 3 : (force ? force : st->pcg_todo);
   if (todo == 0) return;
+  // a direction on an unchanged face: this launch's blocks take the first
+  // of the row-block passes; everything else runs in block 0 alone
+  if (todo == 1 && a.pre_z) {
+    pcg_dir_t(a, sh.t);
+    return;
+  }
+  if (blockIdx.x != 0) return;
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   BlockReducer<5, kPcgWaves> red{redbuf, 0};
@@ -566,7 +625,108 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force
   if (tid == 0) {
     st->pcg_rz = rz;
     st->pcg_todo = 0;
+    st->pcg_arrive = 0;
     if (!isfinite(rz)) st->done = kNumeric;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pcg_dir_z(SolveArgs a, int tblocks) {
+  __shared__ double kc[kPreK * kPreLd];
+  __shared__ double dinv[kPreK];
+  __shared__ double sv[kPreK];
+  __shared__ double tp[(kPreMaxRowBlocks / 2) * kPreK];
+  __shared__ double redbuf[64];
+  if (!pcg_dir_runs(a)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double *pm = a.pre_mat;
+  const bool lowrank = pm[kPreOk] > 0.5;
+  const double sigma = pm[kPreSigma];
+  if (lowrank) {
+    // every load in flight at once, then the sums from LDS
+    for (int e = tid; e < kPreKK; e += 256) kc[(e >> 5) * kPreLd + (e & 31)] = pm[kPreKK + e];
+    for (int e = tid; e < tblocks * kPreK; e += 256) tp[e] = a.pre_part[e];
+    if (tid < kPreK) dinv[tid] = 1.0 / pm[kPreKK + tid * kPreK + tid];
+    __syncthreads();
+    if (wave == 0) {
+      double tc = 0.0;
+      if (lane < kPreK) {
+        for (int b = 0; b < tblocks; ++b) tc += tp[b * kPreK + lane];
+      }
+      tc = chol_solve_lanes(kc, dinv, tc, lane);
+      if (lane < kPreK) sv[lane] = tc;
+    }
+    __syncthreads();
+  }
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  const double r = pcg_dir_residual(a, i);
+  double z = 0.0;
+  if (i < a.n && a.fvec[i] > 0.0) {
+    double w = r;
+    if (lowrank) {
+      const float *yc = a.pre_yt + i;
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < kPreK; ++c) acc = fma((double)yc[c * a.ldp], sv[c], acc);
+      w -= acc;
+    }
+    z = w * (1.0 / sigma);
+  }
+  const double a1 = (i < a.n) ? a.pre_a1[i] : 0.0;
+  const double a2 = (i < a.n) ? a.pre_a2[i] : 0.0;
+  const double mu = (i < a.n) ? a.mu[i] : 0.0;
+  if (i < a.n) a.pre_z[i] = z;
+  double acc[5] = {z, mu * z, r * z, r * a1, r * a2};
+  BlockReducer<5> red{redbuf, 0};
+  red.sum(acc);
+  if (tid < 5) a.pre_part[(int64_t)kPreMaxRowBlocks * kPreK + (int64_t)blockIdx.x * 5 + tid] = acc[tid];
+}
+
+__global__ __launch_bounds__(256) void k_pcg_dir_p(SolveArgs a) {
+  __shared__ double q5[kPreMaxRowBlocks * 5];
+  __shared__ double s5[5];
+  DevState *st = a.st;
+  if (!pcg_dir_runs(a)) return;
+  const int tid = threadIdx.x;
+  if (tid < (int)gridDim.x * 5) q5[tid] = a.pre_part[(int64_t)kPreMaxRowBlocks * kPreK + tid];
+  __syncthreads();
+  if (tid < 5) {
+    double v = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) v += q5[b * 5 + tid];
+    s5[tid] = v;
+  }
+  __syncthreads();
+  const double *pm = a.pre_mat;
+  const double A11 = pm[kPreA11], A12 = pm[kPreA12], A22 = pm[kPreA22];
+  double lam = (A11 > 0.0) ? s5[0] / A11 : 0.0, nu = 0.0;
+  if (st->cg_active != 0) {
+    const double det = A11 * A22 - A12 * A12;
+    if (det > 1e-30 * A11 * A22) {
+      lam = (A22 * s5[0] - A12 * s5[1]) / det;
+      nu = (A11 * s5[1] - A12 * s5[0]) / det;
+    }
+  }
+  const double rz = s5[2] - lam * s5[3] - nu * s5[4];
+  const double rz_old = st->pcg_rz;
+  const double beta = (rz_old > 0.0) ? rz / rz_old : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  if (i < a.n) {
+    const double z = (a.fvec[i] > 0.0) ? fma(-nu, a.pre_a2[i], fma(-lam, a.pre_a1[i], a.pre_z[i])) : 0.0;
+    const double p = fma(beta, a.pvec[i], -z);
+    a.pvec[i] = p;
+    a.xs[i] = (float)p;
+  }
+  // every workgroup has read pcg_rz and pcg_todo before it arrives; the
+  // last one to arrive stores the new values
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&st->pcg_arrive, 1);
+    if (prev == (int)gridDim.x - 1) {
+      st->pcg_arrive = 0;
+      st->pcg_rz = rz;
+      st->pcg_todo = 0;
+      if (!isfinite(rz)) st->done = kNumeric;
+    }
   }
 }
 
@@ -876,6 +1036,23 @@ int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, f
   return (int)hipGetLastError();
 }
 
+// The preconditioner's launches after a refinement or adjoint tail: a face
+// change (k_pcg_step), else the direction on the same face over row blocks.
+int launch_pcg_after_tail(const SolveArgs &a, int slots, hipStream_t s) {
+  if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
+  const int tblocks = a.pre_z ? (int)((a.n + kPcgThreads - 1) / kPcgThreads) : 1;
+  const int blocks = (int)((a.n + 255) / 256);
+  if (a.pre_z && (blocks > kPreMaxRowBlocks || 2 * tblocks > kPreMaxRowBlocks || !a.pre_part))
+    return (int)hipErrorInvalidValue;
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(tblocks), dim3(kPcgThreads), 0, s, a, 0)
+  NPGA_PCG_SLOT_SWITCH(slots, CALL)
+#undef CALL
+  if (!a.pre_z) return (int)hipGetLastError();
+  hipLaunchKernelGGL(k_pcg_dir_z, dim3(blocks), dim3(256), 0, s, a, tblocks);
+  hipLaunchKernelGGL(k_pcg_dir_p, dim3(blocks), dim3(256), 0, s, a);
+  return (int)hipGetLastError();
+}
+
 int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
   if ((a.dykstra || a.backtrack) && a.mode == kTailNpga) {
     // the NPGA tail with Dykstra's projections and/or backtracking: own
@@ -929,23 +1106,13 @@ int launch_tail(const SolveArgs &a, int slots, int covariance, hipStream_t s) {
         NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
       }
-      if (a.pre_y) {
-        if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
-#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
-        NPGA_PCG_SLOT_SWITCH(slots, CALL)
-#undef CALL
-      }
+      if (a.pre_y) return launch_pcg_after_tail(a, slots, s);
       break;
     case kTailAdj:
 #define CALL(E) hipLaunchKernelGGL(k_tail_adj<E>, dim3(1), dim3(256), 0, s, a)
       NPGA_SLOT_SWITCH(slots, CALL)
 #undef CALL
-      if (a.pre_y) {
-        if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
-#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
-        NPGA_PCG_SLOT_SWITCH(slots, CALL)
-#undef CALL
-      }
+      if (a.pre_y) return launch_pcg_after_tail(a, slots, s);
       break;
     case kTailPower:
 #define CALL(E) hipLaunchKernelGGL(k_tail_power<E>, dim3(1), dim3(256), 0, s, a, covariance)
