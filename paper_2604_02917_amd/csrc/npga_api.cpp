@@ -150,6 +150,7 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg) {
     l.off_pre_act = take(sizeof(int32_t) * (size_t)(kPreK + 1));
     l.off_pre_z = take(sizeof(double) * (size_t)npad);
     l.off_pre_part = take(sizeof(double) * (size_t)kPreMaxRowBlocks * (kPreK + 5));
+    l.off_pre_gpart = take(sizeof(double) * (size_t)kPreMaxRowBlocks * kPreK * kPreK);
   }
   l.total = off;
   return l;
@@ -621,6 +622,7 @@ static int solve_once(const npga_factor *f, double r, const npga_options *opt, f
       c.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
       c.a.pre_z = reinterpret_cast<double *>(base + lay.off_pre_z);
       c.a.pre_part = reinterpret_cast<double *>(base + lay.off_pre_part);
+      c.a.pre_gpart = reinterpret_cast<double *>(base + lay.off_pre_gpart);
     }
     // rounds re-anchored in float64 at the previous round's result (removes
     // the drift of the gradient carried by linearity).  A round that ends
@@ -1779,6 +1781,7 @@ int npga_backward(const npga_factor *f, double r, const float *x_star, const flo
     cg.a.pre_a2 = reinterpret_cast<double *>(base + lay.off_pre_a2);
     cg.a.pre_z = reinterpret_cast<double *>(base + lay.off_pre_z);
     cg.a.pre_part = reinterpret_cast<double *>(base + lay.off_pre_part);
+    cg.a.pre_gpart = reinterpret_cast<double *>(base + lay.off_pre_gpart);
   }
   hipEvent_t evs[2], ev0;
   EventSet<3> events;

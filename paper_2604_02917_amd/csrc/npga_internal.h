@@ -178,6 +178,9 @@ struct SolveArgs {
   // partial sums (kPreMaxRowBlocks x (kPreK + 5))
   double *pre_z;
   double *pre_part;
+  // the row blocks' partial Gram products of a face change (per block of
+  // 512 rows: Y_F^T Y_F, then Omega^T Y; kPreMaxRowBlocks / 2 x 2 x kPreK^2)
+  double *pre_gpart;
 };
 
 // Rank of the Nystrom sketch of the refinement's preconditioner, the
@@ -252,7 +255,7 @@ struct SolveLayout {
   // multi-vector product's GEMM buffers (Omega, U^T, split partials, column
   // sums, active list)
   size_t off_pre_y, off_pre_yt, off_pre_mat, off_pre_a1, off_pre_a2, off_pre_x, off_pre_ut, off_pre_p, off_pre_usq,
-      off_pre_act, off_pre_z, off_pre_part;
+      off_pre_act, off_pre_z, off_pre_part, off_pre_gpart;
   bool pcg;
   int32_t slots;
   int32_t sweep_grid;

@@ -73,7 +73,7 @@ struct PcgShared {
   double t[kPcgWaves * kPreK];             // per-wavefront partial sums of Y^T v
   double s[kPreK];                         // K^{-1} Y^T v
   double scal[8];                          // sigma, A11, A12, A22, ok (as pre_mat's scalars)
-  unsigned char mask[kPcgThreads * kPcgMaxE];  // face flags of the rows
+  int last;                                // this workgroup arrived last
 };
 
 // Sum over the wavefront of eight values per lane; lane l returns the total
@@ -129,21 +129,21 @@ __device__ __forceinline__ double chol_solve_lanes(const double *C, const double
   return v;
 }
 
-// out = sum_i w_i y_i^T over the rows of the face (OMEGA: w_i = Omega row i
-// over all rows, i.e. S = Omega^T Y; else w_i = y_i on masked rows, i.e.
-// Y_F^T Y_F) on v_mfma_f64_16x16x4f64: the float32 entries of Y are exact
-// in float64 and so are their products, and the sums are float64 (float32
-// sums would bury the bulk of the spectrum, ~1e-7 of the factor part of
-// Y^T Y, in rounding).  A contiguous range of rows per wavefront, 2 x 2
-// blocks of 16 x 16; the wavefront partials added in a fixed order.
+// out = sum_i w_i y_i^T over this workgroup's kPcgThreads rows (OMEGA:
+// w_i = Omega row i over all rows, the block's part of S = Omega^T Y; else
+// w_i = y_i on the face's rows, its part of Y_F^T Y_F), into global memory,
+// on v_mfma_f64_16x16x4f64: the float32 entries of Y are exact in float64
+// and so are their products, and the sums are float64 (float32 sums would
+// bury the bulk of the spectrum, ~1e-7 of the factor part of Y^T Y, in
+// rounding).  64 rows per wavefront, 2 x 2 blocks of 16 x 16; the
+// wavefront partials added in a fixed order.
 template <bool OMEGA>
-__device__ __forceinline__ void pcg_gram(const SolveArgs &a, PcgShared &sh, double *out) {
+__device__ __forceinline__ void pcg_gram_rows(const SolveArgs &a, PcgShared &sh, double *out) {
   typedef double pcg_d4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = a.n;
-  const int64_t per = ((n + 4 * kPcgWaves - 1) / (4 * kPcgWaves)) * 4;
-  const int64_t r0 = (int64_t)wave * per;
-  const int64_t r1 = (r0 + per < n) ? r0 + per : n;
+  const int64_t r0 = (int64_t)blockIdx.x * kPcgThreads + 64 * wave;
+  const int64_t r1 = (r0 + 64 < n) ? r0 + 64 : n;
   const int c = lane & 15, kq = lane >> 4;
   pcg_d4 acc[2][2];
 #pragma unroll
@@ -159,7 +159,7 @@ __device__ __forceinline__ void pcg_gram(const SolveArgs &a, PcgShared &sh, doub
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
       const int64_t i = b0 + 4 * u + kq;
-      kb[u] = i < r1 && (OMEGA || sh.mask[i] != 0);
+      kb[u] = i < r1 && (OMEGA || a.fvec[i] > 0.0);
 #pragma unroll
       for (int p = 0; p < 2; ++p) yb[u][p] = (i < r1) ? a.pre_y[i * kPreK + 16 * p + c] : 0.f;
     }
@@ -194,6 +194,24 @@ __device__ __forceinline__ void pcg_gram(const SolveArgs &a, PcgShared &sh, doub
       od += sh.part[(w + 1) * kPreKK + e];
     }
     out[e] = ev + od;
+  }
+  __syncthreads();
+}
+
+// out (LDS) = the sum over the row blocks, in block order, of their
+// partial products (block b's at gp + (2 b + which) kPreKK).
+__device__ __forceinline__ void pcg_gram_sum(const double *gp, int blocks, int which, double *out) {
+  for (int e = threadIdx.x; e < kPreKK; e += kPcgThreads) {
+    const double *g = gp + (int64_t)which * kPreKK + e;
+    double acc = 0.0;
+    for (int b0 = 0; b0 < blocks; b0 += 4) {
+      double v[4];  // four loads in flight, then their sums in order
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (b0 + u < blocks) ? g[(int64_t)(b0 + u) * 2 * kPreKK] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += v[u];
+    }
+    out[e] = acc;
   }
   __syncthreads();
 }
@@ -285,27 +303,22 @@ __device__ __forceinline__ void pcg_apply(const SolveArgs &a, const double (&v)[
   }
 }
 
-// Preconditioner for the face fr (LDS mask written here): K = sigma S +
-// Y_F^T Y_F and its Cholesky factor (into sh.kc and pre_mat), then a1, a2
-// and the 2 x 2 metric of the equality rows.  INIT: S = Omega^T Y is formed
-// and sigma estimated on this face (kept for the later faces and rounds of
-// the solve).
+// Preconditioner for the face fr: K = sigma S + Y_F^T Y_F and its Cholesky
+// factor (into sh.kc and pre_mat), then a1, a2 and the 2 x 2 metric of the
+// equality rows.  The Gram products come from the row blocks' partials in
+// pre_gpart (gblocks blocks).  INIT: S = Omega^T Y is formed and sigma
+// estimated on this face (kept for the later faces and rounds of the
+// solve).
 template <int E, bool INIT>
 __device__ __forceinline__ void pcg_face(const SolveArgs &a, const double (&fr)[E], const double (&mu)[E], PcgShared &sh,
-                         BlockReducer<5, kPcgWaves> &red) {
+                         BlockReducer<5, kPcgWaves> &red, int gblocks) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = a.n;
   double *pm = a.pre_mat;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + kPcgThreads * j;
-    if (i < n) sh.mask[i] = fr[j] > 0.0 ? 1 : 0;
-  }
-  __syncthreads();
-  pcg_gram<false>(a, sh, sh.m2);
+  pcg_gram_sum(a.pre_gpart, gblocks, 0, sh.m2);
   double sigma;
   if constexpr (INIT) {
-    pcg_gram<true>(a, sh, sh.part);
+    pcg_gram_sum(a.pre_gpart, gblocks, 1, sh.part);
     // S symmetric up to rounding: keep its symmetric part (pre_mat, and
     // padded rows in kc for the matvecs below)
     double sym[kPreKK / kPcgThreads];

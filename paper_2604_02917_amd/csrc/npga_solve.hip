@@ -168,6 +168,7 @@ __global__ void k_phase_reset(DevState *st, double tol, int32_t max_iter, int32_
     st->restart = 1;
     st->t = 1.0;
     st->beta = 0.0;
+    st->pcg_arrive = 0;
   }
 }
 
@@ -177,6 +178,7 @@ __global__ void k_phase(DevState *st, double tol, int32_t max_iter, int32_t rest
     st->tol = tol;
     st->max_iter = max_iter;
     st->restart = restart;
+    st->pcg_arrive = 0;
   }
 }
 
@@ -572,8 +574,17 @@ __device__ __forceinline__ void pcg_dir_t(const SolveArgs &a, double *tw) {
   }
 }
 
+// A solve's first round start: both partial Gram products (Y_F^T Y_F and
+// Omega^T Y) of each block of kPcgThreads rows.
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_gram_init(SolveArgs a) {
+  __shared__ PcgShared sh;
+  if (a.st->done != kRunning) return;
+  pcg_gram_rows<false>(a, sh, a.pre_gpart + (int64_t)blockIdx.x * 2 * kPreKK);
+  pcg_gram_rows<true>(a, sh, a.pre_gpart + ((int64_t)blockIdx.x * 2 + 1) * kPreKK);
+}
+
 template <int E, bool INIT>
-__global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force) {
+__global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force, int gblocks) {
   __shared__ double redbuf[red_buf_doubles<kPcgWaves>()];
   __shared__ PcgShared sh;
   DevState *st = a.st;
@@ -581,12 +592,24 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force
   const int todo = INIT ? 3 : (force ? force : st->pcg_todo);
   if (todo == 0) return;
   // a direction on an unchanged face: this launch's blocks take the first
-  // of the row-block passes; everything else runs in block 0 alone
-  if (todo == 1 && a.pre_z) {
+  // of the row-block passes
+  if (todo == 1) {
     pcg_dir_t(a, sh.t);
     return;
   }
-  if (blockIdx.x != 0) return;
+  // a new face: every block forms its rows' partial Gram product; the last
+  // block to arrive goes on alone with their sums (at a solve's first round
+  // start k_pcg_gram_init has formed both partials and one block runs)
+  if constexpr (!INIT) {
+    pcg_gram_rows<false>(a, sh, a.pre_gpart + (int64_t)blockIdx.x * 2 * kPreKK);
+    __threadfence();  // the partials are visible device-wide before the block arrives
+    __syncthreads();
+    if (threadIdx.x == 0) sh.last = (atomicAdd(&st->pcg_arrive, 1) == (int)gridDim.x - 1) ? 1 : 0;
+    __syncthreads();
+    if (!sh.last) return;
+    __threadfence();  // and read after every block has arrived
+    gblocks = (int)gridDim.x;
+  }
   const int tid = threadIdx.x;
   const int64_t n = a.n;
   BlockReducer<5, kPcgWaves> red{redbuf, 0};
@@ -599,8 +622,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force
     fr[j] = ok ? a.fvec[i] : 0.0;
   }
   const bool active = st->cg_active != 0;
-  if (INIT) pcg_face<E, true>(a, fr, mu, sh, red);
-  else if (todo == 2) pcg_face<E, false>(a, fr, mu, sh, red);
+  if (INIT) pcg_face<E, true>(a, fr, mu, sh, red, gblocks);
+  else if (todo == 2) pcg_face<E, false>(a, fr, mu, sh, red, gblocks);
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + kPcgThreads * j;
@@ -1006,14 +1029,29 @@ int launch_reduce_tail(const SolveArgs &a, int slots, hipStream_t s) {
     default: return (int)hipErrorInvalidValue;                \
   }
 
+// Row blocks of the preconditioner's launches: 512-row blocks of k_pcg_step
+// (0 if the buffers are missing or n is too large) and 256-row blocks of
+// the direction kernels.
+static int pcg_row_blocks(const SolveArgs &a, int *blocks) {
+  if (!a.pre_y || !a.pre_yt || !a.pre_mat || !a.pre_a1 || !a.pre_a2 || !a.pre_z || !a.pre_part || !a.pre_gpart)
+    return 0;
+  const int tblocks = (int)((a.n + kPcgThreads - 1) / kPcgThreads);
+  *blocks = (int)((a.n + 255) / 256);
+  if (*blocks > kPreMaxRowBlocks || 2 * tblocks > kPreMaxRowBlocks) return 0;
+  return tblocks;
+}
+
 int launch_pcg_init(const SolveArgs &a, int slots, bool first, hipStream_t s) {
-  if (!a.pre_y || !a.pre_yt || !a.pre_mat || !a.pre_a1 || !a.pre_a2) return (int)hipErrorInvalidValue;
+  int blocks = 0;
+  const int tblocks = pcg_row_blocks(a, &blocks);
+  if (tblocks < 1) return (int)hipErrorInvalidValue;
   if (first) {
-#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, true>), dim3(1), dim3(kPcgThreads), 0, s, a, 0)
+    hipLaunchKernelGGL(k_pcg_gram_init, dim3(tblocks), dim3(kPcgThreads), 0, s, a);
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, true>), dim3(1), dim3(kPcgThreads), 0, s, a, 0, tblocks)
     NPGA_PCG_SLOT_SWITCH(slots, CALL)
 #undef CALL
   } else {
-#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(1), dim3(kPcgThreads), 0, s, a, 2)
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(tblocks), dim3(kPcgThreads), 0, s, a, 2, 0)
     NPGA_PCG_SLOT_SWITCH(slots, CALL)
 #undef CALL
   }
@@ -1040,14 +1078,12 @@ int launch_pre_reduce(const float *P, int64_t ldpm, int32_t splits, int64_t n, f
 // change (k_pcg_step), else the direction on the same face over row blocks.
 int launch_pcg_after_tail(const SolveArgs &a, int slots, hipStream_t s) {
   if (hipGetLastError() != hipSuccess) return (int)hipErrorLaunchFailure;
-  const int tblocks = a.pre_z ? (int)((a.n + kPcgThreads - 1) / kPcgThreads) : 1;
-  const int blocks = (int)((a.n + 255) / 256);
-  if (a.pre_z && (blocks > kPreMaxRowBlocks || 2 * tblocks > kPreMaxRowBlocks || !a.pre_part))
-    return (int)hipErrorInvalidValue;
-#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(tblocks), dim3(kPcgThreads), 0, s, a, 0)
+  int blocks = 0;
+  const int tblocks = pcg_row_blocks(a, &blocks);
+  if (tblocks < 1) return (int)hipErrorInvalidValue;
+#define CALL(E) hipLaunchKernelGGL((k_pcg_step<E, false>), dim3(tblocks), dim3(kPcgThreads), 0, s, a, 0, 0)
   NPGA_PCG_SLOT_SWITCH(slots, CALL)
 #undef CALL
-  if (!a.pre_z) return (int)hipGetLastError();
   hipLaunchKernelGGL(k_pcg_dir_z, dim3(blocks), dim3(256), 0, s, a, tblocks);
   hipLaunchKernelGGL(k_pcg_dir_p, dim3(blocks), dim3(256), 0, s, a);
   return (int)hipGetLastError();
