@@ -150,7 +150,7 @@ SolveLayout solve_layout(int64_t n, int64_t cols, int path, bool pcg) {
     l.off_pre_act = take(sizeof(int32_t) * (size_t)(kPreK + 1));
     l.off_pre_z = take(sizeof(double) * (size_t)npad);
     l.off_pre_part = take(sizeof(double) * (size_t)kPreMaxRowBlocks * (kPreK + 5));
-    l.off_pre_gpart = take(sizeof(double) * (size_t)kPreMaxRowBlocks * kPreK * kPreK);
+    l.off_pre_gpart = take(sizeof(double) * (size_t)kPreGpartDoubles);
   }
   l.total = off;
   return l;

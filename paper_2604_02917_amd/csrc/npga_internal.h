@@ -178,8 +178,9 @@ struct SolveArgs {
   // partial sums (kPreMaxRowBlocks x (kPreK + 5))
   double *pre_z;
   double *pre_part;
-  // the row blocks' partial Gram products of a face change (per block of
-  // 512 rows: Y_F^T Y_F, then Omega^T Y; kPreMaxRowBlocks / 2 x 2 x kPreK^2)
+  // the row blocks' partial products of a face change, per block of 512
+  // rows: Y_F^T Y_F, then Omega^T Y (kPreMaxRowBlocks / 2 x 2 x kPreK^2);
+  // from kPreGpartT, Y_F^T 1_F and Y_F^T mu_F (2 x kPreK per block)
   double *pre_gpart;
 };
 
@@ -190,6 +191,8 @@ constexpr int kPcgMaxE = 16;
 constexpr int kPreMatDoubles = 2 * kPreK * kPreK + 8;
 constexpr int kPreMaxSplits = 64;  // period ranges of the multi-vector product's G GEMM
 constexpr int kPreMaxRowBlocks = 32;  // 256-row blocks of the spread direction (n <= 8192)
+constexpr int kPreGpartT = kPreMaxRowBlocks * kPreK * kPreK;
+constexpr int kPreGpartDoubles = kPreGpartT + kPreMaxRowBlocks * kPreK;
 
 // m independent solves sharing L (one target return per solve).  Target j
 // uses the SolveArgs of target 0 with every per-target pointer advanced by

@@ -72,6 +72,7 @@ struct PcgShared {
   double dinv3[kPreK];                     // reciprocal pivots of m3's factor
   double t[kPcgWaves * kPreK];             // per-wavefront partial sums of Y^T v
   double s[kPreK];                         // K^{-1} Y^T v
+  double s2[kPreK];                        // K^{-1} Y_F^T mu_F (a face change)
   double scal[8];                          // sigma, A11, A12, A22, ok (as pre_mat's scalars)
   int last;                                // this workgroup arrived last
 };
@@ -212,6 +213,43 @@ __device__ __forceinline__ void pcg_gram_sum(const double *gp, int blocks, int w
       for (int u = 0; u < 4; ++u) acc += v[u];
     }
     out[e] = acc;
+  }
+  __syncthreads();
+}
+
+// Y_F^T 1_F and Y_F^T mu_F over this workgroup's kPcgThreads rows (one per
+// thread) into out[0, kPreK) and out[kPreK, 2 kPreK); tw: 2 kPcgWaves kPreK
+// doubles of LDS.
+__device__ __forceinline__ void pcg_face_ysum(const SolveArgs &a, double *tw, double *out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kPcgThreads + tid;
+  const bool on = i < a.n && a.fvec[i] > 0.0;
+  const double wmu = on ? a.mu[i] : 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < kPreK / 8; ++q) {
+      double t8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (on) {
+        const float *yc = a.pre_yt + (int64_t)(8 * q) * a.ldp + i;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) t8[cc] = h ? (double)yc[cc * a.ldp] * wmu : (double)yc[cc * a.ldp];
+      }
+      const double v = wave_reduce8(t8, lane);
+      if ((lane & 7) == 0)
+        tw[(h * kPcgWaves + wave) * kPreK + 8 * q + 4 * (lane >> 5) + 2 * ((lane >> 4) & 1) + ((lane >> 3) & 1)] = v;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * kPreK) {
+    const double *th = tw + (tid >> 5) * kPcgWaves * kPreK + (tid & 31);
+    double e = 0.0, o = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPcgWaves; w += 2) {
+      e += th[w * kPreK];
+      o += th[(w + 1) * kPreK];
+    }
+    out[tid] = e + o;
   }
   __syncthreads();
 }
@@ -381,26 +419,54 @@ __device__ __forceinline__ void pcg_face(const SolveArgs &a, const double (&fr)[
     sh.scal[0] = sigma;
     sh.scal[4] = ok ? 1.0 : 0.0;
   }
-  // a1 = M_F^{-1} 1_F, a2 = M_F^{-1} mu_F and their inner products
-  double w[E];
-  pcg_apply<E>(a, fr, fr, w, sh, sigma, ok);
+  // a1 = M_F^{-1} 1_F, a2 = M_F^{-1} mu_F and their inner products: Y_F^T 1_F
+  // and Y_F^T mu_F from the row blocks' partials (added in block order),
+  // K^{-1} of each in its own wavefront, then one pass over Y for both
+  if (ok) {
+    if (wave < 2) {
+      double tc = 0.0;
+      if (lane < kPreK) {
+        const double *tp = a.pre_gpart + kPreGpartT + wave * kPreK + lane;
+        for (int b0 = 0; b0 < gblocks; b0 += 4) {
+          double v[4];  // four loads in flight, then their sums in order
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = (b0 + u < gblocks) ? tp[(int64_t)(b0 + u) * 2 * kPreK] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) tc += v[u];
+        }
+      }
+      tc = chol_solve_lanes(sh.kc, sh.dinv, tc, lane);
+      if (lane < kPreK) (wave ? sh.s2 : sh.s)[lane] = tc;
+    }
+    __syncthreads();
+  }
+  const double inv = 1.0 / sigma;
   double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int64_t i = tid + kPcgThreads * j;
-    acc[0] += w[j];
-    acc[1] = fma(mu[j], w[j], acc[1]);
-    if (i < n) a.pre_a1[i] = w[j];
-  }
-  double fm[E];
+    double w1 = 0.0, w2 = 0.0;
+    if (i < n && fr[j] > 0.0) {
+      double p1 = 0.0, p2 = 0.0;
+      if (ok) {
+        const float *yc = a.pre_yt + i;
 #pragma unroll
-  for (int j = 0; j < E; ++j) fm[j] = fr[j] * mu[j];
-  pcg_apply<E>(a, fm, fr, w, sh, sigma, ok);
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int64_t i = tid + kPcgThreads * j;
-    acc[2] = fma(mu[j], w[j], acc[2]);
-    if (i < n) a.pre_a2[i] = w[j];
+        for (int c = 0; c < kPreK; ++c) {
+          const double y = (double)yc[c * a.ldp];
+          p1 = fma(y, sh.s[c], p1);
+          p2 = fma(y, sh.s2[c], p2);
+        }
+      }
+      w1 = (1.0 - p1) * inv;
+      w2 = (mu[j] - p2) * inv;
+    }
+    acc[0] += w1;
+    acc[1] = fma(mu[j], w1, acc[1]);
+    acc[2] = fma(mu[j], w2, acc[2]);
+    if (i < n) {
+      a.pre_a1[i] = w1;
+      a.pre_a2[i] = w2;
+    }
   }
   red.sum(acc);
   if (tid == 0) {

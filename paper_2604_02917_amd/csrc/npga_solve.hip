@@ -575,12 +575,13 @@ __device__ __forceinline__ void pcg_dir_t(const SolveArgs &a, double *tw) {
 }
 
 // A solve's first round start: both partial Gram products (Y_F^T Y_F and
-// Omega^T Y) of each block of kPcgThreads rows.
+// Omega^T Y) and Y_F^T 1_F, Y_F^T mu_F of each block of kPcgThreads rows.
 __global__ __launch_bounds__(kPcgThreads) void k_pcg_gram_init(SolveArgs a) {
   __shared__ PcgShared sh;
   if (a.st->done != kRunning) return;
   pcg_gram_rows<false>(a, sh, a.pre_gpart + (int64_t)blockIdx.x * 2 * kPreKK);
   pcg_gram_rows<true>(a, sh, a.pre_gpart + ((int64_t)blockIdx.x * 2 + 1) * kPreKK);
+  pcg_face_ysum(a, sh.part, a.pre_gpart + kPreGpartT + (int64_t)blockIdx.x * 2 * kPreK);
 }
 
 template <int E, bool INIT>
@@ -597,11 +598,13 @@ __global__ __launch_bounds__(kPcgThreads) void k_pcg_step(SolveArgs a, int force
     pcg_dir_t(a, sh.t);
     return;
   }
-  // a new face: every block forms its rows' partial Gram product; the last
+  // a new face: every block forms its rows' partial Gram product (and
+  // Y_F^T 1_F, Y_F^T mu_F); the last
   // block to arrive goes on alone with their sums (at a solve's first round
   // start k_pcg_gram_init has formed both partials and one block runs)
   if constexpr (!INIT) {
     pcg_gram_rows<false>(a, sh, a.pre_gpart + (int64_t)blockIdx.x * 2 * kPreKK);
+    pcg_face_ysum(a, sh.part, a.pre_gpart + kPreGpartT + (int64_t)blockIdx.x * 2 * kPreK);
     __threadfence();  // the partials are visible device-wide before the block arrives
     __syncthreads();
     if (threadIdx.x == 0) sh.last = (atomicAdd(&st->pcg_arrive, 1) == (int)gridDim.x - 1) ? 1 : 0;
