@@ -485,7 +485,9 @@ int npga_batched_tune(const npga_factor *f, int32_t m, int32_t reps, int32_t *be
  *     dl/dgamma = -2 a^T x*,        dl/dL = -2 (a u^T + x* v^T),
  * u = L^T x*, v = L^T a.  a is found by projected conjugate gradients with
  * the fused sweep for H p (float32 products) and one float64-anchored
- * correction round.  The formula assumes the face does not change under a
+ * correction round; for n >= 2048 with cols >= n the CG is preconditioned
+ * by the same rank-32 Nystrom sketch of H as npga_solve's refinement (its
+ * buffers are part of npga_backward_workspace_size).  The formula assumes the face does not change under a
  * small perturbation; res->degenerate = 1 flags a zero x_i with near-zero
  * reduced cost, |S| = 1, or mu constant on S.
  *   x_star   device n float32: a solution (e.g. from npga_solve)
