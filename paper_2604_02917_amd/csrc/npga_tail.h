@@ -804,10 +804,11 @@ __device__ void tail_cg(const SolveArgs &a, double *redbuf, double *mbuf, int64_
 // stagnation of the float32 products; after kPdasMaxOuter updates it
 // projects x onto F and reports the fallback (pdas_failed).
 // With the preconditioner set (a.pre_y), the search directions come from
-// k_pcg_step, launched after this tail (npga_pcg.h): the tail then leaves
-// p alone, takes its step length from pcg_rz = g^T z and tells k_pcg_step
-// in pcg_todo what follows (1: next direction, 2: the first direction on a
-// new face); the tests keep using the plain projected gradient.
+// the preconditioner's launches after this tail (k_pcg_step, k_pcg_dir_z,
+// k_pcg_dir_p; npga_pcg.h): the tail then leaves p alone, takes its step
+// length from pcg_rz = g^T z and tells them in pcg_todo what follows (1:
+// next direction, 2: the first direction on a new face); the tests keep
+// using the plain projected gradient.
 // ---------------------------------------------------------------------------
 template <int E, int NW = 4>
 __device__ void tail_pdas(const SolveArgs &a, double *redbuf) {
